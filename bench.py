@@ -1,0 +1,237 @@
+"""Benchmark: accepted MH proposals/s of the tensor-network Metropolis-Hastings
+chain on a 64x64 open ferromagnet at beta = 0.4407 with D = 32 environments,
+4096 independent chains (one proposal per chain per step).
+
+One step = one proposal per chain drawn by the batched fp32 MFMA sampler plus
+the acceptance kernel; the environment build (fp64 QR/SVD) is done once before
+the timed region and reported separately.  The plain fp64 GPU path (per-row
+launches) runs the same chains from the same seeds for the comparison, and
+the FP64 CPU oracle is timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "accepted MH proposals/s, 2D Ising L=64 D=32: batched FP32 vs plain FP64"
+UNIT = "accepted proposals/s"
+PEAK_FP32_MFMA = 157.3e12
+PEAK_HBM = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tau_int(E, burn=0.1, c=6.0):
+    """Integrated autocorrelation time of series E [steps, chains]: the
+    correlation is averaged over chains and start times after a 10% burn-in,
+    summed up to Sokal's window W >= 6 tau."""
+    import numpy as np
+    x = np.asarray(E, dtype=np.float64)
+    x = x[int(burn * x.shape[0]):]
+    n = x.shape[0]
+    if n < 4:
+        return float("nan")
+    x = x - x.mean()
+    var = (x * x).mean()
+    if var == 0:
+        return 1.0
+    tau = 1.0
+    for W in range(1, n):
+        tau += 2.0 * (x[:-W] * x[W:]).mean() / var
+        if W >= c * tau:
+            break
+    return float(tau)
+
+
+def run_gpu(prec, inst, steps, warmup, env_state=None):
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler
+
+    s = Sampler()
+    t0 = time.perf_counter()
+    if env_state is None:
+        logZ = s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, inst.D, prec)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        env_state = s.get_env()
+    else:
+        env, dims, ell, logZ = env_state
+        s.set_env(inst.Jh, inst.Jv, inst.h, inst.beta, inst.D, env, dims, ell, logZ, prec)
+        build_s = None
+    C = inst.chains
+    state = s.init_state(C)
+    prop = s.empty_batch(C)
+    stream = torch.cuda.current_stream()
+    for t in range(warmup):
+        s.sample(C, inst.seed, step=t, out=prop)
+        s.mh_accept(prop, state, inst.seed, t)
+    s.stats(reset=True)
+    E_series = torch.empty((steps, C), dtype=torch.float64, device=s.device)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(steps):
+        t = warmup + k
+        ev[k][0].record(stream)
+        s.sample(C, inst.seed, step=t, out=prop)
+        ev[k][1].record(stream)
+        s.mh_accept(prop, state, inst.seed, t)
+        E_series[k].copy_(state["energy"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    st = s.stats()
+    E = E_series.cpu().numpy()
+    s.close()
+    return dict(wall=wall, accepted=st["accepted"], proposed=st["proposed"],
+                sampler_ms=float(np.mean(kern_ms)), sampler_ms_all=kern_ms,
+                build_s=build_s, logZ=logZ, E=E, near=st["near_threshold"],
+                clamps=st["clamps"]), env_state
+
+
+def run_cpu_oracle(inst, budget_s=12.0):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import bmps, ising, mh
+    m = ising.Model(inst.Jh, inst.Jv, inst.h, inst.beta)
+    envs = bmps.build_envs(m, inst.D)
+    chains = 64
+    state = mh.init_state(m, envs, chains)
+    steps = 0
+    acc_total = 0
+    t0 = time.perf_counter()
+    while True:
+        acc, _, _ = mh.mh_step(m, envs, state, inst.seed, steps)
+        acc_total += int(acc.sum())
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return dict(value=acc_total / dt, unit=UNIT, cores=cores, kind="oracle",
+                sample=f"{steps} MH steps x {chains} chains of the 64x64 D=32 workload "
+                       f"(numpy fp64, vectorised over chains, {dt:.1f} s); env build excluded",
+                proposals_per_s=steps * chains / dt)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ["sampler_mfma.hip", "operands.hip", "common.hpp"]:
+        with open(os.path.join(ROOT, "paper_2104_13264_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "sampler_mfma_ferro64_traffic.json")
+    try:
+        with open(p) as fh:
+            d = json.load(fh)
+    except OSError:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler "
+              "shards by chains, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from workloads import ferro_64
+
+    inst = ferro_64()
+    L, D, C = inst.Lx, inst.D, inst.chains
+    log(f"[bench] ferro 64x64 D={D} chains={C} steps={args.steps} warmup={args.warmup}")
+
+    res32, env_state = run_gpu(1, inst, args.steps, args.warmup)
+    log(f"[bench] fp32 batched: {res32['wall']*1e3/args.steps:.3f} ms/step, "
+        f"sampler {res32['sampler_ms']:.3f} ms, acc {res32['accepted']}/{res32['proposed']}, "
+        f"env build {res32['build_s']:.2f} s")
+    res64 = None
+    if not args.no_plain:
+        res64, _ = run_gpu(0, inst, args.steps, args.warmup, env_state)
+        log(f"[bench] fp64 plain: {res64['wall']*1e3/args.steps:.3f} ms/step, "
+            f"acc {res64['accepted']}/{res64['proposed']}")
+
+    value = res32["accepted"] / res32["wall"]
+    ms_per_step = res32["wall"] * 1e3 / args.steps
+    # algorithmic work of one sampler launch: per proposal and column, the
+    # right sweep multiplies the two D x D matrices G_c(+-1) into its vectors
+    # and the left sweep one D x D matrix: 3 * 2 D^2 flops; L^2 columns.
+    flops_launch = 6.0 * D * D * L * L * C
+    achieved = flops_launch / (res32["sampler_ms"] * 1e-3)
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "ferro64_D32: 64x64 open-boundary ferromagnet J=+1, h=0, "
+                               "beta=0.4407, D=32 fp64 environments, 4096 chains from all-up, "
+                               "one proposal per chain per step",
+                   "chains": C, "L": L, "D": D, "beta": inst.beta, "seed": inst.seed},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": traffic,
+                     "kernel": "k_sampler_mfma<2,false>",
+                     "flops_per_launch": flops_launch,
+                     "kernel_ms": res32["sampler_ms"]},
+        "acceptance": res32["accepted"] / max(res32["proposed"], 1),
+        "proposals_per_s": res32["proposed"] / res32["wall"],
+        "tau_int_mean_energy": tau_int(res32["E"]),
+        "env_build_s": res32["build_s"],
+        "logZ": res32["logZ"],
+        "near_threshold_draws": res32["near"],
+    }
+    if res64 is not None:
+        v64 = res64["accepted"] / res64["wall"]
+        out["plain_fp64"] = {"value": v64, "unit": UNIT,
+                             "ms_per_step": res64["wall"] * 1e3 / args.steps,
+                             "acceptance": res64["accepted"] / max(res64["proposed"], 1),
+                             "sampler_ms": res64["sampler_ms"]}
+        out["speedup_vs_plain_fp64"] = value / v64 if v64 > 0 else None
+    if not args.no_cpu:
+        cb = run_cpu_oracle(inst)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        log(f"[bench] cpu oracle: {cb['value']:.2f} accepted/s on {cb['cores']} cores")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

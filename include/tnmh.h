@@ -1,0 +1,180 @@
+/*
+ * tnmh.h -- C ABI of the MI355X (gfx950) tensor-network Metropolis-Hastings
+ * library: boundary-MPS environments of the 2D Ising Boltzmann network, the
+ * sequential sampler that draws whole configurations with their proposal
+ * log-probability, the MH acceptance step and the derivative of ln Z~.
+ *
+ * Paper: "Collective Monte Carlo updates through tensor network
+ * renormalization" (arXiv:2104.13264).
+ *
+ * Conventions shared by every call
+ *   Lattice Ly x Lx, open boundaries; row r = 0..Ly-1, column c = 0..Lx-1,
+ *   site i = r*Lx + c.  Spins are int8 +1/-1.
+ *   Jh [Ly][Lx-1]  coupling of (r,c)-(r,c+1)          float64, row-major
+ *   Jv [Ly-1][Lx]  coupling of (r,c)-(r+1,c)          float64, row-major
+ *   h  [Ly][Lx]    site field, or NULL meaning 0      float64, row-major
+ *   Energy H(s) = -sum h s - sum J s s'   (Sec. 2, Eq. ising).
+ *   Pointers marked (dev) are device memory of the current HIP device owned
+ *   by the caller; (host) are host memory owned by the caller.  Every call is
+ *   asynchronous on the context's stream unless it returns a host value.
+ *
+ * Random numbers (the paper leaves them open): Philox4x32-10 with key = seed,
+ *   spin draw of site i of proposal id at step t:
+ *       counter (i/4, id, t, inst<<2 | 0), word i%4
+ *   acceptance draw of chain j at step t:
+ *       counter (0, j, t, inst<<2 | 1), word 0
+ *   mapped to u = (x + 0.5) * 2^-32 in float64; spin +1 iff u < p+.
+ *
+ * Errors: every int-returning call returns TN_OK (0) or a negative code and
+ *   leaves a message in tn_last_error(ctx).  No C++ exception crosses the ABI.
+ */
+#ifndef TNMH_H
+#define TNMH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_ctx tn_ctx;
+
+enum tn_status {
+    TN_OK = 0,
+    TN_EINVAL = -1,   /* bad argument (size, NULL pointer, non-finite beta) */
+    TN_ENOMEM = -2,   /* device allocation failed */
+    TN_EHIP = -3,     /* a HIP runtime call failed */
+    TN_ENONPOS = -4,  /* Z~ <= 0 or not finite (App. A: positivity) */
+    TN_ENOCONV = -5,  /* Jacobi SVD did not converge */
+    TN_ESTATE = -6    /* call order: sampling before an environment exists */
+};
+
+/* Arithmetic of the sampler.  The environment build (QR/SVD truncation and
+ * log-normalisers) is float64 in every case.
+ *   TN_FP64  plain path: float64 vector arithmetic, one launch per row
+ *   TN_FP32  batched path: float32 MFMA contractions (fp32 accumulate),
+ *            persistent kernel over all rows, p and ln q in float64
+ *   TN_BF16  batched path with bf16 operands and fp32 accumulation          */
+enum tn_prec { TN_FP64 = 0, TN_FP32 = 1, TN_BF16 = 2 };
+
+/* Create a context bound to `hip_stream` (a hipStream_t, or NULL for the
+ * null stream) on the current device.  *out receives the handle. */
+int tn_create(tn_ctx **out, void *hip_stream);
+
+/* Free the context, its environment stack and its scratch.  NULL is a no-op. */
+int tn_destroy(tn_ctx *ctx);
+
+/* Message of the last failed call on ctx (never NULL; "" after success). */
+const char *tn_last_error(const tn_ctx *ctx);
+
+/* Boundary-MPS environments (App. A, Eq. braket-top-tm-bot and the
+ * MPO-MPS renormalisation figure), contracted bottom-up: env k (k=1..Ly-1)
+ * approximates rows k..Ly-1 with their up legs open.  Each row MPO is applied
+ * to env k+1 and the product is compressed to bond D by a left-to-right
+ * Householder QR sweep and a right-to-left one-sided Jacobi SVD sweep keeping
+ * the min(D, rows, cols) largest singular values ("successive SVD").
+ *   Jh, Jv, h  (dev, fp64) couplings and field, layouts above (h may be NULL)
+ *   beta       inverse temperature, finite
+ *   D          bond dimension, 1 <= D <= 64
+ *   prec       sampler arithmetic (enum tn_prec)
+ *   logZ_out   (host, may be NULL) receives ln Z~ = sum_k ell_k + ln<top|env_1>
+ * Replaces any previous environment.  Synchronises the stream when logZ_out
+ * is not NULL.  TN_ENONPOS if <top|env_1> <= 0 or ln Z~ is not finite. */
+int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
+                 const double *h, double beta, int D, int prec, double *logZ_out);
+
+/* Install an environment computed elsewhere (or saved by tn_get_env) instead
+ * of building it.  Couplings as in tn_build_env (dev).  Host arrays:
+ *   env   [(Ly-1)][Lx][D][2][D] fp64: env k=1..Ly-1, tensor E[a][u][b] of column
+ *         c zero-padded to D x 2 x D (a: left bond, u: leg of the vertical
+ *         bond above the env, b: right bond)
+ *   dims  [(Ly-1)][Lx+1] int: bond dims of env k; dims[.][0] = dims[.][Lx] = 1
+ *   ell   [Ly-1] fp64: log-normaliser of env k (informational)
+ *   logZ  ln Z~ stored with the environment */
+int tn_set_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
+               const double *h, double beta, int D, int prec, const double *env,
+               const int *dims, const double *ell, double logZ);
+
+/* Copy the current environment to host arrays laid out as in tn_set_env
+ * (any pointer may be NULL to skip it).  Synchronises the stream. */
+int tn_get_env(tn_ctx *ctx, double *env, int *dims, double *ell, double *logZ);
+
+/* Switch the sampler arithmetic of an existing environment (re-derives the
+ * sampler operands from the fp64 environment; no rebuild). */
+int tn_set_precision(tn_ctx *ctx, int prec);
+
+/* Instance tag written into the Philox counter (inst << 2 | stream); 0..2^29-1. */
+int tn_set_instance(tn_ctx *ctx, int inst);
+
+/* Draw `batch` independent proposals by the sequential Bayes chain rule
+ * (Sec. 2, Eqs. bayes, pi-approx; App. A Eq. proba-ratio-apx), row-major
+ * site order, each conditional normalised over s in {+1,-1} from the same
+ * stored environment.  Proposal j uses id = first_id + j.
+ *   spins  (dev, int8 [batch][Ly][Lx])  drawn configurations
+ *   logq   (dev, fp64 [batch])          ln q(s) of the arithmetic that drew s
+ *   energy (dev, fp64 [batch])          H(s)
+ * Negative conditional weights are clamped to 0 (counted in tn_stats); if
+ * both are <= 0 the draw uses p+ = 1/2.  TN_ESTATE before an environment. */
+int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
+              int8_t *spins, double *logq, double *energy);
+
+/* ln q(s) and H(s) of given configurations by exactly the arithmetic of
+ * tn_sample (the forced-spin mode of the same kernels).
+ *   spins (dev, int8 [batch][Ly][Lx]), logq, energy (dev, fp64 [batch]) */
+int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq,
+                 double *energy);
+
+/* One step of Algorithm 1 for `chains` independent chains: chain j draws its
+ * proposal with id = j at step `step`, accepts it with probability
+ * min{1, q(w)/q(w') * exp(-beta (H(w') - H(w)))} (Eqs. mh-acc, tns-prior),
+ * and on acceptance copies it into its state (in place).
+ *   state_spins (dev, int8 [chains][Ly][Lx]); state_logq, state_energy (dev,
+ *   fp64 [chains]) must hold ln q and H of the state (tn_eval_logq);
+ *   accepted (dev, uint8 [chains]) receives 1/0.
+ * Uses context-owned proposal buffers; launches only, so it can be captured
+ * into a HIP graph after one warm-up call with the same chain count. */
+int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
+               int8_t *state_spins, double *state_logq, double *state_energy,
+               uint8_t *accepted);
+
+/* The acceptance half of tn_mh_step for proposals the caller already drew
+ * (tn_sample with first_id = 0 and the same step): chain j accepts proposal j
+ * with the probability of Eqs. (mh-acc, tns-prior) and copies it into its
+ * state on acceptance.
+ *   prop_spins (dev, int8 [chains][Ly][Lx]), prop_logq, prop_energy (dev, fp64)
+ *   state_* and accepted as in tn_mh_step. */
+int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
+                 const int8_t *prop_spins, const double *prop_logq,
+                 const double *prop_energy, int8_t *state_spins, double *state_logq,
+                 double *state_energy, uint8_t *accepted);
+
+/* Derivative of ln Z~ with the truncation isometries frozen: every
+ * compression step of the environment build is replaced by the orthogonal
+ * projector onto the span kept at its leftmost truncated bond (the identity
+ * where nothing was truncated), which makes Z~ multilinear in the site
+ * tensors; the adjoint sweeps the rows top-down with exact per-row
+ * environments.
+ *   dJh (dev, fp64 [Ly][Lx-1]), dJv (dev, fp64 [Ly-1][Lx]): d ln Z~ / dJ
+ *   dbeta (host, may be NULL): d ln Z~ / d beta
+ * Synchronises the stream. */
+int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
+
+typedef struct {
+    uint64_t clamps;        /* conditional weights clamped to 0 */
+    uint64_t both_nonpos;   /* sites drawn with p+ = 1/2 */
+    uint64_t near_threshold;/* draws with |u - p+| < 1e-6 */
+    uint64_t accepted;      /* accepted MH moves since the last reset */
+    uint64_t proposed;      /* MH proposals since the last reset */
+    uint64_t degenerate_cuts;/* truncations with s_chi-1 - s_chi < 1e-12 s_0 */
+    double   logZ;          /* ln Z~ of the current environment */
+    double   env_build_ms;  /* wall time of the last tn_build_env */
+} tn_stats_t;
+
+/* Read (and, if reset != 0, clear) the counters.  Synchronises the stream. */
+int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNMH_H */

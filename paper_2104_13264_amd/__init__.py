@@ -1,0 +1,10 @@
+"""MI355X (gfx950) tensor-network Metropolis-Hastings sampler for 2D Ising
+models (arXiv:2104.13264): boundary-MPS environments, sequential proposals
+with their log-probability, MH acceptance and d ln Z~ / dJ, as HIP kernels
+behind the C ABI of include/tnmh.h.
+"""
+from .tnmh import (BF16, FP32, FP64, PREC, Sampler, TNError, exported_symbols, lib,
+                   LIB_PATH)
+
+__all__ = ["Sampler", "TNError", "FP64", "FP32", "BF16", "PREC", "lib", "LIB_PATH",
+           "exported_symbols"]

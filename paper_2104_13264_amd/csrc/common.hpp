@@ -1,0 +1,197 @@
+// Shared definitions of the gfx950 TNMH library: the context, error handling,
+// device helpers (Philox4x32-10, bond-leg factors, wavefront reductions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/tnmh.h"
+
+#define TN_MAX_D 64
+
+// Device counters (uint64) kept per context.
+enum {
+    CNT_CLAMPS = 0,
+    CNT_BOTH = 1,
+    CNT_NEAR = 2,
+    CNT_ACCEPTED = 3,
+    CNT_PROPOSED = 4,
+    CNT_DEGEN = 5,
+    CNT_NOCONV = 6,
+    CNT_N = 8
+};
+
+struct tn_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    // instance
+    int Lx = 0, Ly = 0, D = 0, Dp = 0, prec = TN_FP64, inst = 0;
+    double beta = 0.0;
+    bool has_env = false;
+    bool has_ops64 = false, has_ops32 = false, has_ops16 = false;
+    double logZ = 0.0;
+    double env_build_ms = 0.0;
+
+    // owned device copies of the couplings (fp64)
+    double *Jh = nullptr, *Jv = nullptr, *h = nullptr;
+
+    // environment stack: env[k][c][D][2][D], k = 0..Ly (k = 0 unused, k = Ly
+    // trivial), bond dims dims[k][0..Lx], log-normalisers ell[k]
+    double *env = nullptr;
+    int *dims = nullptr;
+    double *ell = nullptr;
+    size_t env_cap = 0;       // elements allocated for env
+
+    // sampler operands, one per row r = 0..Ly-1 and column:
+    //   G64r[r][c][s][a][b]  = G_c(s)[a][b]  (row-major, fp64)
+    //   G64c[r][c][s][b][a]  = G_c(s)[a][b]  (column-major, fp64)
+    //   G32R / G32L          MFMA A-operand tiles of G and G^T (fp32)
+    //   G16R / G16L          the same in bf16
+    double *G64r = nullptr, *G64c = nullptr;
+    float *G32R = nullptr, *G32L = nullptr;
+    uint16_t *G16R = nullptr, *G16L = nullptr;
+    size_t ops_cap64 = 0, ops_cap32 = 0, ops_cap16 = 0;
+
+    // Boltzmann factors per site: exp(+-beta h), exp(+-beta Jv above),
+    // exp(+-beta Jh left), [Ly][Lx][6] fp64
+    double *fac = nullptr;
+    size_t fac_cap = 0;
+
+    // environment-build scratch
+    double *xbox = nullptr;   // [Lx][2D][2][2D]
+    double *wbuf = nullptr;   // global work buffers when LDS is too small
+    double *scal = nullptr;   // small device scalars (top overlap result ...)
+    int *xdims = nullptr;     // [2][Lx+1]
+    size_t xbox_cap = 0, wbuf_cap = 0;
+
+    // sampler scratch (per-proposal right environments)
+    void *gscr = nullptr;
+    size_t gscr_cap = 0;
+
+    // proposal buffers of tn_mh_step
+    int8_t *pspins = nullptr;
+    double *plogq = nullptr, *pE = nullptr;
+    size_t pcap = 0;
+
+    unsigned long long *counters = nullptr;   // CNT_N
+};
+
+int tn_fail(tn_ctx *ctx, int code, const std::string &msg);
+
+#define TN_HIP(ctx, call)                                                          \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return tn_fail((ctx), TN_EHIP, std::string(#call) + ": " +             \
+                                               hipGetErrorString(e_));             \
+    } while (0)
+
+// grow a device buffer to at least `bytes`
+int tn_ensure(tn_ctx *ctx, void **ptr, size_t *cap, size_t bytes);
+
+// environment build (env_build.hip)
+int tn_env_build_device(tn_ctx *ctx, double *logZ_out);
+int tn_make_operands(tn_ctx *ctx, int prec);
+int tn_top_overlap(tn_ctx *ctx, double *logtop, double *sign);
+
+// samplers
+int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step,
+                uint64_t first_id, int8_t *spins, bool eval, double *logq,
+                double *energy);
+int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step,
+                uint64_t first_id, int8_t *spins, bool eval, double *logq,
+                double *energy);
+
+// MH accept kernel launcher (mh.hip)
+int tn_launch_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
+                     const int8_t *prop_spins, const double *prop_logq,
+                     const double *prop_energy, int8_t *state_spins, double *state_logq,
+                     double *state_energy, uint8_t *accepted);
+
+// adjoint (grad.hip)
+int tn_grad_device(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4x32 S-box with two 32x32->64 multiplies, Weyl-incremented key.
+__device__ __forceinline__ uint4 tn_philox(uint4 ctr, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * ctr.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, ctr.x);
+        const uint32_t lo1 = 0xCD9E8D57u * ctr.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, ctr.z);
+        ctr = make_uint4(hi1 ^ ctr.y ^ k0, lo1, hi0 ^ ctr.w ^ k1, lo0);
+    }
+    return ctr;
+}
+
+__device__ __forceinline__ double tn_u01(uint32_t x) {
+    return ((double)x + 0.5) * 2.3283064365386963e-10;   // 2^-32
+}
+
+__device__ __forceinline__ uint32_t tn_word(uint4 v, int w) {
+    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+}
+
+// Bond-leg factors of W(s,s') = exp(K s s') = P Q (App. A):
+//   P(s,0) = sqrt(cosh K), P(s,1) = s sqrt|sinh K|
+//   Q(0,s) = sqrt(cosh K), Q(1,s) = sign(K) s sqrt|sinh K|
+// spin index 0 is s = +1, index 1 is s = -1.
+__device__ __forceinline__ double tn_pleg(double K, int sidx, int mu) {
+    const double s = sidx ? -1.0 : 1.0;
+    return mu == 0 ? sqrt(cosh(K)) : s * sqrt(fabs(sinh(K)));
+}
+__device__ __forceinline__ double tn_qleg(double K, int mu, int sidx) {
+    const double s = sidx ? -1.0 : 1.0;
+    const double sg = K >= 0.0 ? 1.0 : -1.0;
+    return mu == 0 ? sqrt(cosh(K)) : sg * s * sqrt(fabs(sinh(K)));
+}
+
+template <typename T>
+__device__ __forceinline__ T tn_wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T tn_wave_max(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// block-wide sum over all threads; every thread receives the total.
+// `red` must hold blockDim.x/64 doubles of LDS.
+__device__ __forceinline__ double tn_block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    v = tn_wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+__device__ __forceinline__ double tn_block_max(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    v = tn_wave_max(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t = fmax(t, red[i]);
+    return t;
+}

@@ -1,0 +1,208 @@
+// Plain fp64 sampler: the sequential Bayes-chain-rule draw of Sec. 2
+// (Eqs. bayes, pi-approx) with the conditionals of App. A Eq. (proba-ratio-apx)
+// evaluated against the stored environment, in fp64 vector arithmetic with one
+// kernel launch per lattice row.
+//
+// Work split: a "team" of T lanes (T = smallest power of two >= D) owns one
+// proposal; lane j holds component j of the proposal's bond vectors, and the
+// matrix-vector products broadcast the input vector across the team with
+// lane shuffles.  No LDS is used.
+//
+// Row r, given the fixed row r-1 above and env r+1 below:
+//   right sweep (c = Lx-1 .. 0):  y_s = G_c(s) r_s^(c)   (stored per column)
+//       r_s'^(c-1) = sum_s W_{c-1,c}(s',s) v_c(s) y_s,   v_c(s) = exp(beta h s)
+//       exp(beta Jv s_up s), W = exp(beta Jh s' s); rescaled by a power of two
+//   left sweep (c = 0 .. Lx-1):   w(s) = v_c(s) hf(s) <Lam, y_s>,
+//       hf(s) = exp(beta Jh s_{c-1} s); clamp; p+ = w+/(w+ + w-); draw;
+//       ln q += ln p_s;  Lam <- Lam G_c(s), rescaled by a power of two
+#include "common.hpp"
+
+namespace {
+
+template <int T>
+__device__ __forceinline__ double team_sum(double v) {
+#pragma unroll
+    for (int m = T / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, T);
+    return v;
+}
+template <int T>
+__device__ __forceinline__ double team_max(double v) {
+#pragma unroll
+    for (int m = T / 2; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, T));
+    return v;
+}
+
+__device__ __forceinline__ int pow2_exponent(double m) {
+    int e = 0;
+    if (m > 0.0 && m <= 1.79e308) frexp(m, &e);
+    return e;
+}
+
+template <int T>
+__global__ void __launch_bounds__(256)
+k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
+           const double *__restrict__ Jv, const double *__restrict__ h,
+           const double *__restrict__ fac, const int *__restrict__ dims,
+           const double *__restrict__ G64r, const double *__restrict__ G64c,
+           int8_t *__restrict__ S, int eval, double *__restrict__ logq,
+           double *__restrict__ energy, double *__restrict__ gscr, uint32_t k0, uint32_t k1,
+           uint64_t first_id, uint32_t step, uint32_t inst,
+           unsigned long long *__restrict__ counters) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = tid / T, j = tid % T;
+    if (b >= B) return;   // whole teams leave together (T divides 64)
+    const int *dm = dims + (size_t)(r + 1) * (Lx + 1);
+    const size_t DD = (size_t)D * D;
+    const double *Gr = G64r + (size_t)r * Lx * 2 * DD;
+    const double *Gc = G64c + (size_t)r * Lx * 2 * DD;
+    const double *fr = fac + (size_t)r * Lx * 6;
+    double *gs = gscr + (size_t)b * Lx * 2 * D;
+    const int8_t *up = r > 0 ? S + ((size_t)b * Ly + r - 1) * Lx : nullptr;
+    int8_t *row = S + ((size_t)b * Ly + r) * Lx;
+
+    // ---- right sweep
+    double r0 = (j == 0) ? 1.0 : 0.0, r1 = r0;
+    for (int c = Lx - 1; c >= 0; --c) {
+        const int Dl = dm[c], Dr = dm[c + 1];
+        const double *G0 = Gc + (size_t)c * 2 * DD, *G1 = G0 + DD;
+        double y0 = 0.0, y1 = 0.0;
+        for (int k = 0; k < Dr; ++k) {
+            const double x0 = __shfl(r0, k, T), x1 = __shfl(r1, k, T);
+            if (j < Dl) {
+                y0 += G0[k * D + j] * x0;
+                y1 += G1[k * D + j] * x1;
+            }
+        }
+        if (j < D) {
+            gs[(c * 2 + 0) * D + j] = y0;
+            gs[(c * 2 + 1) * D + j] = y1;
+        }
+        if (c > 0) {
+            const double *f = fr + c * 6;
+            const int su = up ? up[c] : 1;
+            const double v0 = f[0] * (su > 0 ? f[2] : f[3]);   // s = +1
+            const double v1 = f[1] * (su > 0 ? f[3] : f[2]);   // s = -1
+            const double n0 = f[4] * v0 * y0 + f[5] * v1 * y1;
+            const double n1 = f[5] * v0 * y0 + f[4] * v1 * y1;
+            const int e = pow2_exponent(team_max<T>(fmax(fabs(n0), fabs(n1))));
+            r0 = ldexp(n0, -e);
+            r1 = ldexp(n1, -e);
+        }
+    }
+
+    // ---- left sweep
+    double lam = (j == 0) ? 1.0 : 0.0;
+    int sprev = 1;
+    double lq = 0.0, E = 0.0;
+    uint4 blk = make_uint4(0, 0, 0, 0);
+    int blk_id = -1;
+    for (int c = 0; c < Lx; ++c) {
+        const int Dl = dm[c], Dr = dm[c + 1];
+        const double *f = fr + c * 6;
+        const int su = up ? up[c] : 1;
+        double v0 = f[0] * (su > 0 ? f[2] : f[3]);
+        double v1 = f[1] * (su > 0 ? f[3] : f[2]);
+        if (c > 0) {
+            v0 *= sprev > 0 ? f[4] : f[5];
+            v1 *= sprev > 0 ? f[5] : f[4];
+        }
+        const double g0 = j < D ? gs[(c * 2 + 0) * D + j] : 0.0;
+        const double g1 = j < D ? gs[(c * 2 + 1) * D + j] : 0.0;
+        double w0 = v0 * team_sum<T>(lam * g0);
+        double w1 = v1 * team_sum<T>(lam * g1);
+        if (w0 < 0.0) {
+            w0 = 0.0;
+            if (j == 0) atomicAdd(&counters[CNT_CLAMPS], 1ull);
+        }
+        if (w1 < 0.0) {
+            w1 = 0.0;
+            if (j == 0) atomicAdd(&counters[CNT_CLAMPS], 1ull);
+        }
+        const double tot = w0 + w1;
+        const bool bad = !(tot > 0.0 && tot <= 1.79e308);
+        if (bad && j == 0) atomicAdd(&counters[CNT_BOTH], 1ull);
+        const double p = bad ? 0.5 : w0 / tot;
+        int s;
+        if (eval) {
+            s = row[c];
+        } else {
+            const int i = r * Lx + c;
+            if ((i >> 2) != blk_id) {
+                blk_id = i >> 2;
+                blk = tn_philox(make_uint4((uint32_t)blk_id, (uint32_t)(first_id + b), step,
+                                           (inst << 2) | 0u),
+                                k0, k1);
+            }
+            const double u = tn_u01(tn_word(blk, i & 3));
+            s = (u < p) ? 1 : -1;
+            if (j == 0) {
+                row[c] = (int8_t)s;
+                if (fabs(u - p) < 1e-6) atomicAdd(&counters[CNT_NEAR], 1ull);
+            }
+        }
+        lq += log(s > 0 ? p : 1.0 - p);
+        // energy, Eq. (ising): field, left bond, bond to the row above
+        if (h) E -= h[r * Lx + c] * s;
+        if (c > 0) E -= Jh[r * (Lx - 1) + c - 1] * (double)(sprev * s);
+        if (up) E -= Jv[(r - 1) * Lx + c] * (double)(up[c] * s);
+        // Lam <- Lam G_c(s)
+        const double *Gs = Gr + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
+        double nl = 0.0;
+        for (int a = 0; a < Dl; ++a) {
+            const double x = __shfl(lam, a, T);
+            if (j < Dr) nl += x * Gs[a * D + j];
+        }
+        const int e = pow2_exponent(team_max<T>(fabs(nl)));
+        lam = ldexp(nl, -e);
+        sprev = s;
+    }
+    if (j == 0) {
+        if (r == 0) {
+            logq[b] = lq;
+            energy[b] = E;
+        } else {
+            logq[b] += lq;
+            energy[b] += E;
+        }
+    }
+}
+
+template <int T>
+int launch_rows(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
+                double *gscr, uint64_t seed, uint64_t step, uint64_t first_id) {
+    const int threads = 256;
+    const size_t total = (size_t)B * T;
+    const int blocks = (int)((total + threads - 1) / threads);
+    for (int r = 0; r < ctx->Ly; ++r) {
+        hipLaunchKernelGGL(k_row_fp64<T>, dim3(blocks), dim3(threads), 0, ctx->stream, r, B,
+                           ctx->Lx, ctx->Ly, ctx->D, ctx->Jh, ctx->Jv, ctx->h, ctx->fac,
+                           ctx->dims, ctx->G64r, ctx->G64c, S, eval ? 1 : 0, logq, energy,
+                           gscr, (uint32_t)seed, (uint32_t)(seed >> 32), first_id,
+                           (uint32_t)step, (uint32_t)ctx->inst, ctx->counters);
+        TN_HIP(ctx, hipGetLastError());
+    }
+    return TN_OK;
+}
+
+}  // namespace
+
+int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
+                int8_t *spins, bool eval, double *logq, double *energy) {
+    if (batch == 0) return TN_OK;
+    const size_t need = (size_t)batch * ctx->Lx * 2 * ctx->D * sizeof(double);
+    int rc;
+    if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, need))) return rc;
+    double *g = (double *)ctx->gscr;
+    int T = 1;
+    while (T < ctx->D) T <<= 1;
+    switch (T) {
+    case 1: return launch_rows<1>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 2: return launch_rows<2>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 4: return launch_rows<4>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 8: return launch_rows<8>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 16: return launch_rows<16>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 32: return launch_rows<32>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 64: return launch_rows<64>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
+    }
+}

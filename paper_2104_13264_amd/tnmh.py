@@ -1,0 +1,220 @@
+"""Thin Python binding of libtnmh.so (include/tnmh.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  Torch provides device memory and the stream; tensors are
+passed by data pointer.  The binding refuses to run without the in-tree
+shared object (there is no fallback path).
+"""
+import ctypes
+import os
+
+import torch
+
+FP64, FP32, BF16 = 0, 1, 2
+PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtnmh.so")
+_lib = None
+
+_STATUS = {0: "TN_OK", -1: "TN_EINVAL", -2: "TN_ENOMEM", -3: "TN_EHIP",
+           -4: "TN_ENONPOS", -5: "TN_ENOCONV", -6: "TN_ESTATE"}
+
+
+class TNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("clamps", ctypes.c_uint64), ("both_nonpos", ctypes.c_uint64),
+                ("near_threshold", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
+                ("proposed", ctypes.c_uint64), ("degenerate_cuts", ctypes.c_uint64),
+                ("logZ", ctypes.c_double), ("env_build_ms", ctypes.c_double)]
+
+
+def lib():
+    """Load libtnmh.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2104_13264_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+    sig = {
+        "tn_create": (i, [ctypes.POINTER(vp), vp]),
+        "tn_destroy": (i, [vp]),
+        "tn_last_error": (ctypes.c_char_p, [vp]),
+        "tn_build_env": (i, [vp, i, i, vp, vp, vp, d, i, i, ctypes.POINTER(d)]),
+        "tn_set_env": (i, [vp, i, i, vp, vp, vp, d, i, i, vp, vp, vp, d]),
+        "tn_get_env": (i, [vp, vp, vp, vp, ctypes.POINTER(d)]),
+        "tn_set_precision": (i, [vp, i]),
+        "tn_set_instance": (i, [vp, i]),
+        "tn_sample": (i, [vp, i, u64, u64, u64, vp, vp, vp]),
+        "tn_eval_logq": (i, [vp, i, vp, vp, vp]),
+        "tn_mh_step": (i, [vp, i, u64, u64, vp, vp, vp, vp]),
+        "tn_mh_accept": (i, [vp, i, u64, u64, vp, vp, vp, vp, vp, vp, vp]),
+        "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
+        "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["tn_create", "tn_destroy", "tn_last_error", "tn_build_env", "tn_set_env",
+            "tn_get_env", "tn_set_precision", "tn_set_instance", "tn_sample",
+            "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_grad", "tn_stats"]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev64(x, device):
+    if x is None:
+        return None
+    t = torch.as_tensor(x, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+class Sampler:
+    """One library context: an environment stack and its samplers."""
+
+    def __init__(self, device=None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the TNMH library needs a HIP device")
+        self.device = torch.device(device or f"cuda:{torch.cuda.current_device()}")
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self._check(lib().tn_create(ctypes.byref(self._ctx),
+                                        ctypes.c_void_p(self.stream.cuda_stream)))
+        self.Lx = self.Ly = self.D = None
+        self.beta = None
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            msg = lib().tn_last_error(self._ctx).decode() if self._ctx else ""
+            raise TNError(rc, msg)
+
+    def close(self):
+        if self._ctx:
+            lib().tn_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- environments -------------------------------------------------------
+    def build_env(self, Jh, Jv, h, beta, D, prec=FP64):
+        """Build the boundary-MPS environments; returns ln Z~."""
+        Jh, Jv, h = (_dev64(x, self.device) for x in (Jh, Jv, h))
+        Ly, Lx = Jv.shape[0] + 1, Jh.shape[1] + 1
+        self._keep = (Jh, Jv, h)
+        logZ = ctypes.c_double()
+        self._check(lib().tn_build_env(self._ctx, Lx, Ly, _ptr(Jh), _ptr(Jv), _ptr(h),
+                                       float(beta), int(D), int(prec), ctypes.byref(logZ)))
+        self.Lx, self.Ly, self.D, self.beta = Lx, Ly, int(D), float(beta)
+        return logZ.value
+
+    def set_env(self, Jh, Jv, h, beta, D, env, dims, ell, logZ, prec=FP64):
+        """Install environments given as host arrays (layout of tn_set_env)."""
+        import numpy as np
+        Jh, Jv, h = (_dev64(x, self.device) for x in (Jh, Jv, h))
+        Ly, Lx = Jv.shape[0] + 1, Jh.shape[1] + 1
+        env = np.ascontiguousarray(env, dtype=np.float64)
+        dims = np.ascontiguousarray(dims, dtype=np.int32)
+        ell = np.ascontiguousarray(ell, dtype=np.float64)
+        self._check(lib().tn_set_env(self._ctx, Lx, Ly, _ptr(Jh), _ptr(Jv), _ptr(h),
+                                     float(beta), int(D), int(prec),
+                                     env.ctypes.data_as(ctypes.c_void_p),
+                                     dims.ctypes.data_as(ctypes.c_void_p),
+                                     ell.ctypes.data_as(ctypes.c_void_p), float(logZ)))
+        self.Lx, self.Ly, self.D, self.beta = Lx, Ly, int(D), float(beta)
+
+    def get_env(self):
+        """Return (env [(Ly-1)][Lx][D][2][D], dims [(Ly-1)][Lx+1], ell, logZ)."""
+        import numpy as np
+        Lx, Ly, D = self.Lx, self.Ly, self.D
+        env = np.zeros((max(Ly - 1, 0), Lx, D, 2, D))
+        dims = np.zeros((max(Ly - 1, 0), Lx + 1), dtype=np.int32)
+        ell = np.zeros(max(Ly - 1, 0))
+        lz = ctypes.c_double()
+        self._check(lib().tn_get_env(self._ctx, env.ctypes.data_as(ctypes.c_void_p),
+                                     dims.ctypes.data_as(ctypes.c_void_p),
+                                     ell.ctypes.data_as(ctypes.c_void_p), ctypes.byref(lz)))
+        return env, dims, ell, lz.value
+
+    def set_precision(self, prec):
+        self._check(lib().tn_set_precision(self._ctx, int(prec)))
+
+    def set_instance(self, inst):
+        self._check(lib().tn_set_instance(self._ctx, int(inst)))
+
+    # -- sampling -----------------------------------------------------------
+    def empty_batch(self, batch):
+        return (torch.empty((batch, self.Ly, self.Lx), dtype=torch.int8, device=self.device),
+                torch.empty(batch, dtype=torch.float64, device=self.device),
+                torch.empty(batch, dtype=torch.float64, device=self.device))
+
+    def sample(self, batch, seed, step=0, first_id=0, out=None):
+        s, lq, E = out if out is not None else self.empty_batch(batch)
+        self._check(lib().tn_sample(self._ctx, int(batch), int(seed), int(step), int(first_id),
+                                    _ptr(s), _ptr(lq), _ptr(E)))
+        return s, lq, E
+
+    def eval_logq(self, spins):
+        spins = torch.as_tensor(spins, dtype=torch.int8, device=self.device).contiguous()
+        B = spins.shape[0]
+        lq = torch.empty(B, dtype=torch.float64, device=self.device)
+        E = torch.empty(B, dtype=torch.float64, device=self.device)
+        self._check(lib().tn_eval_logq(self._ctx, B, _ptr(spins), _ptr(lq), _ptr(E)))
+        return lq, E
+
+    def init_state(self, chains, spins=None):
+        if spins is None:
+            spins = torch.ones((chains, self.Ly, self.Lx), dtype=torch.int8, device=self.device)
+        spins = torch.as_tensor(spins, dtype=torch.int8, device=self.device).contiguous().clone()
+        lq, E = self.eval_logq(spins)
+        acc = torch.zeros(spins.shape[0], dtype=torch.uint8, device=self.device)
+        return dict(spins=spins, logq=lq, energy=E, accepted=acc)
+
+    def mh_step(self, state, seed, step):
+        C = state["spins"].shape[0]
+        self._check(lib().tn_mh_step(self._ctx, C, int(seed), int(step), _ptr(state["spins"]),
+                                     _ptr(state["logq"]), _ptr(state["energy"]),
+                                     _ptr(state["accepted"])))
+        return state["accepted"]
+
+    def mh_accept(self, proposal, state, seed, step):
+        """Acceptance half of an MH step for proposals drawn with sample()."""
+        sp, lq, E = proposal
+        C = state["spins"].shape[0]
+        self._check(lib().tn_mh_accept(self._ctx, C, int(seed), int(step), _ptr(sp), _ptr(lq),
+                                       _ptr(E), _ptr(state["spins"]), _ptr(state["logq"]),
+                                       _ptr(state["energy"]), _ptr(state["accepted"])))
+        return state["accepted"]
+
+    def grad(self):
+        dJh = torch.zeros((self.Ly, self.Lx - 1), dtype=torch.float64, device=self.device)
+        dJv = torch.zeros((self.Ly - 1, self.Lx), dtype=torch.float64, device=self.device)
+        db = ctypes.c_double()
+        self._check(lib().tn_grad(self._ctx, _ptr(dJh), _ptr(dJv), ctypes.byref(db)))
+        return dJh, dJv, db.value
+
+    def stats(self, reset=False):
+        st = _Stats()
+        self._check(lib().tn_stats(self._ctx, ctypes.byref(st), 1 if reset else 0))
+        return {name: getattr(st, name) for name, _ in _Stats._fields_}
