@@ -36,7 +36,7 @@ namespace {
 void free_all(tn_ctx *ctx) {
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
-                    ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->plogq, ctx->counters};
+                    ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -136,6 +136,7 @@ const char *tn_last_error(const tn_ctx *ctx) {
 
 int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                  const double *h, double beta, int D, int prec, double *logZ_out) {
+    (void)hipGetLastError();
     if (!ctx) return TN_EINVAL;
     ctx->err.clear();
     int rc;
@@ -154,6 +155,7 @@ int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv
 int tn_set_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                const double *h, double beta, int D, int prec, const double *env,
                const int *dims, const double *ell, double logZ) {
+    (void)hipGetLastError();
     if (!ctx) return TN_EINVAL;
     ctx->err.clear();
     if (Ly > 1 && (!env || !dims)) return tn_fail(ctx, TN_EINVAL, "env or dims is NULL");
@@ -188,6 +190,7 @@ int tn_set_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
 }
 
 int tn_get_env(tn_ctx *ctx, double *env, int *dims, double *ell, double *logZ) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
@@ -210,6 +213,7 @@ int tn_get_env(tn_ctx *ctx, double *env, int *dims, double *ell, double *logZ) {
 }
 
 int tn_set_precision(tn_ctx *ctx, int prec) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     if ((rc = check_prec(ctx, prec))) return rc;
@@ -227,6 +231,7 @@ int tn_set_instance(tn_ctx *ctx, int inst) {
 
 int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
               int8_t *spins, double *logq, double *energy) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
@@ -239,6 +244,7 @@ int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t fir
 }
 
 int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, double *energy) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
@@ -252,6 +258,7 @@ int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, doub
 
 int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *state_spins,
                double *state_logq, double *state_energy, uint8_t *accepted) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
@@ -278,6 +285,7 @@ int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                  const int8_t *prop_spins, const double *prop_logq, const double *prop_energy,
                  int8_t *state_spins, double *state_logq, double *state_energy,
                  uint8_t *accepted) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
@@ -291,6 +299,7 @@ int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
 }
 
 int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
+    (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
@@ -300,6 +309,7 @@ int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
 }
 
 int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset) {
+    (void)hipGetLastError();
     if (!ctx || !out) return TN_EINVAL;
     unsigned long long c[CNT_N];
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));

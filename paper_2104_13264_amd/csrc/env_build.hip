@@ -142,14 +142,23 @@ __device__ void wg_form_q(const double *A, int m, int n, const double *tau, doub
 
 // One-sided (Hestenes) Jacobi on the rows of W [n][len]: plane rotations of
 // row pairs, in the parallel round-robin order, until every pair is
-// orthogonal to relative tolerance; the same rotations are applied to the rows
-// of Ut [n][n] (so that M = Ut^T W holds throughout).  Returns the number of
-// sweeps, or -1 without convergence.
-__device__ int wg_jacobi(double *W, double *Ut, int n, int len, int *flag) {
+// orthogonal to relative tolerance 4*len*eps; the same rotations are applied
+// to the rows of Ut [n][n] (so that M = Ut^T W holds throughout).  Rows whose
+// squared norm is below (len*eps)^2 ||W||_F^2 are numerically zero: they are
+// not rotated and *zero2 receives that threshold so the caller drops them.
+// Returns the number of sweeps, or -1 without convergence.
+__device__ int wg_jacobi(double *W, double *Ut, int n, int len, int *flag, double *red,
+                         double *zero2) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const double eps = 2.220446049250313e-16;
+    double f2 = 0.0;
+    for (int t = threadIdx.x; t < n * len; t += blockDim.x) f2 += W[t] * W[t];
+    f2 = tn_block_sum(f2, red);
+    const double small2 = f2 * (len * eps) * (len * eps);
+    *zero2 = small2;
     if (n <= 1) return 0;
     const int npad = n + (n & 1);
-    const double tol = 1e-15 * sqrt((double)len);
+    const double tol = 4.0 * len * eps;
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
@@ -174,7 +183,7 @@ __device__ int wg_jacobi(double *W, double *Ut, int n, int len, int *flag) {
                 a = tn_wave_sum(a);
                 b = tn_wave_sum(b);
                 g = tn_wave_sum(g);
-                if (g != 0.0 && fabs(g) > tol * sqrt(a * b)) {
+                if (a > small2 && b > small2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
                     const double zeta = (b - a) / (2.0 * g);
                     const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -216,6 +225,7 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
     __shared__ int mX[4 * TN_MAX_D + 1], nX[4 * TN_MAX_D + 1];
     __shared__ double red[16];
     __shared__ int flag;
+    __shared__ double zero2;
 
     double *B1 = use_lds ? lds : gwork;
     double *B2 = B1 + 8 * D * D;
@@ -297,7 +307,7 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
         for (int t = threadIdx.x; t < rows * rows; t += blockDim.x)
             Ut[t] = (t / rows == t % rows) ? 1.0 : 0.0;
         __syncthreads();
-        const int sweeps = wg_jacobi(W, Ut, rows, len, &flag);
+        const int sweeps = wg_jacobi(W, Ut, rows, len, &flag, red, &zero2);
         if (sweeps < 0 && threadIdx.x == 0) atomicAdd(&counters[CNT_NOCONV], 1ull);
         {
             const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -305,7 +315,7 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
                 double s2 = 0.0;
                 for (int e = lane; e < len; e += 64) s2 += W[i * len + e] * W[i * len + e];
                 s2 = tn_wave_sum(s2);
-                if (lane == 0) sv[i] = sqrt(s2);
+                if (lane == 0) sv[i] = s2 > zero2 ? sqrt(s2) : 0.0;
             }
         }
         __syncthreads();

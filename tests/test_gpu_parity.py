@@ -249,6 +249,7 @@ def test_full_size_ferro64_sampled_parity():
     ref_env = bmps.build_envs(model_of(inst), 32)
     s = Sampler()
     lz = s.build_env(inst.Jh, inst.Jv, None, inst.beta, 32, FP32)
+    log(f"  env build {s.stats()['env_build_ms']:.1f} ms, ln Z~ {lz!r} vs {ref_env['logZ']!r}")
     assert abs(lz - ref_env['logZ']) <= TOL_LOGZ_FP64 * abs(ref_env['logZ'])
     sp, lq, E = s.sample(4096, SEED, step=0)
     pick = np.arange(0, 4096, 257)
