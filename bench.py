@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler "
@@ -169,6 +171,13 @@ def main():
 
     inst = ferro_64()
     L, D, C = inst.Lx, inst.D, inst.chains
+    if args.calib_copy:
+        # a plain copy of known size: 256 MiB read + 256 MiB written
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     log(f"[bench] ferro 64x64 D={D} chains={C} steps={args.steps} warmup={args.warmup}")
 
     res32, env_state = run_gpu(1, inst, args.steps, args.warmup)

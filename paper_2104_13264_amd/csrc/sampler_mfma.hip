@@ -42,19 +42,39 @@ __device__ __forceinline__ short bf16_rne(float f) {
     return (short)(u >> 16);
 }
 
+// A operand of one output tile for one column: the NQ = 4 NT k-chunks of the
+// fp32 16x16x4 product, or the NT chunks of the bf16 16x16x16 product.
 template <int NT, bool BF16>
-__device__ __forceinline__ floatx4 tile_product(const void *Abase, const floatx4 (&x)[NT],
-                                                int lane) {
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (!BF16) {
-        const float *A = (const float *)Abase;
-        constexpr int NQ = 4 * NT;
+struct ATile;
+
+template <int NT>
+struct ATile<NT, false> {
+    static constexpr int NQ = 4 * NT;
+    float a[NQ];
+    __device__ __forceinline__ void load(const void *base, int lane) {
+        const float *A = (const float *)base;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = A[q * 64 + lane];
+    }
+    __device__ __forceinline__ floatx4 mul(const floatx4 (&x)[NT]) const {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q * 64 + lane], x[q >> 2][q & 3], acc, 0,
-                                                       0, 0);
-    } else {
-        const shortx4 *A = (const shortx4 *)Abase;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], x[q >> 2][q & 3], acc, 0, 0, 0);
+        return acc;
+    }
+};
+
+template <int NT>
+struct ATile<NT, true> {
+    shortx4 a[NT];
+    __device__ __forceinline__ void load(const void *base, int lane) {
+        const shortx4 *A = (const shortx4 *)base;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) a[mt] = A[mt * 64 + lane];
+    }
+    __device__ __forceinline__ floatx4 mul(const floatx4 (&x)[NT]) const {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) {
             shortx4 bv;
@@ -62,11 +82,24 @@ __device__ __forceinline__ floatx4 tile_product(const void *Abase, const floatx4
             bv[1] = bf16_rne(x[mt][1]);
             bv[2] = bf16_rne(x[mt][2]);
             bv[3] = bf16_rne(x[mt][3]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[mt * 64 + lane], bv, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], bv, acc, 0, 0, 0);
         }
+        return acc;
     }
-    return acc;
+};
+
+template <int NT, bool BF16>
+__device__ __forceinline__ const void *tile_ptr(const void *G, size_t site, int sw, int mow) {
+    constexpr int Dp = 16 * NT;
+    constexpr size_t TILE = BF16 ? (size_t)NT * 64 * 4 : (size_t)4 * NT * 64;   // elements
+    const size_t off = site * 2 * Dp * Dp + ((size_t)sw * NT + mow) * TILE;
+    return BF16 ? (const void *)((const uint16_t *)G + off) : (const void *)((const float *)G + off);
 }
+
+// Columns of the environment tiles are prefetched PF columns ahead (two for
+// the fp32 tiles of the largest bonds, to stay within the register file).
+template <int NT, bool BF16>
+constexpr int prefetch_depth() { return (NT <= 2 || BF16) ? 3 : 2; }
 
 template <int NT, bool BF16>
 __global__ void __launch_bounds__(128 * NT)
@@ -77,8 +110,6 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                double *__restrict__ logq, double *__restrict__ energy,
                float *__restrict__ gscr, uint32_t k0, uint32_t k1, uint64_t first_id,
                uint32_t step, uint32_t inst, unsigned long long *__restrict__ counters) {
-    constexpr int Dp = 16 * NT;
-    constexpr size_t TILE = BF16 ? (size_t)NT * 64 * 4 : (size_t)4 * NT * 64;  // elements
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int sw = w / NT, mow = w % NT;
     const int n = lane & 15, grp = lane >> 4;
@@ -88,9 +119,11 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
 
     __shared__ floatx4 xch[2][2][NT][64];
     __shared__ int8_t rows[2][16][TN_MAX_LX];
+    __shared__ double sfac[TN_MAX_LX][6];   // Boltzmann factors of the current row
+    __shared__ double scpl[TN_MAX_LX][3];   // h, Jh to the left, Jv to the row above
 
     float *gwg = gscr + (size_t)blockIdx.x * Lx * 2 * NT * 64 * 4;
-    const size_t site_elems = (size_t)2 * Dp * Dp;
+    const size_t gstride = (size_t)2 * NT * 64 * 4;   // floats per column
 
     double mant = 1.0;
     int mexp = 0;
@@ -102,20 +135,37 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
     for (int r = 0; r < Ly; ++r) {
         const int8_t *prow = rows[(r + 1) & 1][n];   // row r-1
         int8_t *crow = rows[r & 1][n];
-        const double *fr = fac + (size_t)r * Lx * 6;
+        for (int t = threadIdx.x; t < Lx; t += blockDim.x) {
+            const double *f = fac + ((size_t)r * Lx + t) * 6;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sfac[t][q] = f[q];
+            scpl[t][0] = h ? h[(size_t)r * Lx + t] : 0.0;
+            scpl[t][1] = t > 0 ? Jh[(size_t)r * (Lx - 1) + t - 1] : 0.0;
+            scpl[t][2] = r > 0 ? Jv[(size_t)(r - 1) * Lx + t] : 0.0;
+        }
+        __syncthreads();
 
         // ---- right sweep: rv = r_{sw} over all Dp components
         floatx4 rv[NT];
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) rv[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         if (grp == 0) rv[0][0] = 1.0f;
+        const size_t rbase = (size_t)r * Lx;
+        constexpr int PF = prefetch_depth<NT, BF16>();
+        ATile<NT, BF16> a0, a1, a2;
+        a0.load(tile_ptr<NT, BF16>(GRv, rbase + Lx - 1, sw, mow), lane);
+        a1.load(tile_ptr<NT, BF16>(GRv, rbase + max(Lx - 2, 0), sw, mow), lane);
+        if constexpr (PF == 3) a2.load(tile_ptr<NT, BF16>(GRv, rbase + max(Lx - 3, 0), sw, mow), lane);
         for (int c = Lx - 1; c >= 0; --c) {
-            const size_t site = (size_t)r * Lx + c;
-            const size_t aoff = site * site_elems + ((size_t)sw * NT + mow) * TILE;
-            const void *A = BF16 ? (const void *)((const uint16_t *)GRv + aoff)
-                                 : (const void *)((const float *)GRv + aoff);
-            const floatx4 acc = tile_product<NT, BF16>(A, rv, lane);
-            *(floatx4 *)(gwg + ((((size_t)c * 2 + sw) * NT + mow) * 64 + lane) * 4) = acc;
+            const floatx4 acc = a0.mul(rv);
+            a0 = a1;
+            if constexpr (PF == 3) {
+                a1 = a2;
+                a2.load(tile_ptr<NT, BF16>(GRv, rbase + max(c - PF, 0), sw, mow), lane);
+            } else {
+                a1.load(tile_ptr<NT, BF16>(GRv, rbase + max(c - PF, 0), sw, mow), lane);
+            }
+            *(floatx4 *)(gwg + c * gstride + (((size_t)sw * NT + mow) * 64 + lane) * 4) = acc;
             if (c == 0) break;
             xch[buf][sw][mow][lane] = acc;
             __syncthreads();
@@ -133,17 +183,16 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
             mx = fmaxf(mx, __shfl_xor(mx, 16));
             mx = fmaxf(mx, __shfl_xor(mx, 32));
             const int e = pow2_exponent_f(mx);
-            const double *f = fr + c * 6;
             const int su = r > 0 ? prow[c] : 1;
-            const double v0 = f[0] * (su > 0 ? f[2] : f[3]);
-            const double v1 = f[1] * (su > 0 ? f[3] : f[2]);
-            const float a0 = (float)((sw == 0 ? f[4] : f[5]) * v0);   // W(s_w,+) v(+)
-            const float a1 = (float)((sw == 0 ? f[5] : f[4]) * v1);   // W(s_w,-) v(-)
+            const double v0 = sfac[c][0] * (su > 0 ? sfac[c][2] : sfac[c][3]);
+            const double v1 = sfac[c][1] * (su > 0 ? sfac[c][3] : sfac[c][2]);
+            const float m0 = (float)((sw == 0 ? sfac[c][4] : sfac[c][5]) * v0);   // W(s_w,+) v(+)
+            const float m1 = (float)((sw == 0 ? sfac[c][5] : sfac[c][4]) * v1);   // W(s_w,-) v(-)
 #pragma unroll
             for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    rv[mo][i] = ldexpf(a0 * y[0][mo][i] + a1 * y[1][mo][i], -e);
+                    rv[mo][i] = ldexpf(m0 * y[0][mo][i] + m1 * y[1][mo][i], -e);
         }
 
         __syncthreads();   // every wave's column-0 tile stored before the left sweep reads it
@@ -154,30 +203,47 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
         for (int mt = 0; mt < NT; ++mt) lam[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         if (grp == 0) lam[0][0] = 1.0f;
         int sprev = 1;
-        for (int c = 0; c < Lx; ++c) {
-            const float *g = gwg + (size_t)c * 2 * NT * 64 * 4;
-            float d0 = 0.0f, d1 = 0.0f;
+        a0.load(tile_ptr<NT, BF16>(GLv, rbase, sw, mow), lane);
+        a1.load(tile_ptr<NT, BF16>(GLv, rbase + min(1, Lx - 1), sw, mow), lane);
+        if constexpr (PF == 3) a2.load(tile_ptr<NT, BF16>(GLv, rbase + min(2, Lx - 1), sw, mow), lane);
+        floatx4 gc[2][NT], gn[2][NT];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int mo = 0; mo < NT; ++mo) {
-                const floatx4 g0 = *(const floatx4 *)(g + ((0 * NT + mo) * 64 + lane) * 4);
-                const floatx4 g1 = *(const floatx4 *)(g + ((1 * NT + mo) * 64 + lane) * 4);
+                gc[s][mo] = *(const floatx4 *)(gwg + (((size_t)s * NT + mo) * 64 + lane) * 4);
+                gn[s][mo] = *(const floatx4 *)(gwg + min(1, Lx - 1) * gstride +
+                                               (((size_t)s * NT + mo) * 64 + lane) * 4);
+            }
+        for (int c = 0; c < Lx; ++c) {
+            float d0 = 0.0f, d1 = 0.0f;
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    d0 = fmaf(lam[mo][i], g0[i], d0);
-                    d1 = fmaf(lam[mo][i], g1[i], d1);
+                    d0 = fmaf(lam[mo][i], gc[0][mo][i], d0);
+                    d1 = fmaf(lam[mo][i], gc[1][mo][i], d1);
                 }
+            {
+                const float *gp = gwg + min(c + 2, Lx - 1) * gstride;
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo) {
+                        gc[s][mo] = gn[s][mo];
+                        gn[s][mo] = *(const floatx4 *)(gp + (((size_t)s * NT + mo) * 64 + lane) * 4);
+                    }
             }
             d0 += __shfl_xor(d0, 16);
             d0 += __shfl_xor(d0, 32);
             d1 += __shfl_xor(d1, 16);
             d1 += __shfl_xor(d1, 32);
-            const double *f = fr + c * 6;
             const int su = r > 0 ? prow[c] : 1;
-            double v0 = f[0] * (su > 0 ? f[2] : f[3]);
-            double v1 = f[1] * (su > 0 ? f[3] : f[2]);
+            double v0 = sfac[c][0] * (su > 0 ? sfac[c][2] : sfac[c][3]);
+            double v1 = sfac[c][1] * (su > 0 ? sfac[c][3] : sfac[c][2]);
             if (c > 0) {
-                v0 *= sprev > 0 ? f[4] : f[5];
-                v1 *= sprev > 0 ? f[5] : f[4];
+                v0 *= sprev > 0 ? sfac[c][4] : sfac[c][5];
+                v1 *= sprev > 0 ? sfac[c][5] : sfac[c][4];
             }
             double w0 = v0 * (double)d0, w1 = v1 * (double)d1;
             if (w0 < 0.0) {
@@ -216,15 +282,18 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 mant = frexp(mant * (s > 0 ? p : 1.0 - p), &e2);
                 mexp += e2;
             }
-            if (h) E -= h[r * Lx + c] * s;
-            if (c > 0) E -= Jh[r * (Lx - 1) + c - 1] * (double)(sprev * s);
-            if (r > 0) E -= Jv[(r - 1) * Lx + c] * (double)(su * s);
+            if (h) E -= scpl[c][0] * s;
+            if (c > 0) E -= scpl[c][1] * (double)(sprev * s);
+            if (r > 0) E -= scpl[c][2] * (double)(su * s);
 
-            const size_t site = (size_t)r * Lx + c;
-            const size_t aoff = site * site_elems + ((size_t)sw * NT + mow) * TILE;
-            const void *A = BF16 ? (const void *)((const uint16_t *)GLv + aoff)
-                                 : (const void *)((const float *)GLv + aoff);
-            const floatx4 acc = tile_product<NT, BF16>(A, lam, lane);
+            const floatx4 acc = a0.mul(lam);
+            a0 = a1;
+            if constexpr (PF == 3) {
+                a1 = a2;
+                a2.load(tile_ptr<NT, BF16>(GLv, rbase + min(c + PF, Lx - 1), sw, mow), lane);
+            } else {
+                a1.load(tile_ptr<NT, BF16>(GLv, rbase + min(c + PF, Lx - 1), sw, mow), lane);
+            }
             xch[buf][sw][mow][lane] = acc;
             __syncthreads();
             float mx = 0.0f;
@@ -244,7 +313,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 for (int i = 0; i < 4; ++i) lam[mo][i] = ldexpf(lam[mo][i], -e);
             sprev = s;
         }
-        __syncthreads();   // row r spins visible to every wave before row r+1
+        __syncthreads();   // row r spins and factors consumed before row r+1 overwrites
     }
     if (leader) {
         logq[b] = log(mant) + (double)mexp * 0.69314718055994530942;
