@@ -1,0 +1,112 @@
+"""Pins of the frozen-truncation derivative of ln Z~ in the oracle."""
+import numpy as np
+import pytest
+
+from oracle import bmps, exact, grad, ising
+from workloads import random_instance, fully_frustrated, uniform
+
+
+def model_of(inst):
+    return ising.Model(inst.Jh, inst.Jv, inst.h, inst.beta)
+
+
+def brute_derivatives(inst):
+    cfg, E, lz, lp = exact.brute_force(inst.Jh, inst.Jv, inst.h, inst.beta)
+    p = np.exp(lp)
+    s = cfg.astype(float)
+    b = inst.beta
+    dJh = b * np.einsum('n,nij->ij', p, s[:, :, :-1] * s[:, :, 1:])
+    dJv = b * np.einsum('n,nij->ij', p, s[:, :-1, :] * s[:, 1:, :])
+    dH = np.einsum('n,nij->ij', p, s)           # d ln Z / d(beta h) = <s>
+    return dJh, dJv, -np.dot(p, E), dH
+
+
+@pytest.mark.parametrize("Ly,Lx,seed,field", [(4, 4, 1, 0.0), (3, 5, 2, 0.3), (5, 3, 3, 0.2),
+                                               (2, 6, 4, 0.0), (4, 1, 5, 0.0), (1, 5, 6, 0.1)])
+def test_untruncated_derivative_is_exact(Ly, Lx, seed, field):
+    inst = random_instance(Ly, Lx, 0.8, 64, seed=seed, field_scale=field)
+    m = model_of(inst)
+    env = bmps.build_envs(m, 64)
+    assert not any(env['trunc'])
+    g = grad.grad_frozen(m, env)
+    bh, bv, bb, bH = brute_derivatives(inst)
+    np.testing.assert_allclose(g['dJh'], bh, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g['dJv'], bv, rtol=0, atol=1e-12)
+    assert abs(g['dbeta'] - bb) < 1e-11
+    np.testing.assert_allclose(g['dH'], bH, rtol=0, atol=1e-12)
+
+
+def fd(model_fn, envs, eps=1e-5):
+    return (grad.frozen_logZ(model_fn(+eps), envs) - grad.frozen_logZ(model_fn(-eps), envs)) / (2 * eps)
+
+
+@pytest.mark.parametrize("mk,D", [
+    (lambda: random_instance(4, 4, 0.8, 2, seed=7), 2),
+    (lambda: random_instance(9, 10, 0.7, 4, seed=8), 4),
+    (lambda: fully_frustrated(8, 1.0, 4), 4),
+    (lambda: random_instance(7, 6, 0.9, 3, seed=9, field_scale=0.3), 3),
+])
+def test_truncated_derivative_matches_finite_differences(mk, D):
+    inst = mk()
+    m = model_of(inst)
+    env = bmps.build_envs(m, D)
+    assert any(env['trunc'])
+    assert abs(grad.frozen_logZ(m, env) - env['logZ']) < 1e-11 * abs(env['logZ'])
+    g = grad.grad_frozen(m, env)
+    rng = np.random.default_rng(1)
+    Ly, Lx = inst.Ly, inst.Lx
+    for _ in range(6):
+        r, c = rng.integers(Ly), rng.integers(Lx - 1)
+
+        def mh(e, r=r, c=c):
+            Jh = inst.Jh.copy()
+            Jh[r, c] += e
+            return ising.Model(Jh, inst.Jv, inst.h, inst.beta)
+        assert abs(fd(mh, env) - g['dJh'][r, c]) < 2e-8
+        r, c = rng.integers(Ly - 1), rng.integers(Lx)
+
+        def mv(e, r=r, c=c):
+            Jv = inst.Jv.copy()
+            Jv[r, c] += e
+            return ising.Model(inst.Jh, Jv, inst.h, inst.beta)
+        assert abs(fd(mv, env) - g['dJv'][r, c]) < 2e-8
+
+    def mb(e):
+        return ising.Model(inst.Jh, inst.Jv, inst.h, inst.beta + e)
+    assert abs(fd(mb, env) - g['dbeta']) < 1e-7
+
+
+def test_beta_identity_without_field():
+    # Z~_frozen depends on beta and J only through K = beta J: beta d_beta = sum J d_J
+    inst = random_instance(8, 7, 0.9, 3, seed=12)
+    m = model_of(inst)
+    env = bmps.build_envs(m, 3)
+    g = grad.grad_frozen(m, env)
+
+    def mb(e):
+        return ising.Model(inst.Jh, inst.Jv, None, inst.beta + e)
+    lhs = inst.beta * fd(mb, env)
+    rhs = (g['dJh'] * inst.Jh).sum() + (g['dJv'] * inst.Jv).sum()
+    assert abs(lhs - rhs) < 1e-7 * max(1.0, abs(rhs))
+
+
+def test_ferro_bond_correlation_symmetry():
+    # the uniform ferromagnet is symmetric under left-right reflection; the
+    # exact (untruncated) bond correlations must be too
+    Jh, Jv = uniform(6, 6, 1.0)
+    m = ising.Model(Jh, Jv, None, 0.44)
+    env = bmps.build_envs(m, 64)
+    g = grad.grad_frozen(m, env)
+    np.testing.assert_allclose(g['dJh'], g['dJh'][:, ::-1], atol=1e-12)
+    np.testing.assert_allclose(g['dJv'], g['dJv'][:, ::-1], atol=1e-12)
+    assert np.all(g['dJh'] > 0) and np.all(g['dJh'] < 0.44)
+
+
+def test_zero_coupling_is_rejected():
+    inst = random_instance(3, 3, 0.5, 4, seed=1)
+    Jh = inst.Jh.copy()
+    Jh[0, 0] = 0.0
+    m = ising.Model(Jh, inst.Jv, None, 0.5)
+    env = bmps.build_envs(m, 4)
+    with pytest.raises(ValueError):
+        grad.grad_frozen(m, env)
