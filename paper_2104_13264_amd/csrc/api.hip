@@ -36,7 +36,8 @@ namespace {
 void free_all(tn_ctx *ctx) {
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
-                    ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters};
+                    ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters,
+                    ctx->cst,   ctx->gradscr};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -84,10 +85,15 @@ int set_instance(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv
     if ((rc = tn_ensure(ctx, (void **)&ctx->env, &ctx->env_cap, envn * sizeof(double)))) return rc;
     if (ctx->dims) (void)hipFree(ctx->dims);
     if (ctx->ell) (void)hipFree(ctx->ell);
+    if (ctx->cst) (void)hipFree(ctx->cst);
     ctx->dims = nullptr;
     ctx->ell = nullptr;
+    ctx->cst = nullptr;
+    ctx->has_cst = false;
     TN_HIP(ctx, hipMalloc((void **)&ctx->dims, (size_t)(Ly + 1) * (Lx + 1) * sizeof(int)));
     TN_HIP(ctx, hipMalloc((void **)&ctx->ell, (size_t)(Ly + 1) * sizeof(double)));
+    TN_HIP(ctx, hipMalloc((void **)&ctx->cst, (size_t)(Ly + 1) * sizeof(int)));
+    TN_HIP(ctx, hipMemsetAsync(ctx->cst, 0xff, (size_t)(Ly + 1) * sizeof(int), ctx->stream));
     TN_HIP(ctx, hipMemsetAsync(ctx->ell, 0, (size_t)(Ly + 1) * sizeof(double), ctx->stream));
     return TN_OK;
 }
@@ -145,6 +151,7 @@ int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv
     if ((rc = tn_env_build_device(ctx, &lz))) return rc;
     if ((rc = tn_make_operands(ctx, prec))) return rc;
     ctx->has_env = true;
+    ctx->has_cst = true;
     if (logZ_out) {
         TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
         *logZ_out = lz;

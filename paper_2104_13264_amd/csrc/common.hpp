@@ -43,6 +43,8 @@ struct tn_ctx {
     double *env = nullptr;
     int *dims = nullptr;
     double *ell = nullptr;
+    int *cst = nullptr;       // leftmost truncated column of env k, -1 if none
+    bool has_cst = false;     // cst valid (environment built here, not installed)
     size_t env_cap = 0;       // elements allocated for env
 
     // sampler operands, one per row r = 0..Ly-1 and column:
@@ -77,6 +79,10 @@ struct tn_ctx {
     size_t pcap = 0;
 
     unsigned long long *counters = nullptr;   // CNT_N
+
+    // adjoint scratch
+    void *gradscr = nullptr;
+    size_t gradscr_cap = 0;
 };
 
 int tn_fail(tn_ctx *ctx, int code, const std::string &msg);

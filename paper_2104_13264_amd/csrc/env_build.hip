@@ -10,6 +10,7 @@
 //   xbox [c][i][u][j]     2D x 2 x 2D box per column: the MPO-MPS product
 //                         X_c[(a,l), u, (b,x)] and its canonical forms
 #include "common.hpp"
+#include "linalg.hpp"
 
 #include <chrono>
 #include <cmath>
@@ -69,74 +70,6 @@ k_mpo_apply(int k, int Lx, int Ly, int D, double beta, const double *__restrict_
     if (threadIdx.x == 0) {
         xdims[c] = m;
         xdims[Lx + 1 + c] = n;
-    }
-}
-
-// Householder QR of A [m][n] (compact, ld = n) by one workgroup: R in the
-// upper triangle, reflector j = (1, A[j+1:, j]) with coefficient tau[j].
-__device__ void wg_householder(double *A, int m, int n, double *tau) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int kk = min(m, n);
-    for (int j = 0; j < kk; ++j) {
-        if (w == 0) {
-            double s2 = 0.0;
-            for (int i = j + 1 + lane; i < m; i += 64) {
-                const double x = A[i * n + j];
-                s2 += x * x;
-            }
-            s2 = tn_wave_sum(s2);
-            const double alpha = A[j * n + j];
-            double t = 0.0, scl = 0.0, beta = alpha;
-            if (s2 > 0.0) {
-                beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-                t = (beta - alpha) / beta;
-                scl = 1.0 / (alpha - beta);
-            }
-            for (int i = j + 1 + lane; i < m; i += 64) A[i * n + j] *= scl;
-            if (lane == 0) {
-                A[j * n + j] = beta;
-                tau[j] = t;
-            }
-        }
-        __syncthreads();
-        const double t = tau[j];
-        if (t != 0.0) {
-            for (int l = j + 1 + w; l < n; l += nw) {
-                double dot = 0.0;
-                for (int i = j + lane; i < m; i += 64)
-                    dot += (i == j ? 1.0 : A[i * n + j]) * A[i * n + l];
-                dot = tn_wave_sum(dot);
-                for (int i = j + lane; i < m; i += 64)
-                    A[i * n + l] -= t * dot * (i == j ? 1.0 : A[i * n + j]);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// Q [m][kk] (ld ldq) = H_0 ... H_{kk-1} [I; 0] from the reflectors in A.
-__device__ void wg_form_q(const double *A, int m, int n, const double *tau, double *Q,
-                          int ldq) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int kk = min(m, n);
-    for (int t = threadIdx.x; t < m * kk; t += blockDim.x) {
-        const int i = t / kk, l = t % kk;
-        Q[i * ldq + l] = (i == l) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int j = kk - 1; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj != 0.0) {
-            for (int l = j + w; l < kk; l += nw) {
-                double dot = 0.0;
-                for (int i = j + lane; i < m; i += 64)
-                    dot += (i == j ? 1.0 : A[i * n + j]) * Q[i * ldq + l];
-                dot = tn_wave_sum(dot);
-                for (int i = j + lane; i < m; i += 64)
-                    Q[i * ldq + l] -= tj * dot * (i == j ? 1.0 : A[i * n + j]);
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -217,7 +150,7 @@ __global__ void __launch_bounds__(1024)
 k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict__ xdims,
                double *__restrict__ env, int *__restrict__ dims, double *__restrict__ ell,
                double *__restrict__ gwork, int use_lds,
-               unsigned long long *__restrict__ counters) {
+               unsigned long long *__restrict__ counters, int *__restrict__ cst) {
     extern __shared__ double lds[];
     __shared__ double tau[2 * TN_MAX_D];
     __shared__ double sv[2 * TN_MAX_D];
@@ -226,6 +159,8 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
     __shared__ double red[16];
     __shared__ int flag;
     __shared__ double zero2;
+    __shared__ int cmin;
+    if (threadIdx.x == 0) cmin = -1;
 
     double *B1 = use_lds ? lds : gwork;
     double *B2 = B1 + 8 * D * D;
@@ -328,9 +263,11 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
         __syncthreads();
         const int nsv = min(rows, len);
         const int chi = min(D, nsv);
-        if (threadIdx.x == 0 && chi < nsv &&
-            sv[idx[chi - 1]] - sv[idx[chi]] < 1e-12 * sv[idx[0]])
-            atomicAdd(&counters[CNT_DEGEN], 1ull);
+        if (threadIdx.x == 0 && chi < nsv) {
+            cmin = c;   // the sweep runs right to left: the last cut is the leftmost
+            if (sv[idx[chi - 1]] - sv[idx[chi]] < 1e-12 * sv[idx[0]])
+                atomicAdd(&counters[CNT_DEGEN], 1ull);
+        }
         // X_{c-1} <- X_{c-1} U[:, :chi] S[:chi]   (into T first)
         const int m1 = 2 * mX[c - 1];
         for (int t = threadIdx.x; t < m1 * chi; t += blockDim.x) {
@@ -387,7 +324,10 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
     }
     for (int c = threadIdx.x; c <= Lx; c += blockDim.x)
         dims[k * (Lx + 1) + c] = c < Lx ? mX[c] : 1;
-    if (threadIdx.x == 0) ell[k] = lognorm;
+    if (threadIdx.x == 0) {
+        ell[k] = lognorm;
+        cst[k] = cmin;
+    }
 }
 
 // ln <top|env_1>: row 0 (no up legs) contracted with env 1 left to right,
@@ -506,7 +446,7 @@ int tn_env_build_device(tn_ctx *ctx, double *logZ_out) {
         TN_HIP(ctx, hipGetLastError());
         hipLaunchKernelGGL(k_truncate_row, dim3(1), dim3(1024), lds_bytes, ctx->stream, k, Lx,
                            D, ctx->xbox, ctx->xdims, ctx->env, ctx->dims, ctx->ell,
-                           ctx->wbuf, use_lds ? 1 : 0, ctx->counters);
+                           ctx->wbuf, use_lds ? 1 : 0, ctx->counters, ctx->cst);
         TN_HIP(ctx, hipGetLastError());
     }
     double logtop, sign;

@@ -1,0 +1,79 @@
+"""Parity of tn_grad (frozen-truncation derivative of ln Z~) with the oracle.
+
+The GPU builds its own environment; the frozen projectors are spans, so the
+derivative is gauge invariant and comparable to the oracle's element by
+element.  Tolerance: 1e-9 absolute on d ln Z~/dJ (entries are O(beta)),
+1e-9 relative on d ln Z~/d beta.
+"""
+import numpy as np
+import pytest
+
+from oracle import bmps, exact, grad, ising
+from workloads import random_instance, fully_frustrated, ea_pm, ferro
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("4x4 untruncated field", lambda: random_instance(4, 4, 0.8, 8, seed=1, field_scale=0.3), 8),
+    ("3x5 untruncated", lambda: random_instance(3, 5, 0.7, 8, seed=2), 8),
+    ("4x4 D2", lambda: random_instance(4, 4, 0.8, 2, seed=7), 2),
+    ("9x10 D4", lambda: random_instance(9, 10, 0.7, 4, seed=8), 4),
+    ("frustrated 8 D4", lambda: fully_frustrated(8, 1.0, 4), 4),
+    ("ea 12 D8", lambda: ea_pm(12, 1.0, 8, seed=5), 8),
+    ("ragged 11x7 D5 field", lambda: random_instance(11, 7, 0.6, 5, seed=9, field_scale=0.2), 5),
+    ("strip 1x6", lambda: random_instance(1, 6, 0.6, 4, seed=10), 4),
+    ("column 6x1", lambda: random_instance(6, 1, 0.6, 4, seed=11), 4),
+]
+
+
+@pytest.mark.parametrize("name,mk,D", CASES, ids=[c[0] for c in CASES])
+def test_grad_matches_oracle(name, mk, D):
+    from paper_2104_13264_amd import Sampler
+    inst = mk()
+    print(f"[grad] {name} Ly={inst.Ly} Lx={inst.Lx} D={D}", flush=True)
+    m = ising.Model(inst.Jh, inst.Jv, inst.h, inst.beta)
+    env = bmps.build_envs(m, D)
+    ref = grad.grad_frozen(m, env)
+    s = Sampler()
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, D)
+    dJh, dJv, db = s.grad()
+    dJh, dJv = dJh.cpu().numpy(), dJv.cpu().numpy()
+    np.testing.assert_allclose(dJh, ref['dJh'], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(dJv, ref['dJv'], rtol=0, atol=1e-9)
+    assert abs(db - ref['dbeta']) <= 1e-9 * max(1.0, abs(ref['dbeta']))
+    s.close()
+
+
+def test_untruncated_grad_is_bond_correlation():
+    from paper_2104_13264_amd import Sampler
+    inst = random_instance(4, 4, 0.9, 8, seed=3)
+    cfg, E, lz, lp = exact.brute_force(inst.Jh, inst.Jv, None, inst.beta)
+    p = np.exp(lp)
+    sp = cfg.astype(float)
+    s = Sampler()
+    s.build_env(inst.Jh, inst.Jv, None, inst.beta, 8)
+    dJh, dJv, db = s.grad()
+    bh = inst.beta * np.einsum('n,nij->ij', p, sp[:, :, :-1] * sp[:, :, 1:])
+    bv = inst.beta * np.einsum('n,nij->ij', p, sp[:, :-1, :] * sp[:, 1:, :])
+    np.testing.assert_allclose(dJh.cpu().numpy(), bh, atol=1e-11)
+    np.testing.assert_allclose(dJv.cpu().numpy(), bv, atol=1e-11)
+    assert abs(db + np.dot(p, E)) < 1e-10
+    s.close()
+
+
+def test_grad_rejects_zero_coupling_and_installed_env():
+    from paper_2104_13264_amd import Sampler, TNError
+    inst = random_instance(3, 4, 0.5, 4, seed=1)
+    Jh = inst.Jh.copy()
+    Jh[1, 1] = 0.0
+    s = Sampler()
+    s.build_env(Jh, inst.Jv, None, 0.5, 4)
+    with pytest.raises(TNError):
+        s.grad()
+    envs = s.get_env()
+    t = Sampler()
+    t.set_env(inst.Jh, inst.Jv, None, 0.5, 4, *envs[:3], envs[3])
+    with pytest.raises(TNError):
+        t.grad()
+    s.close()
+    t.close()
