@@ -8,19 +8,24 @@ notes that with the boundary tensors stored the whole update costs time linear
 in the lattice size, i.e. partial contractions are cached.
 
 Readings adopted:
-  * Site order is row-major: row 0 first, left to right inside a row (the
-    labelling figure of the paper is not available; the within-row order does
-    not change q, since every row is contracted exactly).
+  * Site order is the snake (boustrophedon) labelling: row 0 first, even
+    rows left to right, odd rows right to left (the labelling figure of the
+    paper is not available; the within-row order does not change q, since every
+    row is contracted exactly, but it fixes which random number meets which
+    site).  Before sampling a row, the environments of its free columns are
+    contracted from the far end towards the row's starting column.
   * For row r, the fixed rows above reduce to a product state: the fixed spin
     s' above column c enters through its down leg contracted with the up leg of
     (r,c), v_c(s) = exp(beta h s) sum_u P(s',u) Q(u,s).  The rows below are the
     stored env r+1.  The conditional of column c is the ratio of two exact
-    contractions of row r with that env, normalised over s in {+1,-1}:
+    contractions of row r with that env, normalised over s in {+1,-1}; in a
+    rightward row
         w(s) = v_c(s) hf(s) sum_x' R(s,x') [(Lam G_c(s)) . rho_c[x']]
         G_c(s) = sum_d D(s,d) env_{r+1,c}[:, d, :]
-    with rho_c the right environment of the free columns c+1.. (horizontal leg
-    x' and env bond), Lam the left environment of the fixed columns ..c-1 and
-    hf(s) the horizontal bond to the fixed left neighbour.
+    with rho_c the environment of the free columns c+1.. (horizontal leg x' and
+    env bond), Lam the environment of the fixed columns ..c-1 and hf(s) the
+    horizontal bond to the fixed neighbour; a leftward row is the mirror image
+    (free columns ..c-1 contracted from the left, Lam <- G_c(s) Lam).
   * Negative weights (ill-conditioning, App. A remark on positivity) are
     clamped to 0 and counted; if both weights are <= 0 (or not finite) the
     draw uses p+ = 1/2 and is counted.
@@ -95,29 +100,54 @@ def run_rows(model, envs, batch, seed=0, step=0, first_id=0, inst=0,
                 v[:, c, :] = f[None, :] * W[idx, :]
             else:
                 v[:, c, :] = f[None, :]
-        # right sweep: rho[c][b, x', a] for the free columns c+1..Lx-1
-        rho = [None] * Lx
-        rho[Lx - 1] = np.ones((B, 1, 1))
-        for c in range(Lx - 1, 0, -1):
-            Gc = G[c]                                             # [2, Dl, Dr]
-            ns, Dl, Dr = Gc.shape
-            Xp = rho[c].shape[1]
-            t = (rho[c].reshape(B * Xp, Dr) @ Gc.reshape(ns * Dl, Dr).T)
-            t = t.reshape(B, Xp, ns, Dl)                          # [b,x',s,a]
-            y = np.einsum('sx,bxsa->bsa', model.right_leg(r, c), t)
-            nr = np.einsum('xs,bs,bsa->bxa', model.left_leg(r, c), v[:, c, :], y)
-            rho[c - 1] = _pow2_rescale(nr, (1, 2))
-        # left sweep: draw (or read) column by column
+        if r % 2 == 0:
+            # rightward row: environments of the free columns to the right
+            env_side = [None] * Lx
+            env_side[Lx - 1] = np.ones((B, 1, 1))                  # [b, x', a]
+            for c in range(Lx - 1, 0, -1):
+                Gc = G[c]                                         # [2, Dl, Dr]
+                ns, Dl, Dr = Gc.shape
+                Xp = env_side[c].shape[1]
+                t = (env_side[c].reshape(B * Xp, Dr) @ Gc.reshape(ns * Dl, Dr).T)
+                t = t.reshape(B, Xp, ns, Dl)                      # [b,x',s,a]
+                y = np.einsum('sx,bxsa->bsa', model.right_leg(r, c), t)
+                nr = np.einsum('xs,bs,bsa->bxa', model.left_leg(r, c), v[:, c, :], y)
+                env_side[c - 1] = _pow2_rescale(nr, (1, 2))
+            order = range(Lx)
+        else:
+            # leftward row: environments of the free columns to the left
+            env_side = [None] * Lx
+            env_side[0] = np.ones((B, 1, 1))                      # [b, x, a]
+            for c in range(0, Lx - 1):
+                Gc = G[c]
+                ns, Dl, Dr = Gc.shape
+                Xl = env_side[c].shape[1]
+                t = (env_side[c].reshape(B * Xl, Dl) @ Gc.transpose(1, 0, 2).reshape(Dl, ns * Dr))
+                t = t.reshape(B, Xl, ns, Dr)                      # [b,x,s,a']
+                y = np.einsum('xs,bxsa->bsa', model.left_leg(r, c), t)
+                nl = np.einsum('sx,bs,bsa->bxa', model.right_leg(r, c), v[:, c, :], y)
+                env_side[c + 1] = _pow2_rescale(nl, (1, 2))
+            order = range(Lx - 1, -1, -1)
+        # sampling sweep in the row's direction, column by column
         lam = np.ones((B, 1))
-        for c in range(Lx):
+        prev = None
+        for c in order:
             Gc = G[c]
             ns, Dl, Dr = Gc.shape
-            lg = (lam @ Gc.transpose(1, 0, 2).reshape(Dl, ns * Dr)).reshape(B, ns, Dr)
-            z = np.einsum('bsa,bxa->bsx', lg, rho[c])
-            w = v[:, c, :] * np.einsum('sx,bsx->bs', model.right_leg(r, c), z)
-            if c > 0:
-                W = model.right_leg(r, c - 1) @ model.left_leg(r, c)   # [s', s]
-                idx = (1 - out[:, r, c - 1]) // 2
+            if r % 2 == 0:
+                lg = (lam @ Gc.transpose(1, 0, 2).reshape(Dl, ns * Dr)).reshape(B, ns, Dr)
+                z = np.einsum('bsa,bxa->bsx', lg, env_side[c])
+                w = v[:, c, :] * np.einsum('sx,bsx->bs', model.right_leg(r, c), z)
+                if prev is not None:
+                    W = model.right_leg(r, c - 1) @ model.left_leg(r, c)   # [s', s]
+            else:
+                lg = np.einsum('sab,zb->zsa', Gc, lam)            # G_c(s) Lam
+                z = np.einsum('bsa,bxa->bsx', lg, env_side[c])
+                w = v[:, c, :] * np.einsum('xs,bsx->bs', model.left_leg(r, c), z)
+                if prev is not None:
+                    W = (model.right_leg(r, c) @ model.left_leg(r, c + 1)).T   # [s', s]
+            if prev is not None:
+                idx = (1 - out[:, r, prev]) // 2
                 w = w * W[idx, :]
             neg = w < 0
             clamps += neg.sum(axis=1)
@@ -141,6 +171,7 @@ def run_rows(model, envs, batch, seed=0, step=0, first_id=0, inst=0,
                 logq += np.log(ps)
             idx = (1 - s) // 2
             lam = _pow2_rescale(lg[rows_b, idx, :], (1,))
+            prev = c
     E = energy(out, model.Jh, model.Jv, model.h)
     return dict(spins=out, logq=logq, energy=E, clamps=clamps,
                 both_nonpos=both, near=nnear, min_gap=min_gap)

@@ -8,11 +8,13 @@
 // matrix-vector products broadcast the input vector across the team with
 // lane shuffles.  No LDS is used.
 //
-// Row r, given the fixed row r-1 above and env r+1 below:
-//   right sweep (c = Lx-1 .. 0):  y_s = G_c(s) r_s^(c)   (stored per column)
+// Site order: snake (even rows left to right, odd rows right to left).
+// Row r, given the fixed row r-1 above and env r+1 below (rightward row; a
+// leftward row is the mirror image with G^T and the bonds to the right):
+//   environment sweep (c = Lx-1 .. 0):  y_s = G_c(s) r_s^(c)  (stored per column)
 //       r_s'^(c-1) = sum_s W_{c-1,c}(s',s) v_c(s) y_s,   v_c(s) = exp(beta h s)
 //       exp(beta Jv s_up s), W = exp(beta Jh s' s); rescaled by a power of two
-//   left sweep (c = 0 .. Lx-1):   w(s) = v_c(s) hf(s) <Lam, y_s>,
+//   sampling sweep (c = 0 .. Lx-1):   w(s) = v_c(s) hf(s) <Lam, y_s>,
 //       hf(s) = exp(beta Jh s_{c-1} s); clamp; p+ = w+/(w+ + w-); draw;
 //       ln q += ln p_s;  Lam <- Lam G_c(s), rescaled by a power of two
 #include "common.hpp"
@@ -60,51 +62,69 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
     const int8_t *up = r > 0 ? S + ((size_t)b * Ly + r - 1) * Lx : nullptr;
     int8_t *row = S + ((size_t)b * Ly + r) * Lx;
 
-    // ---- right sweep
+    const bool rightward = (r & 1) == 0;   // snake order: even rows left to right
+
+    // ---- environment sweep of the free columns, from the far end of the row
     double r0 = (j == 0) ? 1.0 : 0.0, r1 = r0;
-    for (int c = Lx - 1; c >= 0; --c) {
+    for (int t = 0; t < Lx; ++t) {
+        const int c = rightward ? Lx - 1 - t : t;
         const int Dl = dm[c], Dr = dm[c + 1];
-        const double *G0 = Gc + (size_t)c * 2 * DD, *G1 = G0 + DD;
         double y0 = 0.0, y1 = 0.0;
-        for (int k = 0; k < Dr; ++k) {
-            const double x0 = __shfl(r0, k, T), x1 = __shfl(r1, k, T);
-            if (j < Dl) {
-                y0 += G0[k * D + j] * x0;
-                y1 += G1[k * D + j] * x1;
+        if (rightward) {   // y_s = G_c(s) r_s: input right bond, output left bond
+            const double *G0 = Gc + (size_t)c * 2 * DD, *G1 = G0 + DD;
+            for (int k = 0; k < Dr; ++k) {
+                const double x0 = __shfl(r0, k, T), x1 = __shfl(r1, k, T);
+                if (j < Dl) {
+                    y0 += G0[k * D + j] * x0;
+                    y1 += G1[k * D + j] * x1;
+                }
+            }
+        } else {           // y_s = G_c(s)^T l_s: input left bond, output right bond
+            const double *G0 = Gr + (size_t)c * 2 * DD, *G1 = G0 + DD;
+            for (int k = 0; k < Dl; ++k) {
+                const double x0 = __shfl(r0, k, T), x1 = __shfl(r1, k, T);
+                if (j < Dr) {
+                    y0 += G0[k * D + j] * x0;
+                    y1 += G1[k * D + j] * x1;
+                }
             }
         }
         if (j < D) {
             gs[(c * 2 + 0) * D + j] = y0;
             gs[(c * 2 + 1) * D + j] = y1;
         }
-        if (c > 0) {
+        if (t + 1 < Lx) {
             const double *f = fr + c * 6;
+            // bond towards the next column of the sweep
+            const double *fb = fr + (rightward ? c : c + 1) * 6;
             const int su = up ? up[c] : 1;
             const double v0 = f[0] * (su > 0 ? f[2] : f[3]);   // s = +1
             const double v1 = f[1] * (su > 0 ? f[3] : f[2]);   // s = -1
-            const double n0 = f[4] * v0 * y0 + f[5] * v1 * y1;
-            const double n1 = f[5] * v0 * y0 + f[4] * v1 * y1;
+            const double n0 = fb[4] * v0 * y0 + fb[5] * v1 * y1;
+            const double n1 = fb[5] * v0 * y0 + fb[4] * v1 * y1;
             const int e = pow2_exponent(team_max<T>(fmax(fabs(n0), fabs(n1))));
             r0 = ldexp(n0, -e);
             r1 = ldexp(n1, -e);
         }
     }
 
-    // ---- left sweep
+    // ---- sampling sweep in the row's direction
     double lam = (j == 0) ? 1.0 : 0.0;
     int sprev = 1;
     double lq = 0.0, E = 0.0;
     uint4 blk = make_uint4(0, 0, 0, 0);
     int blk_id = -1;
-    for (int c = 0; c < Lx; ++c) {
+    for (int t = 0; t < Lx; ++t) {
+        const int c = rightward ? t : Lx - 1 - t;
         const int Dl = dm[c], Dr = dm[c + 1];
         const double *f = fr + c * 6;
         const int su = up ? up[c] : 1;
         double v0 = f[0] * (su > 0 ? f[2] : f[3]);
         double v1 = f[1] * (su > 0 ? f[3] : f[2]);
-        if (c > 0) {
-            v0 *= sprev > 0 ? f[4] : f[5];
-            v1 *= sprev > 0 ? f[5] : f[4];
+        if (t > 0) {   // bond to the previously drawn neighbour
+            const double *fb = fr + (rightward ? c : c + 1) * 6;
+            v0 *= sprev > 0 ? fb[4] : fb[5];
+            v1 *= sprev > 0 ? fb[5] : fb[4];
         }
         const double g0 = j < D ? gs[(c * 2 + 0) * D + j] : 0.0;
         const double g1 = j < D ? gs[(c * 2 + 1) * D + j] : 0.0;
@@ -141,16 +161,23 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
             }
         }
         lq += log(s > 0 ? p : 1.0 - p);
-        // energy, Eq. (ising): field, left bond, bond to the row above
+        // energy, Eq. (ising): field, bond to the previous neighbour, bond above
         if (h) E -= h[r * Lx + c] * s;
-        if (c > 0) E -= Jh[r * (Lx - 1) + c - 1] * (double)(sprev * s);
+        if (t > 0) E -= Jh[r * (Lx - 1) + (rightward ? c - 1 : c)] * (double)(sprev * s);
         if (up) E -= Jv[(r - 1) * Lx + c] * (double)(up[c] * s);
-        // Lam <- Lam G_c(s)
-        const double *Gs = Gr + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
         double nl = 0.0;
-        for (int a = 0; a < Dl; ++a) {
-            const double x = __shfl(lam, a, T);
-            if (j < Dr) nl += x * Gs[a * D + j];
+        if (rightward) {   // Lam <- Lam G_c(s): input left bond, output right bond
+            const double *Gs = Gr + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
+            for (int a = 0; a < Dl; ++a) {
+                const double x = __shfl(lam, a, T);
+                if (j < Dr) nl += x * Gs[a * D + j];
+            }
+        } else {           // Lam <- G_c(s) Lam: input right bond, output left bond
+            const double *Gs = Gc + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
+            for (int k = 0; k < Dr; ++k) {
+                const double x = __shfl(lam, k, T);
+                if (j < Dl) nl += x * Gs[k * D + j];
+            }
         }
         const int e = pow2_exponent(team_max<T>(fabs(nl)));
         lam = ldexp(nl, -e);

@@ -101,8 +101,17 @@ __device__ __forceinline__ const void *tile_ptr(const void *G, size_t site, int 
 template <int NT, bool BF16>
 constexpr int prefetch_depth() { return (NT <= 2 || BF16) ? 3 : 2; }
 
+// Snake order: row r is drawn left to right when r is even, right to left
+// when odd.  Before a row is drawn, the environments of its free columns are
+// swept from its far end; that sweep runs in the same column order as the
+// drawing of the row above, so the two run side by side: phase p pairs the
+// environment sweep of row p (group p & 1) with the drawing of row p-1 (the
+// other group), one column per step and one barrier per step, and the drawn
+// spin of a column is in LDS before the environment sweep of the row below
+// needs it.  A rightward phase multiplies by G^T (GL tiles), a leftward one by
+// G (GR tiles), for both groups.
 template <int NT, bool BF16>
-__global__ void __launch_bounds__(128 * NT)
+__global__ void __launch_bounds__(256 * NT)
 k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                const double *__restrict__ Jv, const double *__restrict__ h,
                const double *__restrict__ fac, const void *__restrict__ GRv,
@@ -110,213 +119,253 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                double *__restrict__ logq, double *__restrict__ energy,
                float *__restrict__ gscr, uint32_t k0, uint32_t k1, uint64_t first_id,
                uint32_t step, uint32_t inst, unsigned long long *__restrict__ counters) {
+    constexpr int NW = 2 * NT;                        // waves per group
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int sw = w / NT, mow = w % NT;
+    const int gp = w / NW, wl = w % NW;
+    const int sw = wl / NT, mow = wl % NT;
     const int n = lane & 15, grp = lane >> 4;
     const int b = blockIdx.x * 16 + n;
     const bool valid = b < B;
-    const bool leader = (w == 0 && grp == 0 && valid);
+    const bool leader = (wl == 0 && grp == 0);        // one lane per proposal per group
 
-    __shared__ floatx4 xch[2][2][NT][64];
-    __shared__ int8_t rows[2][16][TN_MAX_LX];
-    __shared__ double sfac[TN_MAX_LX][6];   // Boltzmann factors of the current row
-    __shared__ double scpl[TN_MAX_LX][3];   // h, Jh to the left, Jv to the row above
+    __shared__ floatx4 xch[2][2][2][NT][64];         // [group][buf][s][mo][lane]
+    __shared__ int8_t rows[2][16][TN_MAX_LX];         // spins by row parity
+    __shared__ uint32_t uni[2][16][TN_MAX_LX];        // random words by row parity
+    __shared__ float mixP[TN_MAX_LX][2][2][2];        // [c][s_up][s_w][s]
+    __shared__ double vS[TN_MAX_LX][2][2][2];         // [c][s_up][s_prev][s]
+    __shared__ double lqx[2][16][2];                  // ln q parts per group
 
-    float *gwg = gscr + (size_t)blockIdx.x * Lx * 2 * NT * 64 * 4;
     const size_t gstride = (size_t)2 * NT * 64 * 4;   // floats per column
+    float *gwg = gscr + (size_t)(blockIdx.x * 2 + gp) * Lx * gstride;
+    const int NTH = blockDim.x;
 
-    double mant = 1.0;
+    double mant = 1.0, E = 0.0;
     int mexp = 0;
-    double E = 0.0;
+    unsigned long long n_clamp = 0, n_both = 0, n_near = 0;
     int buf = 0;
-    uint4 blk = make_uint4(0, 0, 0, 0);
-    int blk_id = -1;
 
-    for (int r = 0; r < Ly; ++r) {
-        const int8_t *prow = rows[(r + 1) & 1][n];   // row r-1
-        int8_t *crow = rows[r & 1][n];
-        for (int t = threadIdx.x; t < Lx; t += blockDim.x) {
-            const double *f = fac + ((size_t)r * Lx + t) * 6;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) sfac[t][q] = f[q];
-            scpl[t][0] = h ? h[(size_t)r * Lx + t] : 0.0;
-            scpl[t][1] = t > 0 ? Jh[(size_t)r * (Lx - 1) + t - 1] : 0.0;
-            scpl[t][2] = r > 0 ? Jv[(size_t)(r - 1) * Lx + t] : 0.0;
+    for (int p = 0; p <= Ly; ++p) {
+        const bool hasP = p < Ly, hasS = p >= 1;
+        const bool isP = hasP && gp == (p & 1);
+        const bool isS = hasS && gp != (p & 1);
+        const bool rightward = (p & 1) != 0;          // column order of this phase
+        const int rS = p - 1;                          // row drawn in this phase
+        // ---- phase set-up: factor tables, random words, given spins
+        for (int t = threadIdx.x; t < Lx * 8; t += NTH) {
+            const int c = t >> 3, su = (t >> 2) & 1, x = (t >> 1) & 1, s = t & 1;
+            if (hasP) {   // environment sweep of row p: W(s_w = x, s) v_c(s; s_up)
+                const double *f = fac + ((size_t)p * Lx + c) * 6;
+                const int cb = rightward ? c + 1 : c;   // bond towards the next column
+                double Wv = 1.0;
+                if (cb >= 1 && cb <= Lx - 1) Wv = fac[((size_t)p * Lx + cb) * 6 + ((x == s) ? 4 : 5)];
+                const double v = f[s] * f[2 + (su ^ s)];
+                mixP[c][su][x][s] = (float)(Wv * v);
+            }
+            if (hasS) {   // drawing of row p-1: v_c(s; s_up) hf(s; s_prev)
+                const double *f = fac + ((size_t)rS * Lx + c) * 6;
+                const int cb = rightward ? c : c + 1;   // bond to the previous column
+                double hf = 1.0;
+                if (cb >= 1 && cb <= Lx - 1) hf = fac[((size_t)rS * Lx + cb) * 6 + ((x == s) ? 4 : 5)];
+                vS[c][su][x][s] = f[s] * f[2 + (su ^ s)] * hf;
+            }
+        }
+        if (hasP && !eval) {   // random words of row p (drawn in the next phase)
+            for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
+                const int nn = t / Lx, c = t % Lx;
+                const int i = p * Lx + c;
+                const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2),
+                                                     (uint32_t)(first_id + blockIdx.x * 16 + nn),
+                                                     step, (inst << 2) | 0u), k0, k1);
+                uni[p & 1][nn][c] = tn_word(x, i & 3);
+            }
+        }
+        if (hasS && eval) {   // the given spins of row p-1
+            for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
+                const int nn = t / Lx, c = t % Lx;
+                const int bb = blockIdx.x * 16 + nn;
+                rows[rS & 1][nn][c] = bb < B ? S[((size_t)bb * Ly + rS) * Lx + c] : (int8_t)1;
+            }
         }
         __syncthreads();
 
-        // ---- right sweep: rv = r_{sw} over all Dp components
-        floatx4 rv[NT];
+        const size_t rowP = (size_t)p * Lx, rowSb = (size_t)rS * Lx;
+        const void *Gph = rightward ? GLv : GRv;
+        floatx4 vec[NT];   // r_{s_w} (environment sweep) or Lam (drawing)
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) rv[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        if (grp == 0) rv[0][0] = 1.0f;
-        const size_t rbase = (size_t)r * Lx;
-        constexpr int PF = prefetch_depth<NT, BF16>();
+        for (int mt = 0; mt < NT; ++mt) vec[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (grp == 0) vec[0][0] = 1.0f;
         ATile<NT, BF16> a0, a1, a2;
-        a0.load(tile_ptr<NT, BF16>(GRv, rbase + Lx - 1, sw, mow), lane);
-        a1.load(tile_ptr<NT, BF16>(GRv, rbase + max(Lx - 2, 0), sw, mow), lane);
-        if constexpr (PF == 3) a2.load(tile_ptr<NT, BF16>(GRv, rbase + max(Lx - 3, 0), sw, mow), lane);
-        for (int c = Lx - 1; c >= 0; --c) {
-            const floatx4 acc = a0.mul(rv);
-            a0 = a1;
-            if constexpr (PF == 3) {
-                a1 = a2;
-                a2.load(tile_ptr<NT, BF16>(GRv, rbase + max(c - PF, 0), sw, mow), lane);
-            } else {
-                a1.load(tile_ptr<NT, BF16>(GRv, rbase + max(c - PF, 0), sw, mow), lane);
-            }
-            *(floatx4 *)(gwg + c * gstride + (((size_t)sw * NT + mow) * 64 + lane) * 4) = acc;
-            if (c == 0) break;
-            xch[buf][sw][mow][lane] = acc;
-            __syncthreads();
-            floatx4 y[2][NT];
-            float mx = 0.0f;
+        constexpr int PF = prefetch_depth<NT, BF16>();
+        const size_t rbase = isP ? rowP : rowSb;
+        auto colof = [&](int t) { return rightward ? t : Lx - 1 - t; };
+        if (isP || isS) {
+            a0.load(tile_ptr<NT, BF16>(Gph, rbase + colof(0), sw, mow), lane);
+            a1.load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(1, Lx - 1)), sw, mow), lane);
+            if constexpr (PF == 3)
+                a2.load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(2, Lx - 1)), sw, mow), lane);
+        }
+        floatx4 gc[2][NT], gn[2][NT];
+        if (isS) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+            for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
                 for (int mo = 0; mo < NT; ++mo) {
-                    y[s][mo] = xch[buf][s][mo][lane];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(y[s][mo][i]));
+                    gc[s2][mo] = *(const floatx4 *)(gwg + colof(0) * gstride +
+                                                    (((size_t)s2 * NT + mo) * 64 + lane) * 4);
+                    gn[s2][mo] = *(const floatx4 *)(gwg + colof(min(1, Lx - 1)) * gstride +
+                                                    (((size_t)s2 * NT + mo) * 64 + lane) * 4);
                 }
-            buf ^= 1;
-            mx = fmaxf(mx, __shfl_xor(mx, 16));
-            mx = fmaxf(mx, __shfl_xor(mx, 32));
-            const int e = pow2_exponent_f(mx);
-            const int su = r > 0 ? prow[c] : 1;
-            const double v0 = sfac[c][0] * (su > 0 ? sfac[c][2] : sfac[c][3]);
-            const double v1 = sfac[c][1] * (su > 0 ? sfac[c][3] : sfac[c][2]);
-            const float m0 = (float)((sw == 0 ? sfac[c][4] : sfac[c][5]) * v0);   // W(s_w,+) v(+)
-            const float m1 = (float)((sw == 0 ? sfac[c][5] : sfac[c][4]) * v1);   // W(s_w,-) v(-)
-#pragma unroll
-            for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    rv[mo][i] = ldexpf(m0 * y[0][mo][i] + m1 * y[1][mo][i], -e);
         }
+        const int8_t *prowP = rows[(p + 1) & 1][n];     // row p-1 (above row p)
+        const int8_t *prowS = rows[p & 1][n];           // row p-2 (above row p-1)
+        int8_t *crowS = rows[(p + 1) & 1][n];           // row p-1, written by the drawing
+        const uint32_t *urow = uni[(p + 1) & 1][n];     // words of row p-1
+        int sprev = 0;   // index of the previous spin (0: +1, 1: -1); unused at t = 0
 
-        __syncthreads();   // every wave's column-0 tile stored before the left sweep reads it
-
-        // ---- left sweep
-        floatx4 lam[NT];
+        for (int t = 0; t < Lx; ++t) {
+            const int c = colof(t);
+            int s = 1;
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (isS) {
+                float d0 = 0.0f, d1 = 0.0f;
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) lam[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        if (grp == 0) lam[0][0] = 1.0f;
-        int sprev = 1;
-        a0.load(tile_ptr<NT, BF16>(GLv, rbase, sw, mow), lane);
-        a1.load(tile_ptr<NT, BF16>(GLv, rbase + min(1, Lx - 1), sw, mow), lane);
-        if constexpr (PF == 3) a2.load(tile_ptr<NT, BF16>(GLv, rbase + min(2, Lx - 1), sw, mow), lane);
-        floatx4 gc[2][NT], gn[2][NT];
+                for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+                    for (int i = 0; i < 4; ++i) {
+                        d0 = fmaf(vec[mo][i], gc[0][mo][i], d0);
+                        d1 = fmaf(vec[mo][i], gc[1][mo][i], d1);
+                    }
+                {
+                    const float *gp2 = gwg + colof(min(t + 2, Lx - 1)) * gstride;
 #pragma unroll
-            for (int mo = 0; mo < NT; ++mo) {
-                gc[s][mo] = *(const floatx4 *)(gwg + (((size_t)s * NT + mo) * 64 + lane) * 4);
-                gn[s][mo] = *(const floatx4 *)(gwg + min(1, Lx - 1) * gstride +
-                                               (((size_t)s * NT + mo) * 64 + lane) * 4);
-            }
-        for (int c = 0; c < Lx; ++c) {
-            float d0 = 0.0f, d1 = 0.0f;
+                    for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-            for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    d0 = fmaf(lam[mo][i], gc[0][mo][i], d0);
-                    d1 = fmaf(lam[mo][i], gc[1][mo][i], d1);
+                        for (int mo = 0; mo < NT; ++mo) {
+                            gc[s2][mo] = gn[s2][mo];
+                            gn[s2][mo] = *(const floatx4 *)(gp2 + (((size_t)s2 * NT + mo) * 64 + lane) * 4);
+                        }
                 }
-            {
-                const float *gp = gwg + min(c + 2, Lx - 1) * gstride;
+                d0 += __shfl_xor(d0, 16);
+                d0 += __shfl_xor(d0, 32);
+                d1 += __shfl_xor(d1, 16);
+                d1 += __shfl_xor(d1, 32);
+                const int su = rS > 0 ? (prowS[c] > 0 ? 0 : 1) : 0;
+                double w0 = vS[c][su][sprev][0] * (double)d0;
+                double w1 = vS[c][su][sprev][1] * (double)d1;
+                n_clamp += (w0 < 0.0) + (w1 < 0.0);
+                w0 = fmax(w0, 0.0);
+                w1 = fmax(w1, 0.0);
+                const double tot = w0 + w1;
+                const bool bad = !(tot > 0.0 && tot <= 1.79e308);
+                n_both += bad;
+                const double pp = bad ? 0.5 : w0 / tot;
+                if (eval) {
+                    s = crowS[c];
+                } else {
+                    const double u = tn_u01(urow[c]);
+                    s = (u < pp) ? 1 : -1;
+                    n_near += fabs(u - pp) < 1e-6;
+                    if (wl == 0 && grp == 0) crowS[c] = (int8_t)s;
+                }
+                int e2;
+                mant = frexp(mant * (s > 0 ? pp : 1.0 - pp), &e2);
+                mexp += e2;
+                sprev = s > 0 ? 0 : 1;
+                acc = a0.mul(vec);
+            } else if (isP) {
+                acc = a0.mul(vec);
+                *(floatx4 *)(gwg + c * gstride + (((size_t)sw * NT + mow) * 64 + lane) * 4) = acc;
+            }
+            if (isP || isS) {
+                a0 = a1;
+                const int tn = min(t + PF, Lx - 1);
+                if constexpr (PF == 3) {
+                    a1 = a2;
+                    a2.load(tile_ptr<NT, BF16>(Gph, rbase + colof(tn), sw, mow), lane);
+                } else {
+                    a1.load(tile_ptr<NT, BF16>(Gph, rbase + colof(tn), sw, mow), lane);
+                }
+                xch[gp][buf][sw][mow][lane] = acc;
+            }
+            __syncthreads();
+            if (isP && t + 1 < Lx) {
+                floatx4 y[2][NT];
+                float mx = 0.0f;
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
+                for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
                     for (int mo = 0; mo < NT; ++mo) {
-                        gc[s][mo] = gn[s][mo];
-                        gn[s][mo] = *(const floatx4 *)(gp + (((size_t)s * NT + mo) * 64 + lane) * 4);
+                        y[s2][mo] = xch[gp][buf][s2][mo][lane];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(y[s2][mo][i]));
                     }
-            }
-            d0 += __shfl_xor(d0, 16);
-            d0 += __shfl_xor(d0, 32);
-            d1 += __shfl_xor(d1, 16);
-            d1 += __shfl_xor(d1, 32);
-            const int su = r > 0 ? prow[c] : 1;
-            double v0 = sfac[c][0] * (su > 0 ? sfac[c][2] : sfac[c][3]);
-            double v1 = sfac[c][1] * (su > 0 ? sfac[c][3] : sfac[c][2]);
-            if (c > 0) {
-                v0 *= sprev > 0 ? sfac[c][4] : sfac[c][5];
-                v1 *= sprev > 0 ? sfac[c][5] : sfac[c][4];
-            }
-            double w0 = v0 * (double)d0, w1 = v1 * (double)d1;
-            if (w0 < 0.0) {
-                w0 = 0.0;
-                if (leader) atomicAdd(&counters[CNT_CLAMPS], 1ull);
-            }
-            if (w1 < 0.0) {
-                w1 = 0.0;
-                if (leader) atomicAdd(&counters[CNT_CLAMPS], 1ull);
-            }
-            const double tot = w0 + w1;
-            const bool bad = !(tot > 0.0 && tot <= 1.79e308);
-            if (bad && leader) atomicAdd(&counters[CNT_BOTH], 1ull);
-            const double p = bad ? 0.5 : w0 / tot;
-            int s;
-            if (eval) {
-                s = valid ? S[((size_t)b * Ly + r) * Lx + c] : 1;
-            } else {
-                const int i = r * Lx + c;
-                if ((i >> 2) != blk_id) {
-                    blk_id = i >> 2;
-                    blk = tn_philox(make_uint4((uint32_t)blk_id, (uint32_t)(first_id + b), step,
-                                               (inst << 2) | 0u),
-                                    k0, k1);
-                }
-                const double u = tn_u01(tn_word(blk, i & 3));
-                s = (u < p) ? 1 : -1;
-                if (leader) {
-                    S[((size_t)b * Ly + r) * Lx + c] = (int8_t)s;
-                    if (fabs(u - p) < 1e-6) atomicAdd(&counters[CNT_NEAR], 1ull);
-                }
-            }
-            if (w == 0 && grp == 0) crow[c] = (int8_t)s;
-            {
-                int e2;
-                mant = frexp(mant * (s > 0 ? p : 1.0 - p), &e2);
-                mexp += e2;
-            }
-            if (h) E -= scpl[c][0] * s;
-            if (c > 0) E -= scpl[c][1] * (double)(sprev * s);
-            if (r > 0) E -= scpl[c][2] * (double)(su * s);
-
-            const floatx4 acc = a0.mul(lam);
-            a0 = a1;
-            if constexpr (PF == 3) {
-                a1 = a2;
-                a2.load(tile_ptr<NT, BF16>(GLv, rbase + min(c + PF, Lx - 1), sw, mow), lane);
-            } else {
-                a1.load(tile_ptr<NT, BF16>(GLv, rbase + min(c + PF, Lx - 1), sw, mow), lane);
-            }
-            xch[buf][sw][mow][lane] = acc;
-            __syncthreads();
-            float mx = 0.0f;
+                mx = fmaxf(mx, __shfl_xor(mx, 16));
+                mx = fmaxf(mx, __shfl_xor(mx, 32));
+                const int e = pow2_exponent_f(mx);
+                const int su = p > 0 ? (prowP[c] > 0 ? 0 : 1) : 0;
+                const float m0 = mixP[c][su][sw][0], m1 = mixP[c][su][sw][1];
 #pragma unroll
-            for (int mo = 0; mo < NT; ++mo) {
-                lam[mo] = s > 0 ? xch[buf][0][mo][lane] : xch[buf][1][mo][lane];
+                for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(lam[mo][i]));
+                    for (int i = 0; i < 4; ++i)
+                        vec[mo][i] = ldexpf(m0 * y[0][mo][i] + m1 * y[1][mo][i], -e);
+            } else if (isS) {
+                float mx = 0.0f;
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo) {
+                    vec[mo] = s > 0 ? xch[gp][buf][0][mo][lane] : xch[gp][buf][1][mo][lane];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(vec[mo][i]));
+                }
+                mx = fmaxf(mx, __shfl_xor(mx, 16));
+                mx = fmaxf(mx, __shfl_xor(mx, 32));
+                const int e = pow2_exponent_f(mx);
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) vec[mo][i] = ldexpf(vec[mo][i], -e);
             }
             buf ^= 1;
-            mx = fmaxf(mx, __shfl_xor(mx, 16));
-            mx = fmaxf(mx, __shfl_xor(mx, 32));
-            const int e = pow2_exponent_f(mx);
-#pragma unroll
-            for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) lam[mo][i] = ldexpf(lam[mo][i], -e);
-            sprev = s;
         }
-        __syncthreads();   // row r spins and factors consumed before row r+1 overwrites
+        __syncthreads();   // the drawn row is complete in LDS
+
+        if (hasS) {
+            // energy of row p-1 (Eq. ising: field, bonds in the row, bonds to the row above)
+            if (gp == 0 && wl == 0 && grp == 0) {
+                const int8_t *cur = rows[(p + 1) & 1][n];
+                const int8_t *abv = rows[p & 1][n];
+                double e = 0.0;
+                for (int c = 0; c < Lx; ++c) {
+                    const int sc = cur[c];
+                    if (h) e -= h[rowSb + c] * sc;
+                    if (c > 0) e -= Jh[(size_t)rS * (Lx - 1) + c - 1] * (double)(cur[c - 1] * sc);
+                    if (rS > 0) e -= Jv[(size_t)(rS - 1) * Lx + c] * (double)(abv[c] * sc);
+                }
+                E += e;
+            }
+            if (!eval) {
+                for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
+                    const int nn = t / Lx, c = t % Lx;
+                    const int bb = blockIdx.x * 16 + nn;
+                    if (bb < B) S[((size_t)bb * Ly + rS) * Lx + c] = rows[(p + 1) & 1][nn][c];
+                }
+            }
+        }
     }
+    // combine the two groups' ln q parts; flush the counters
     if (leader) {
-        logq[b] = log(mant) + (double)mexp * 0.69314718055994530942;
+        lqx[gp][n][0] = mant;
+        lqx[gp][n][1] = (double)mexp;
+        if (valid) {
+            if (n_clamp) atomicAdd(&counters[CNT_CLAMPS], n_clamp);
+            if (n_both) atomicAdd(&counters[CNT_BOTH], n_both);
+            if (n_near && !eval) atomicAdd(&counters[CNT_NEAR], n_near);
+        }
+    }
+    __syncthreads();
+    if (gp == 0 && leader && valid) {
+        logq[b] = (log(lqx[0][n][0]) + log(lqx[1][n][0])) +
+                  (lqx[0][n][1] + lqx[1][n][1]) * 0.69314718055994530942;
         energy[b] = E;
     }
 }
@@ -327,7 +376,7 @@ int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
     const int blocks = (B + 15) / 16;
     const void *GR = BF16 ? (const void *)ctx->G16R : (const void *)ctx->G32R;
     const void *GL = BF16 ? (const void *)ctx->G16L : (const void *)ctx->G32L;
-    hipLaunchKernelGGL((k_sampler_mfma<NT, BF16>), dim3(blocks), dim3(128 * NT), 0, ctx->stream,
+    hipLaunchKernelGGL((k_sampler_mfma<NT, BF16>), dim3(blocks), dim3(256 * NT), 0, ctx->stream,
                        B, ctx->Lx, ctx->Ly, ctx->Jh, ctx->Jv, ctx->h, ctx->fac, GR, GL, S,
                        eval ? 1 : 0, logq, energy, g, (uint32_t)seed, (uint32_t)(seed >> 32),
                        first_id, (uint32_t)step, (uint32_t)ctx->inst, ctx->counters);
@@ -354,7 +403,7 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t f
     if (batch == 0) return TN_OK;
     if (ctx->Lx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     const int blocks = (batch + 15) / 16;
-    const size_t need = (size_t)blocks * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
+    const size_t need = (size_t)blocks * 2 * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
     int rc;
     if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, need))) return rc;
     float *g = (float *)ctx->gscr;
