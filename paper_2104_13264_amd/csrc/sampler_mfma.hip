@@ -96,10 +96,27 @@ __device__ __forceinline__ const void *tile_ptr(const void *G, size_t site, int 
     return BF16 ? (const void *)((const uint16_t *)G + off) : (const void *)((const float *)G + off);
 }
 
-// Columns of the environment tiles are prefetched PF columns ahead (two for
-// the fp32 tiles of the largest bonds, to stay within the register file).
+// Columns of the environment tiles (and, for the drawing group, of the stored
+// y_s tiles) are kept in a ring of PF registers sets: the set used at column
+// step t is refilled with step t + PF.  The step loop is unrolled by PF so that
+// the ring is indexed statically and no register copy waits for a load.
 template <int NT, bool BF16>
 constexpr int prefetch_depth() { return (NT <= 2 || BF16) ? 3 : 2; }
+
+// Sum (or max) over the four 16-lane rows of a wavefront, the same result in
+// every lane: the 32-lane and 16-lane swaps of gfx950 (VALU, no LDS traffic).
+__device__ __forceinline__ float rows4_sum(float v) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+__device__ __forceinline__ float rows4_max(float v) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));
+}
 
 // Snake order: row r is drawn left to right when r is even, right to left
 // when odd.  Before a row is drawn, the environments of its free columns are
@@ -110,6 +127,9 @@ constexpr int prefetch_depth() { return (NT <= 2 || BF16) ? 3 : 2; }
 // spin of a column is in LDS before the environment sweep of the row below
 // needs it.  A rightward phase multiplies by G^T (GL tiles), a leftward one by
 // G (GR tiles), for both groups.
+//
+// LDS arrays indexed by proposal keep the proposal index innermost, so the 16
+// proposals of a wavefront touch 16 consecutive entries (no bank conflicts).
 template <int NT, bool BF16>
 __global__ void __launch_bounds__(256 * NT)
 k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
@@ -120,6 +140,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                float *__restrict__ gscr, uint32_t k0, uint32_t k1, uint64_t first_id,
                uint32_t step, uint32_t inst, unsigned long long *__restrict__ counters) {
     constexpr int NW = 2 * NT;                        // waves per group
+    constexpr int PF = prefetch_depth<NT, BF16>();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int gp = w / NW, wl = w % NW;
     const int sw = wl / NT, mow = wl % NT;
@@ -129,8 +150,8 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
     const bool leader = (wl == 0 && grp == 0);        // one lane per proposal per group
 
     __shared__ floatx4 xch[2][2][2][NT][64];         // [group][buf][s][mo][lane]
-    __shared__ int8_t rows[2][16][TN_MAX_LX];         // spins by row parity
-    __shared__ uint32_t uni[2][16][TN_MAX_LX];        // random words by row parity
+    __shared__ int8_t rows[2][TN_MAX_LX][16];         // spins by row parity
+    __shared__ uint32_t uni[TN_MAX_LX][16];           // random words of the drawn row
     __shared__ float mixP[TN_MAX_LX][2][2][2];        // [c][s_up][s_w][s]
     __shared__ double vS[TN_MAX_LX][2][2][2];         // [c][s_up][s_prev][s]
     __shared__ double lqx[2][16][2];                  // ln q parts per group
@@ -169,21 +190,21 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 vS[c][su][x][s] = f[s] * f[2 + (su ^ s)] * hf;
             }
         }
-        if (hasP && !eval) {   // random words of row p (drawn in the next phase)
+        if (hasS && !eval) {   // random words of row p-1
             for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
-                const int nn = t / Lx, c = t % Lx;
-                const int i = p * Lx + c;
+                const int c = t >> 4, nn = t & 15;
+                const int i = rS * Lx + c;
                 const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2),
                                                      (uint32_t)(first_id + blockIdx.x * 16 + nn),
                                                      step, (inst << 2) | 0u), k0, k1);
-                uni[p & 1][nn][c] = tn_word(x, i & 3);
+                uni[c][nn] = tn_word(x, i & 3);
             }
         }
         if (hasS && eval) {   // the given spins of row p-1
             for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                 const int nn = t / Lx, c = t % Lx;
                 const int bb = blockIdx.x * 16 + nn;
-                rows[rS & 1][nn][c] = bb < B ? S[((size_t)bb * Ly + rS) * Lx + c] : (int8_t)1;
+                rows[rS & 1][c][nn] = bb < B ? S[((size_t)bb * Ly + rS) * Lx + c] : (int8_t)1;
             }
         }
         __syncthreads();
@@ -194,62 +215,57 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) vec[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         if (grp == 0) vec[0][0] = 1.0f;
-        ATile<NT, BF16> a0, a1, a2;
-        constexpr int PF = prefetch_depth<NT, BF16>();
         const size_t rbase = isP ? rowP : rowSb;
         auto colof = [&](int t) { return rightward ? t : Lx - 1 - t; };
+        auto gptr = [&](int c, int s2, int mo) {
+            return (const floatx4 *)(gwg + c * gstride + (((size_t)s2 * NT + mo) * 64 + lane) * 4);
+        };
+        ATile<NT, BF16> a[PF];
+        floatx4 g[PF][2][NT];   // stored y_s tiles of the drawn row (drawing group)
         if (isP || isS) {
-            a0.load(tile_ptr<NT, BF16>(Gph, rbase + colof(0), sw, mow), lane);
-            a1.load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(1, Lx - 1)), sw, mow), lane);
-            if constexpr (PF == 3)
-                a2.load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(2, Lx - 1)), sw, mow), lane);
+#pragma unroll
+            for (int k = 0; k < PF; ++k)
+                a[k].load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(k, Lx - 1)), sw, mow), lane);
         }
-        floatx4 gc[2][NT], gn[2][NT];
         if (isS) {
 #pragma unroll
-            for (int s2 = 0; s2 < 2; ++s2)
+            for (int k = 0; k < PF; ++k)
 #pragma unroll
-                for (int mo = 0; mo < NT; ++mo) {
-                    gc[s2][mo] = *(const floatx4 *)(gwg + colof(0) * gstride +
-                                                    (((size_t)s2 * NT + mo) * 64 + lane) * 4);
-                    gn[s2][mo] = *(const floatx4 *)(gwg + colof(min(1, Lx - 1)) * gstride +
-                                                    (((size_t)s2 * NT + mo) * 64 + lane) * 4);
-                }
+                for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo) g[k][s2][mo] = *gptr(colof(min(k, Lx - 1)), s2, mo);
         }
-        const int8_t *prowP = rows[(p + 1) & 1][n];     // row p-1 (above row p)
-        const int8_t *prowS = rows[p & 1][n];           // row p-2 (above row p-1)
-        int8_t *crowS = rows[(p + 1) & 1][n];           // row p-1, written by the drawing
-        const uint32_t *urow = uni[(p + 1) & 1][n];     // words of row p-1
-        int sprev = 0;   // index of the previous spin (0: +1, 1: -1); unused at t = 0
+        const int8_t(*prowP)[16] = rows[(p + 1) & 1];   // row p-1 (above row p)
+        const int8_t(*prowS)[16] = rows[p & 1];         // row p-2 (above row p-1)
+        int8_t(*crowS)[16] = rows[(p + 1) & 1];         // row p-1, written by the drawing
 
-        for (int t = 0; t < Lx; ++t) {
-            const int c = colof(t);
-            int s = 1;
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (isS) {
+        // One loop per role over whole turns of the ring, then the remaining
+        // steps; the loads are unconditional (the last columns re-read the final
+        // one), so that the compiler can count the loads in flight and waits
+        // only for the ring entry it uses.
+        if (isS) {
+            int sprev = 0;   // index of the previous spin (0: +1, 1: -1); unused at t = 0
+            auto stepS = [&](int k, int t) {
+                const int c = colof(t);
+                const int cn = colof(min(t + PF, Lx - 1));
+                // the product with G_c(s_w) does not depend on the draw: issue it first
+                const floatx4 acc = a[k].mul(vec);
                 float d0 = 0.0f, d1 = 0.0f;
 #pragma unroll
                 for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        d0 = fmaf(vec[mo][i], gc[0][mo][i], d0);
-                        d1 = fmaf(vec[mo][i], gc[1][mo][i], d1);
+                        d0 = fmaf(vec[mo][i], g[k][0][mo][i], d0);
+                        d1 = fmaf(vec[mo][i], g[k][1][mo][i], d1);
                     }
-                {
-                    const float *gp2 = gwg + colof(min(t + 2, Lx - 1)) * gstride;
 #pragma unroll
-                    for (int s2 = 0; s2 < 2; ++s2)
+                for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-                        for (int mo = 0; mo < NT; ++mo) {
-                            gc[s2][mo] = gn[s2][mo];
-                            gn[s2][mo] = *(const floatx4 *)(gp2 + (((size_t)s2 * NT + mo) * 64 + lane) * 4);
-                        }
-                }
-                d0 += __shfl_xor(d0, 16);
-                d0 += __shfl_xor(d0, 32);
-                d1 += __shfl_xor(d1, 16);
-                d1 += __shfl_xor(d1, 32);
-                const int su = rS > 0 ? (prowS[c] > 0 ? 0 : 1) : 0;
+                    for (int mo = 0; mo < NT; ++mo) g[k][s2][mo] = *gptr(cn, s2, mo);
+                a[k].load(tile_ptr<NT, BF16>(Gph, rbase + cn, sw, mow), lane);
+                d0 = rows4_sum(d0);
+                d1 = rows4_sum(d1);
+                const int su = rS > 0 ? (prowS[c][n] > 0 ? 0 : 1) : 0;
                 double w0 = vS[c][su][sprev][0] * (double)d0;
                 double w1 = vS[c][su][sprev][1] * (double)d1;
                 n_clamp += (w0 < 0.0) + (w1 < 0.0);
@@ -259,57 +275,21 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 const bool bad = !(tot > 0.0 && tot <= 1.79e308);
                 n_both += bad;
                 const double pp = bad ? 0.5 : w0 / tot;
+                int s;
                 if (eval) {
-                    s = crowS[c];
+                    s = crowS[c][n];
                 } else {
-                    const double u = tn_u01(urow[c]);
+                    const double u = tn_u01(uni[c][n]);
                     s = (u < pp) ? 1 : -1;
                     n_near += fabs(u - pp) < 1e-6;
-                    if (wl == 0 && grp == 0) crowS[c] = (int8_t)s;
+                    if (leader) crowS[c][n] = (int8_t)s;
                 }
                 int e2;
                 mant = frexp(mant * (s > 0 ? pp : 1.0 - pp), &e2);
                 mexp += e2;
                 sprev = s > 0 ? 0 : 1;
-                acc = a0.mul(vec);
-            } else if (isP) {
-                acc = a0.mul(vec);
-                *(floatx4 *)(gwg + c * gstride + (((size_t)sw * NT + mow) * 64 + lane) * 4) = acc;
-            }
-            if (isP || isS) {
-                a0 = a1;
-                const int tn = min(t + PF, Lx - 1);
-                if constexpr (PF == 3) {
-                    a1 = a2;
-                    a2.load(tile_ptr<NT, BF16>(Gph, rbase + colof(tn), sw, mow), lane);
-                } else {
-                    a1.load(tile_ptr<NT, BF16>(Gph, rbase + colof(tn), sw, mow), lane);
-                }
                 xch[gp][buf][sw][mow][lane] = acc;
-            }
-            __syncthreads();
-            if (isP && t + 1 < Lx) {
-                floatx4 y[2][NT];
-                float mx = 0.0f;
-#pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-                    for (int mo = 0; mo < NT; ++mo) {
-                        y[s2][mo] = xch[gp][buf][s2][mo][lane];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(y[s2][mo][i]));
-                    }
-                mx = fmaxf(mx, __shfl_xor(mx, 16));
-                mx = fmaxf(mx, __shfl_xor(mx, 32));
-                const int e = pow2_exponent_f(mx);
-                const int su = p > 0 ? (prowP[c] > 0 ? 0 : 1) : 0;
-                const float m0 = mixP[c][su][sw][0], m1 = mixP[c][su][sw][1];
-#pragma unroll
-                for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        vec[mo][i] = ldexpf(m0 * y[0][mo][i] + m1 * y[1][mo][i], -e);
-            } else if (isS) {
+                __syncthreads();
                 float mx = 0.0f;
 #pragma unroll
                 for (int mo = 0; mo < NT; ++mo) {
@@ -317,29 +297,78 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
 #pragma unroll
                     for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(vec[mo][i]));
                 }
-                mx = fmaxf(mx, __shfl_xor(mx, 16));
-                mx = fmaxf(mx, __shfl_xor(mx, 32));
-                const int e = pow2_exponent_f(mx);
+                const int e = pow2_exponent_f(rows4_max(mx));
 #pragma unroll
                 for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) vec[mo][i] = ldexpf(vec[mo][i], -e);
+                buf ^= 1;
+            };
+            int t0 = 0;
+            for (; t0 + PF <= Lx; t0 += PF) {
+#pragma unroll
+                for (int k = 0; k < PF; ++k) stepS(k, t0 + k);
             }
-            buf ^= 1;
+#pragma unroll
+            for (int k = 0; k < PF - 1; ++k)
+                if (t0 + k < Lx) stepS(k, t0 + k);
+        } else if (isP) {
+            auto stepP = [&](int k, int t) {
+                const int c = colof(t);
+                const floatx4 acc = a[k].mul(vec);
+                *(floatx4 *)gptr(c, sw, mow) = acc;
+                a[k].load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(t + PF, Lx - 1)), sw, mow), lane);
+                xch[gp][buf][sw][mow][lane] = acc;
+                __syncthreads();
+                if (t + 1 < Lx) {
+                    floatx4 y[2][NT];
+                    float mx = 0.0f;
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                        for (int mo = 0; mo < NT; ++mo) {
+                            y[s2][mo] = xch[gp][buf][s2][mo][lane];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(y[s2][mo][i]));
+                        }
+                    const int e = pow2_exponent_f(rows4_max(mx));
+                    const int su = p > 0 ? (prowP[c][n] > 0 ? 0 : 1) : 0;
+                    const float m0 = mixP[c][su][sw][0], m1 = mixP[c][su][sw][1];
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            vec[mo][i] = ldexpf(m0 * y[0][mo][i] + m1 * y[1][mo][i], -e);
+                }
+                buf ^= 1;
+            };
+            int t0 = 0;
+            for (; t0 + PF <= Lx; t0 += PF) {
+#pragma unroll
+                for (int k = 0; k < PF; ++k) stepP(k, t0 + k);
+            }
+#pragma unroll
+            for (int k = 0; k < PF - 1; ++k)
+                if (t0 + k < Lx) stepP(k, t0 + k);
+        } else {   // idle group (first and last phase): keep the barrier count
+            for (int t = 0; t < Lx; ++t) {
+                __syncthreads();
+                buf ^= 1;
+            }
         }
         __syncthreads();   // the drawn row is complete in LDS
 
         if (hasS) {
             // energy of row p-1 (Eq. ising: field, bonds in the row, bonds to the row above)
-            if (gp == 0 && wl == 0 && grp == 0) {
-                const int8_t *cur = rows[(p + 1) & 1][n];
-                const int8_t *abv = rows[p & 1][n];
+            if (gp == 0 && leader) {
+                const int8_t(*cur)[16] = rows[(p + 1) & 1];
+                const int8_t(*abv)[16] = rows[p & 1];
                 double e = 0.0;
                 for (int c = 0; c < Lx; ++c) {
-                    const int sc = cur[c];
+                    const int sc = cur[c][n];
                     if (h) e -= h[rowSb + c] * sc;
-                    if (c > 0) e -= Jh[(size_t)rS * (Lx - 1) + c - 1] * (double)(cur[c - 1] * sc);
-                    if (rS > 0) e -= Jv[(size_t)(rS - 1) * Lx + c] * (double)(abv[c] * sc);
+                    if (c > 0) e -= Jh[(size_t)rS * (Lx - 1) + c - 1] * (double)(cur[c - 1][n] * sc);
+                    if (rS > 0) e -= Jv[(size_t)(rS - 1) * Lx + c] * (double)(abv[c][n] * sc);
                 }
                 E += e;
             }
@@ -347,7 +376,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                     const int nn = t / Lx, c = t % Lx;
                     const int bb = blockIdx.x * 16 + nn;
-                    if (bb < B) S[((size_t)bb * Ly + rS) * Lx + c] = rows[(p + 1) & 1][nn][c];
+                    if (bb < B) S[((size_t)bb * Ly + rS) * Lx + c] = rows[(p + 1) & 1][c][nn];
                 }
             }
         }
