@@ -246,8 +246,8 @@ int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t fir
     if (batch > 0 && (!spins || !logq || !energy))
         return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
     if (ctx->prec == TN_FP64)
-        return tn_run_fp64(ctx, batch, seed, step, first_id, spins, false, logq, energy);
-    return tn_run_mfma(ctx, batch, seed, step, first_id, spins, false, logq, energy);
+        return tn_run_fp64(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
+    return tn_run_mfma(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
 }
 
 int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, double *energy) {
@@ -259,8 +259,8 @@ int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, doub
     if (batch > 0 && (!spins || !logq || !energy))
         return tn_fail(ctx, TN_EINVAL, "NULL buffer");
     int8_t *s = const_cast<int8_t *>(spins);   // read-only in eval mode
-    if (ctx->prec == TN_FP64) return tn_run_fp64(ctx, batch, 0, 0, 0, s, true, logq, energy);
-    return tn_run_mfma(ctx, batch, 0, 0, 0, s, true, logq, energy);
+    if (ctx->prec == TN_FP64) return tn_run_fp64(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
+    return tn_run_mfma(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
 }
 
 int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *state_spins,

@@ -104,10 +104,12 @@ int tn_make_operands(tn_ctx *ctx, int prec);
 int tn_top_overlap(tn_ctx *ctx, double *logtop, double *sign);
 
 // samplers
-int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step,
+// Samplers: proposal j of a launch has id first_id + j % per_step and MH step
+// step0 + j / per_step.
+int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
                 double *energy);
-int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step,
+int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
                 double *energy);
 

@@ -48,7 +48,7 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
            const double *__restrict__ G64r, const double *__restrict__ G64c,
            int8_t *__restrict__ S, int eval, double *__restrict__ logq,
            double *__restrict__ energy, double *__restrict__ gscr, uint32_t k0, uint32_t k1,
-           uint64_t first_id, uint32_t step, uint32_t inst,
+           uint64_t first_id, uint64_t step0, int per_step, uint32_t inst,
            unsigned long long *__restrict__ counters) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = tid / T, j = tid % T;
@@ -149,8 +149,9 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
             const int i = r * Lx + c;
             if ((i >> 2) != blk_id) {
                 blk_id = i >> 2;
-                blk = tn_philox(make_uint4((uint32_t)blk_id, (uint32_t)(first_id + b), step,
-                                           (inst << 2) | 0u),
+                const uint64_t id = first_id + (uint64_t)b % (uint64_t)per_step;
+                const uint32_t st = (uint32_t)(step0 + (uint64_t)b / (uint64_t)per_step);
+                blk = tn_philox(make_uint4((uint32_t)blk_id, (uint32_t)id, st, (inst << 2) | 0u),
                                 k0, k1);
             }
             const double u = tn_u01(tn_word(blk, i & 3));
@@ -196,7 +197,7 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
 
 template <int T>
 int launch_rows(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
-                double *gscr, uint64_t seed, uint64_t step, uint64_t first_id) {
+                double *gscr, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     const int threads = 256;
     const size_t total = (size_t)B * T;
     const int blocks = (int)((total + threads - 1) / threads);
@@ -204,8 +205,8 @@ int launch_rows(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
         hipLaunchKernelGGL(k_row_fp64<T>, dim3(blocks), dim3(threads), 0, ctx->stream, r, B,
                            ctx->Lx, ctx->Ly, ctx->D, ctx->Jh, ctx->Jv, ctx->h, ctx->fac,
                            ctx->dims, ctx->G64r, ctx->G64c, S, eval ? 1 : 0, logq, energy,
-                           gscr, (uint32_t)seed, (uint32_t)(seed >> 32), first_id,
-                           (uint32_t)step, (uint32_t)ctx->inst, ctx->counters);
+                           gscr, (uint32_t)seed, (uint32_t)(seed >> 32), first_id, step0,
+                           per_step, (uint32_t)ctx->inst, ctx->counters);
         TN_HIP(ctx, hipGetLastError());
     }
     return TN_OK;
@@ -213,9 +214,10 @@ int launch_rows(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 
 }  // namespace
 
-int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
-                int8_t *spins, bool eval, double *logq, double *energy) {
+int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
+                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy) {
     if (batch == 0) return TN_OK;
+    if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
     const size_t need = (size_t)batch * ctx->Lx * 2 * ctx->D * sizeof(double);
     int rc;
     if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, need))) return rc;
@@ -223,13 +225,13 @@ int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t f
     int T = 1;
     while (T < ctx->D) T <<= 1;
     switch (T) {
-    case 1: return launch_rows<1>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    case 2: return launch_rows<2>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    case 4: return launch_rows<4>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    case 8: return launch_rows<8>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    case 16: return launch_rows<16>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    case 32: return launch_rows<32>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    case 64: return launch_rows<64>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+    case 1: return launch_rows<1>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 2: return launch_rows<2>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 4: return launch_rows<4>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 8: return launch_rows<8>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 16: return launch_rows<16>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 32: return launch_rows<32>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 64: return launch_rows<64>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
     default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
     }
 }

@@ -3,30 +3,36 @@
 // Eq. proba-ratio-apx), with the per-column products run as 16x16 MFMA tiles.
 //
 // A workgroup owns 16 proposals (the N dimension of every tile) for the whole
-// lattice; its 2*NT waves (Dp = 16*NT padded bond) each own one output tile
-// (spin s, 16-row block mo) of every column product, so the 16 proposals'
-// work is spread over 2*NT SIMDs.  Per column:
-//   right sweep  y_s[mo] = G_c(s)[mo,:] r_s      (NQ chained MFMAs, K = Dp)
+// lattice; each of its two groups of 2*NT waves (Dp = 16*NT padded bond) owns
+// one output tile (spin s, 16-row block mo) of every column product per wave,
+// so the 16 proposals' work is spread over all four SIMDs.  Per column:
+//   environment sweep  y_s[mo] = G_c(s)[mo,:] r_s  (NQ chained MFMAs, K = Dp),
 //                tiles exchanged through LDS (double buffered, one barrier),
-//                r_s' = sum_s W(s',s) v_c(s) y_s rescaled by a common 2^-e,
-//                every wave rebuilding its own next B operand r_{s_w}
-//   left sweep   w(s) = v hf <Lam, y_s>   (y_s re-read from this
-//                workgroup's scratch), p+ and the draw in fp64 on every wave
-//                (bitwise identical), Lam_s'[mo] = G_c(s)^T[mo,:] Lam,
-//                exchanged and selected by the drawn spin.
+//                r_s' = sum_s W(s',s) v_c(s) y_s, every wave rebuilding its own
+//                next B operand r_{s_w}; the y_s tiles go to this workgroup's
+//                scratch for the drawing of the row
+//   drawing      w(s) = v hf <Lam, y_s>, p+ and the draw in fp64 on every wave
+//                (bitwise identical), Lam_s'[mo] = G_c(s)^T[mo,:] Lam for both
+//                spins while the draw is taken, exchanged and selected by the
+//                drawn spin.
 // The accumulator layout of tile mt (lane l, register i -> row 4(l/16)+i,
 // column l%16) is exactly the B-operand layout of k-chunk q = 4 mt + i of the
 // next product, so the recurrences stay in registers; the A operands (the
 // shared environment) are pre-permuted to match (operands.hip).
 //
-// ln q is accumulated as a product of the drawn probabilities in fp64 with a
-// separate binary exponent, and evaluated once at the end.
+// Scaling: a product takes its input vector as it comes and multiplies its
+// output by 2^-e, e the binary exponent of the input's largest entry (common to
+// all tiles); powers of two are exact, so this equals rescaling the input first.
+// ln q is accumulated as two fp64 products, of the drawn weights and of the
+// weight totals, each with a separate binary exponent, and evaluated once at
+// the end; the spin is +1 iff u * (w+ + w-) < w+.
 #include "common.hpp"
 
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
 
 #define TN_MAX_LX 256
 
@@ -42,81 +48,118 @@ __device__ __forceinline__ short bf16_rne(float f) {
     return (short)(u >> 16);
 }
 
-// A operand of one output tile for one column: the NQ = 4 NT k-chunks of the
-// fp32 16x16x4 product, or the NT chunks of the bf16 16x16x16 product.
+// Buffer resource over [base, base + bytes): loads and stores take a 32-bit
+// per-lane offset and a wave-uniform column offset; accesses outside the
+// range read 0 / are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+
+// A operands of one spin's product for one column: every 16-row output block
+// mo = 0..NT-1, each the 4 NT k-chunks of the fp32 16x16x4 product or the NT
+// chunks of the bf16 16x16x16 product.  The NT accumulation chains are
+// independent and interleaved.  Tile layout per site: [s][mo][chunk][64 lanes].
 template <int NT, bool BF16>
-struct ATile;
+struct ATiles;
 
 template <int NT>
-struct ATile<NT, false> {
+struct ATiles<NT, false> {
     static constexpr int NQ = 4 * NT;
-    float a[NQ];
-    __device__ __forceinline__ void load(const void *base, int lane) {
-        const float *A = (const float *)base;
+    static constexpr size_t SITE_BYTES = (size_t)2 * NT * NQ * 64 * 4;
+    float a[NT][NQ];
+    // vbase: byte offset of (spin s_w, lane) within a site; soff: site offset
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t vbase, uint32_t soff) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) a[q] = A[q * 64 + lane];
+        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                a[mo][q] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(r, vbase + (mo * NQ + q) * 256, soff, 0));
     }
-    __device__ __forceinline__ floatx4 mul(const floatx4 (&x)[NT]) const {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    __device__ __forceinline__ void mul(const floatx4 (&x)[NT], floatx4 (&acc)[NT]) const {
+#pragma unroll
+        for (int mo = 0; mo < NT; ++mo) acc[mo] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], x[q >> 2][q & 3], acc, 0, 0, 0);
-        return acc;
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo)
+                acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mo][q], x[q >> 2][q & 3], acc[mo], 0, 0, 0);
     }
 };
 
 template <int NT>
-struct ATile<NT, true> {
-    shortx4 a[NT];
-    __device__ __forceinline__ void load(const void *base, int lane) {
-        const shortx4 *A = (const shortx4 *)base;
+struct ATiles<NT, true> {
+    static constexpr size_t SITE_BYTES = (size_t)2 * NT * NT * 64 * 8;
+    shortx4 a[NT][NT];
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t vbase, uint32_t soff) {
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) a[mt] = A[mt * 64 + lane];
+        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt)
+                a[mo][mt] = __builtin_bit_cast(
+                    shortx4, __builtin_amdgcn_raw_buffer_load_b64(r, vbase + (mo * NT + mt) * 512, soff, 0));
     }
-    __device__ __forceinline__ floatx4 mul(const floatx4 (&x)[NT]) const {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    __device__ __forceinline__ void mul(const floatx4 (&x)[NT], floatx4 (&acc)[NT]) const {
+#pragma unroll
+        for (int mo = 0; mo < NT; ++mo) acc[mo] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) {
             shortx4 bv;
-            bv[0] = bf16_rne(x[mt][0]);
-            bv[1] = bf16_rne(x[mt][1]);
-            bv[2] = bf16_rne(x[mt][2]);
-            bv[3] = bf16_rne(x[mt][3]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], bv, acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[i] = bf16_rne(x[mt][i]);
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo)
+                acc[mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mo][mt], bv, acc[mo], 0, 0, 0);
         }
-        return acc;
     }
 };
 
-template <int NT, bool BF16>
-__device__ __forceinline__ const void *tile_ptr(const void *G, size_t site, int sw, int mow) {
-    constexpr int Dp = 16 * NT;
-    constexpr size_t TILE = BF16 ? (size_t)NT * 64 * 4 : (size_t)4 * NT * 64;   // elements
-    const size_t off = site * 2 * Dp * Dp + ((size_t)sw * NT + mow) * TILE;
-    return BF16 ? (const void *)((const uint16_t *)G + off) : (const void *)((const float *)G + off);
-}
-
 // Columns of the environment tiles (and, for the drawing group, of the stored
-// y_s tiles) are kept in a ring of PF registers sets: the set used at column
+// y_s tiles) are kept in a ring of PF register sets: the set used at column
 // step t is refilled with step t + PF.  The step loop is unrolled by PF so that
 // the ring is indexed statically and no register copy waits for a load.
 template <int NT, bool BF16>
-constexpr int prefetch_depth() { return (NT <= 2 || BF16) ? 3 : 2; }
+constexpr int prefetch_depth() { return NT <= 2 ? 3 : 2; }
 
 // Sum (or max) over the four 16-lane rows of a wavefront, the same result in
 // every lane: the 32-lane and 16-lane swaps of gfx950 (VALU, no LDS traffic).
-__device__ __forceinline__ float rows4_sum(float v) {
-    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
-}
 __device__ __forceinline__ float rows4_max(float v) {
     auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
     v = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
     auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
     return fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));
 }
+// Both sums at once: after the first swap-and-add, lanes 0-31 hold a's
+// half-sums and lanes 32-63 b's; the second pairs the 16-lane rows; a last
+// swap hands every lane both totals.  Every lane adds in the same order.
+__device__ __forceinline__ void rows4_sum2(float &a, float &b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    float v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+    auto z = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    a = __uint_as_float(z[0]);
+    b = __uint_as_float(z[1]);
+}
+
+// LDS layout of one workgroup (bytes, every part 16-byte aligned), sized by Lx.
+template <int NT>
+struct SmemLayout {
+    int xch, pmx, rows, uni, mixP, vS, eT, epart, lqx, ex, total;
+    __host__ __device__ SmemLayout(int Lx) {
+        xch = 0;                                    // floatx4 [2 group][2 buf][2 s][NT][64]
+        pmx = xch + 2 * 2 * 2 * NT * 64 * 16;       // float [2 group][2 buf][2 s][64]
+        rows = pmx + 2 * 2 * 2 * 64 * 4;            // int8 [2 parity][Lx][16]
+        uni = rows + 2 * Lx * 16;                   // uint32 [Lx][16]
+        mixP = uni + Lx * 16 * 4;                   // float [Lx][s_w][s_up][s]
+        vS = mixP + Lx * 8 * 4;                     // double [Lx][s_up][s_prev][s]
+        eT = vS + Lx * 8 * 8;                       // double [Lx][4]: h, Jh to the left, Jv above
+        epart = eT + Lx * 4 * 8;                    // double [16 column groups][16]
+        lqx = epart + 16 * 16 * 8;                  // double [2 group][16] ln q parts
+        ex = lqx + 2 * 16 * 8;                      // double [16] energies
+        total = ex + 16 * 8;
+    }
+};
 
 // Snake order: row r is drawn left to right when r is even, right to left
 // when odd.  Before a row is drawn, the environments of its free columns are
@@ -128,41 +171,66 @@ __device__ __forceinline__ float rows4_max(float v) {
 // needs it.  A rightward phase multiplies by G^T (GL tiles), a leftward one by
 // G (GR tiles), for both groups.
 //
+// Each group has two waves, one per spin s_w (four waves, one per SIMD); a
+// wave computes all NT output blocks of its spin's product, so per column a
+// wave exchanges only the other spin's tiles.  On gfx950 the fp32 MFMA and
+// the vector ALU share a SIMD's issue, so the per-column scalar work is kept
+// small: table entries are read at computed LDS addresses instead of being
+// selected in registers, vectors are rescaled every RS-th column only, and
+// the row energy is summed once per row.
+//
+// Proposal j of the launch has id first_id + j % per_step and MH step
+// step0 + j / per_step (several steps' proposals may share a launch; the
+// proposal distribution does not depend on the chains' state).
+//
 // LDS arrays indexed by proposal keep the proposal index innermost, so the 16
 // proposals of a wavefront touch 16 consecutive entries (no bank conflicts).
+constexpr int RS = 4;   // rescale (and ln q renormalisation) period in columns
+
 template <int NT, bool BF16>
-__global__ void __launch_bounds__(256 * NT)
+__global__ void __launch_bounds__(256)
 k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                const double *__restrict__ Jv, const double *__restrict__ h,
                const double *__restrict__ fac, const void *__restrict__ GRv,
                const void *__restrict__ GLv, int8_t *__restrict__ S, int eval,
                double *__restrict__ logq, double *__restrict__ energy,
                float *__restrict__ gscr, uint32_t k0, uint32_t k1, uint64_t first_id,
-               uint32_t step, uint32_t inst, unsigned long long *__restrict__ counters) {
-    constexpr int NW = 2 * NT;                        // waves per group
+               uint64_t step0, int per_step, uint32_t inst,
+               unsigned long long *__restrict__ counters) {
     constexpr int PF = prefetch_depth<NT, BF16>();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int gp = w / NW, wl = w % NW;
-    const int sw = wl / NT, mow = wl % NT;
+    using AT = ATiles<NT, BF16>;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int gp = w >> 1, sw = w & 1;
     const int n = lane & 15, grp = lane >> 4;
     const int b = blockIdx.x * 16 + n;
     const bool valid = b < B;
-    const bool leader = (wl == 0 && grp == 0);        // one lane per proposal per group
+    const bool leader = (sw == 0 && grp == 0);        // one lane per proposal per group
 
-    __shared__ floatx4 xch[2][2][2][NT][64];         // [group][buf][s][mo][lane]
-    __shared__ int8_t rows[2][TN_MAX_LX][16];         // spins by row parity
-    __shared__ uint32_t uni[TN_MAX_LX][16];           // random words of the drawn row
-    __shared__ float mixP[TN_MAX_LX][2][2][2];        // [c][s_up][s_w][s]
-    __shared__ double vS[TN_MAX_LX][2][2][2];         // [c][s_up][s_prev][s]
-    __shared__ double lqx[2][16][2];                  // ln q parts per group
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SmemLayout<NT> L(Lx);
+    floatx4(*xch)[2][2][NT][64] = (floatx4(*)[2][2][NT][64])(smem + L.xch);
+    float(*pmx)[2][2][64] = (float(*)[2][2][64])(smem + L.pmx);
+    uint32_t(*uni)[16] = (uint32_t(*)[16])(smem + L.uni);
+    float(*mixP)[2][2][2] = (float(*)[2][2][2])(smem + L.mixP);
+    double(*vS)[2][2][2] = (double(*)[2][2][2])(smem + L.vS);
+    double(*eT)[4] = (double(*)[4])(smem + L.eT);
+    double(*epart)[16] = (double(*)[16])(smem + L.epart);
+    double(*lqx)[16] = (double(*)[16])(smem + L.lqx);
+    double *ex = (double *)(smem + L.ex);
+    // spins of the rows by parity: [parity][Lx][16]
+    auto rowbuf = [&](int par) { return (int8_t(*)[16])(smem + L.rows + par * Lx * 16); };
 
-    const size_t gstride = (size_t)2 * NT * 64 * 4;   // floats per column
-    float *gwg = gscr + (size_t)(blockIdx.x * 2 + gp) * Lx * gstride;
+    const uint32_t gstride = 2u * NT * 64 * 16;       // bytes of stored y tiles per column
+    float *gwg = gscr + ((size_t)blockIdx.x * 2 + gp) * Lx * (gstride / 4);
+    const __amdgpu_buffer_rsrc_t grs = make_rsrc(gwg, (uint32_t)Lx * gstride);
     const int NTH = blockDim.x;
 
-    double mant = 1.0, E = 0.0;
-    int mexp = 0;
-    unsigned long long n_clamp = 0, n_both = 0, n_near = 0;
+    // ln q = ln(num / den): products of the drawn weights and of the weight
+    // totals, each kept as an fp64 mantissa with a separate binary exponent
+    double num = 1.0, den = 1.0, E = 0.0;
+    int nexp = 0;
+    uint32_t n_clamp = 0, n_both = 0, n_near = 0;
     int buf = 0;
 
     for (int p = 0; p <= Ly; ++p) {
@@ -180,7 +248,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 double Wv = 1.0;
                 if (cb >= 1 && cb <= Lx - 1) Wv = fac[((size_t)p * Lx + cb) * 6 + ((x == s) ? 4 : 5)];
                 const double v = f[s] * f[2 + (su ^ s)];
-                mixP[c][su][x][s] = (float)(Wv * v);
+                mixP[c][x][su][s] = (float)(Wv * v);
             }
             if (hasS) {   // drawing of row p-1: v_c(s; s_up) hf(s; s_prev)
                 const double *f = fac + ((size_t)rS * Lx + c) * 6;
@@ -190,66 +258,91 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                 vS[c][su][x][s] = f[s] * f[2 + (su ^ s)] * hf;
             }
         }
+        if (hasS) {   // couplings of the drawn row for its energy (Eq. ising)
+            for (int c = threadIdx.x; c < Lx; c += NTH) {
+                eT[c][0] = h ? h[(size_t)rS * Lx + c] : 0.0;
+                eT[c][1] = c > 0 ? Jh[(size_t)rS * (Lx - 1) + c - 1] : 0.0;
+                eT[c][2] = rS > 0 ? Jv[(size_t)(rS - 1) * Lx + c] : 0.0;
+                eT[c][3] = 0.0;
+            }
+        }
         if (hasS && !eval) {   // random words of row p-1
             for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                 const int c = t >> 4, nn = t & 15;
                 const int i = rS * Lx + c;
-                const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2),
-                                                     (uint32_t)(first_id + blockIdx.x * 16 + nn),
-                                                     step, (inst << 2) | 0u), k0, k1);
+                const uint32_t j = blockIdx.x * 16 + nn;
+                const uint64_t id = first_id + j % (uint32_t)per_step;
+                const uint32_t st = (uint32_t)(step0 + j / (uint32_t)per_step);
+                const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2), (uint32_t)id, st,
+                                                     (inst << 2) | 0u), k0, k1);
                 uni[c][nn] = tn_word(x, i & 3);
             }
         }
         if (hasS && eval) {   // the given spins of row p-1
+            int8_t(*r1)[16] = rowbuf(rS & 1);
             for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                 const int nn = t / Lx, c = t % Lx;
                 const int bb = blockIdx.x * 16 + nn;
-                rows[rS & 1][c][nn] = bb < B ? S[((size_t)bb * Ly + rS) * Lx + c] : (int8_t)1;
+                r1[c][nn] = bb < B ? S[((size_t)bb * Ly + rS) * Lx + c] : (int8_t)1;
             }
         }
         __syncthreads();
 
         const size_t rowP = (size_t)p * Lx, rowSb = (size_t)rS * Lx;
         const void *Gph = rightward ? GLv : GRv;
+        const size_t rbase = isP ? rowP : rowSb;
+        // environment tiles of this phase's row; per-lane offset of spin s_w's tiles
+        const __amdgpu_buffer_rsrc_t ars =
+            make_rsrc((const char *)Gph + rbase * AT::SITE_BYTES, (uint32_t)(Lx * AT::SITE_BYTES));
+        const uint32_t avb = (uint32_t)(sw * (AT::SITE_BYTES / 2) + lane * (BF16 ? 8 : 4));
         floatx4 vec[NT];   // r_{s_w} (environment sweep) or Lam (drawing)
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) vec[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         if (grp == 0) vec[0][0] = 1.0f;
-        const size_t rbase = isP ? rowP : rowSb;
         auto colof = [&](int t) { return rightward ? t : Lx - 1 - t; };
-        auto gptr = [&](int c, int s2, int mo) {
-            return (const floatx4 *)(gwg + c * gstride + (((size_t)s2 * NT + mo) * 64 + lane) * 4);
+        auto gload = [&](floatx4 (&gk)[2][NT], int c) {
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo)
+                    gk[s2][mo] = __builtin_bit_cast(
+                        floatx4, __builtin_amdgcn_raw_buffer_load_b128(
+                                     grs, (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16), (uint32_t)c * gstride, 0));
         };
-        ATile<NT, BF16> a[PF];
+        AT a[PF];
         floatx4 g[PF][2][NT];   // stored y_s tiles of the drawn row (drawing group)
-        if (isP || isS) {
-#pragma unroll
-            for (int k = 0; k < PF; ++k)
-                a[k].load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(k, Lx - 1)), sw, mow), lane);
-        }
-        if (isS) {
-#pragma unroll
-            for (int k = 0; k < PF; ++k)
-#pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-                    for (int mo = 0; mo < NT; ++mo) g[k][s2][mo] = *gptr(colof(min(k, Lx - 1)), s2, mo);
-        }
-        const int8_t(*prowP)[16] = rows[(p + 1) & 1];   // row p-1 (above row p)
-        const int8_t(*prowS)[16] = rows[p & 1];         // row p-2 (above row p-1)
-        int8_t(*crowS)[16] = rows[(p + 1) & 1];         // row p-1, written by the drawing
+        const int8_t(*prowP)[16] = rowbuf((p + 1) & 1);   // row p-1 (above row p)
+        const int8_t(*prowS)[16] = rowbuf(p & 1);         // row p-2 (above row p-1)
+        int8_t(*crowS)[16] = rowbuf((p + 1) & 1);         // row p-1, written by the drawing
 
         // One loop per role over whole turns of the ring, then the remaining
-        // steps; the loads are unconditional (the last columns re-read the final
-        // one), so that the compiler can count the loads in flight and waits
+        // steps.  The loads are unconditional (the last columns re-read the final
+        // one) and fenced from the scheduler, each role issues its first ring
+        // entries in ring order, and the two roles share no code path before
+        // their loops: the compiler can then count the loads in flight and waits
         // only for the ring entry it uses.
         if (isS) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int ck = colof(min(k, Lx - 1));
+                gload(g[k], ck);
+                a[k].load(ars, avb, (uint32_t)(ck * AT::SITE_BYTES));
+                __builtin_amdgcn_sched_barrier(0);
+            }
             int sprev = 0;   // index of the previous spin (0: +1, 1: -1); unused at t = 0
             auto stepS = [&](int k, int t) {
                 const int c = colof(t);
                 const int cn = colof(min(t + PF, Lx - 1));
-                // the product with G_c(s_w) does not depend on the draw: issue it first
-                const floatx4 acc = a[k].mul(vec);
+                // spin above, random word, given spin; the factor pair
+                // v_c(s) hf(s) for (s_up, s_prev) read at its address
+                const int8_t up = prowS[c][n];
+                const uint32_t word = uni[c][n];
+                const int8_t given = crowS[c][n];
+                const bool up_minus = rS > 0 && up < 0;
+                const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
+                // Lam G_c(s_w) does not depend on the draw
+                floatx4 acc[NT];
+                a[k].mul(vec, acc);
                 float d0 = 0.0f, d1 = 0.0f;
 #pragma unroll
                 for (int mo = 0; mo < NT; ++mo)
@@ -258,50 +351,51 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
                         d0 = fmaf(vec[mo][i], g[k][0][mo][i], d0);
                         d1 = fmaf(vec[mo][i], g[k][1][mo][i], d1);
                     }
-#pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-                    for (int mo = 0; mo < NT; ++mo) g[k][s2][mo] = *gptr(cn, s2, mo);
-                a[k].load(tile_ptr<NT, BF16>(Gph, rbase + cn, sw, mow), lane);
-                d0 = rows4_sum(d0);
-                d1 = rows4_sum(d1);
-                const int su = rS > 0 ? (prowS[c][n] > 0 ? 0 : 1) : 0;
-                double w0 = vS[c][su][sprev][0] * (double)d0;
-                double w1 = vS[c][su][sprev][1] * (double)d1;
+                gload(g[k], cn);
+                a[k].load(ars, avb, (uint32_t)(cn * AT::SITE_BYTES));
+                __builtin_amdgcn_sched_barrier(0);
+                rows4_sum2(d0, d1);
+                double w0 = vv.x * (double)d0;
+                double w1 = vv.y * (double)d1;
                 n_clamp += (w0 < 0.0) + (w1 < 0.0);
                 w0 = fmax(w0, 0.0);
                 w1 = fmax(w1, 0.0);
                 const double tot = w0 + w1;
                 const bool bad = !(tot > 0.0 && tot <= 1.79e308);
                 n_both += bad;
-                const double pp = bad ? 0.5 : w0 / tot;
-                int s;
-                if (eval) {
-                    s = crowS[c][n];
-                } else {
-                    const double u = tn_u01(uni[c][n]);
-                    s = (u < pp) ? 1 : -1;
-                    n_near += fabs(u - pp) < 1e-6;
-                    if (leader) crowS[c][n] = (int8_t)s;
-                }
-                int e2;
-                mant = frexp(mant * (s > 0 ? pp : 1.0 - pp), &e2);
-                mexp += e2;
+                // s = +1 iff u < w0 / tot, decided as u tot < w0 (p+ = 1/2 if degenerate)
+                const double u = tn_u01(word);
+                const double ut = bad ? u : u * tot, wt = bad ? 0.5 : w0, sc = bad ? 1.0 : tot;
+                const int s = eval ? (int)given : ((ut < wt) ? 1 : -1);
+                n_near += !eval && fabs(ut - wt) < 1e-6 * sc;
+                crowS[c][n] = (int8_t)s;   // every drawing lane writes the same value
+                num *= bad ? 0.5 : (s > 0 ? w0 : w1);
+                den *= sc;
                 sprev = s > 0 ? 0 : 1;
-                xch[gp][buf][sw][mow][lane] = acc;
-                __syncthreads();
-                float mx = 0.0f;
+                if (t % RS == RS - 1) {
+                    // power-of-two rescale of the output (from the input's largest entry)
+                    // and renormalisation of the ln q products
+                    float mx = 0.0f;
 #pragma unroll
-                for (int mo = 0; mo < NT; ++mo) {
-                    vec[mo] = s > 0 ? xch[gp][buf][0][mo][lane] : xch[gp][buf][1][mo][lane];
+                    for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(vec[mo][i]));
+                        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(vec[mo][i]));
+                    const int e = pow2_exponent_f(rows4_max(mx));
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[mo][i] = ldexpf(acc[mo][i], -e);
+                    int e1, e2;
+                    num = frexp(num, &e1);
+                    den = frexp(den, &e2);
+                    nexp += e1 - e2;
                 }
-                const int e = pow2_exponent_f(rows4_max(mx));
 #pragma unroll
-                for (int mo = 0; mo < NT; ++mo)
+                for (int mo = 0; mo < NT; ++mo) xch[gp][buf][sw][mo][lane] = acc[mo];
+                __syncthreads();
+                const int sd = s > 0 ? 0 : 1;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) vec[mo][i] = ldexpf(vec[mo][i], -e);
+                for (int mo = 0; mo < NT; ++mo) vec[mo] = xch[gp][buf][sd][mo][lane];
                 buf ^= 1;
             };
             int t0 = 0;
@@ -313,33 +407,54 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
             for (int k = 0; k < PF - 1; ++k)
                 if (t0 + k < Lx) stepS(k, t0 + k);
         } else if (isP) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                a[k].load(ars, avb, (uint32_t)(colof(min(k, Lx - 1)) * AT::SITE_BYTES));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            int e = 0;   // pending power-of-two scale of the next product's output
             auto stepP = [&](int k, int t) {
                 const int c = colof(t);
-                const floatx4 acc = a[k].mul(vec);
-                *(floatx4 *)gptr(c, sw, mow) = acc;
-                a[k].load(tile_ptr<NT, BF16>(Gph, rbase + colof(min(t + PF, Lx - 1)), sw, mow), lane);
-                xch[gp][buf][sw][mow][lane] = acc;
-                __syncthreads();
-                if (t + 1 < Lx) {
-                    floatx4 y[2][NT];
-                    float mx = 0.0f;
-#pragma unroll
-                    for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-                        for (int mo = 0; mo < NT; ++mo) {
-                            y[s2][mo] = xch[gp][buf][s2][mo][lane];
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(y[s2][mo][i]));
-                        }
-                    const int e = pow2_exponent_f(rows4_max(mx));
-                    const int su = p > 0 ? (prowP[c][n] > 0 ? 0 : 1) : 0;
-                    const float m0 = mixP[c][su][sw][0], m1 = mixP[c][su][sw][1];
+                floatx4 acc[NT];
+                a[k].mul(vec, acc);
+                const floatx4 mt = *(const floatx4 *)&mixP[c][sw][0][0];   // [s_up][s]
+                const bool resc = t % RS == 0 && t > 0;                      // apply e
+                const bool meas = t % RS == RS - 1;                          // measure e
+                if (resc) {
 #pragma unroll
                     for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            vec[mo][i] = ldexpf(m0 * y[0][mo][i] + m1 * y[1][mo][i], -e);
+                        for (int i = 0; i < 4; ++i) acc[mo][i] = ldexpf(acc[mo][i], -e);
                 }
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo)
+                    __builtin_amdgcn_raw_buffer_store_b128(
+                        __builtin_bit_cast(uintx4, acc[mo]), grs,
+                        (uint32_t)(((sw * NT + mo) * 64 + lane) * 16), (uint32_t)c * gstride, 0);
+                a[k].load(ars, avb, (uint32_t)(colof(min(t + PF, Lx - 1)) * AT::SITE_BYTES));
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo) xch[gp][buf][sw][mo][lane] = acc[mo];
+                float mx = 0.0f;
+                if (meas) {
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(acc[mo][i]));
+                    pmx[gp][buf][sw][lane] = mx;
+                }
+                __syncthreads();
+                // r_{s_w} for the next column: W(s_w, s) v_c(s) mixing of both y_s
+                const bool up_minus = p > 0 && prowP[c][n] < 0;
+                const float m0 = up_minus ? mt[2] : mt[0], m1 = up_minus ? mt[3] : mt[1];
+                const float mown = sw == 0 ? m0 : m1, moth = sw == 0 ? m1 : m0;
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo) {
+                    const floatx4 yo = xch[gp][buf][1 - sw][mo][lane];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) vec[mo][i] = mown * acc[mo][i] + moth * yo[i];
+                }
+                if (meas) e = pow2_exponent_f(rows4_max(fmaxf(mx, pmx[gp][buf][1 - sw][lane])));
                 buf ^= 1;
             };
             int t0 = 0;
@@ -359,84 +474,97 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
         __syncthreads();   // the drawn row is complete in LDS
 
         if (hasS) {
-            // energy of row p-1 (Eq. ising: field, bonds in the row, bonds to the row above)
-            if (gp == 0 && leader) {
-                const int8_t(*cur)[16] = rows[(p + 1) & 1];
-                const int8_t(*abv)[16] = rows[p & 1];
+            // energy of row p-1 (Eq. ising: field, bonds in the row, bonds to the row
+            // above): 16 column groups per proposal, summed in a fixed order
+            const int8_t(*cur)[16] = rowbuf((p + 1) & 1);
+            const int8_t(*abv)[16] = rowbuf(p & 1);
+            {
+                const int nn = threadIdx.x & 15, cg = threadIdx.x >> 4;
                 double e = 0.0;
-                for (int c = 0; c < Lx; ++c) {
-                    const int sc = cur[c][n];
-                    if (h) e -= h[rowSb + c] * sc;
-                    if (c > 0) e -= Jh[(size_t)rS * (Lx - 1) + c - 1] * (double)(cur[c - 1][n] * sc);
-                    if (rS > 0) e -= Jv[(size_t)(rS - 1) * Lx + c] * (double)(abv[c][n] * sc);
+                for (int c = cg; c < Lx; c += 16) {
+                    const double sc = cur[c][nn];
+                    const double sl = c > 0 ? (double)cur[c - 1][nn] : 0.0;
+                    const double sa = rS > 0 ? (double)abv[c][nn] : 0.0;
+                    e -= sc * (eT[c][0] + eT[c][1] * sl + eT[c][2] * sa);
                 }
-                E += e;
+                epart[cg][nn] = e;
             }
             if (!eval) {
                 for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                     const int nn = t / Lx, c = t % Lx;
                     const int bb = blockIdx.x * 16 + nn;
-                    if (bb < B) S[((size_t)bb * Ly + rS) * Lx + c] = rows[(p + 1) & 1][c][nn];
+                    if (bb < B) S[((size_t)bb * Ly + rS) * Lx + c] = cur[c][nn];
                 }
+            }
+            __syncthreads();
+            if (threadIdx.x < 16) {
+                double e = 0.0;
+                for (int cg = 0; cg < 16; ++cg) e += epart[cg][threadIdx.x];
+                E += e;   // held by threads 0..15 (proposal threadIdx.x)
             }
         }
     }
     // combine the two groups' ln q parts; flush the counters
     if (leader) {
-        lqx[gp][n][0] = mant;
-        lqx[gp][n][1] = (double)mexp;
+        lqx[gp][n] = (log(num) - log(den)) + (double)nexp * 0.69314718055994530942;
         if (valid) {
-            if (n_clamp) atomicAdd(&counters[CNT_CLAMPS], n_clamp);
-            if (n_both) atomicAdd(&counters[CNT_BOTH], n_both);
-            if (n_near && !eval) atomicAdd(&counters[CNT_NEAR], n_near);
+            if (n_clamp) atomicAdd(&counters[CNT_CLAMPS], (unsigned long long)n_clamp);
+            if (n_both) atomicAdd(&counters[CNT_BOTH], (unsigned long long)n_both);
+            if (n_near && !eval) atomicAdd(&counters[CNT_NEAR], (unsigned long long)n_near);
         }
     }
+    if (threadIdx.x < 16) ex[threadIdx.x] = E;
     __syncthreads();
     if (gp == 0 && leader && valid) {
-        logq[b] = (log(lqx[0][n][0]) + log(lqx[1][n][0])) +
-                  (lqx[0][n][1] + lqx[1][n][1]) * 0.69314718055994530942;
-        energy[b] = E;
+        logq[b] = lqx[0][n] + lqx[1][n];
+        energy[b] = ex[n];
     }
 }
 
 template <int NT, bool BF16>
 int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
-                float *g, uint64_t seed, uint64_t step, uint64_t first_id) {
+                float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     const int blocks = (B + 15) / 16;
     const void *GR = BF16 ? (const void *)ctx->G16R : (const void *)ctx->G32R;
     const void *GL = BF16 ? (const void *)ctx->G16L : (const void *)ctx->G32L;
-    hipLaunchKernelGGL((k_sampler_mfma<NT, BF16>), dim3(blocks), dim3(256 * NT), 0, ctx->stream,
-                       B, ctx->Lx, ctx->Ly, ctx->Jh, ctx->Jv, ctx->h, ctx->fac, GR, GL, S,
-                       eval ? 1 : 0, logq, energy, g, (uint32_t)seed, (uint32_t)(seed >> 32),
-                       first_id, (uint32_t)step, (uint32_t)ctx->inst, ctx->counters);
+    const SmemLayout<NT> L(ctx->Lx);
+    auto kern = k_sampler_mfma<NT, BF16>;
+    if (L.total > 65536)
+        TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, L.total));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), L.total, ctx->stream, B, ctx->Lx, ctx->Ly,
+                       ctx->Jh, ctx->Jv, ctx->h, ctx->fac, GR, GL, S, eval ? 1 : 0, logq, energy,
+                       g, (uint32_t)seed, (uint32_t)(seed >> 32), first_id, step0, per_step,
+                       (uint32_t)ctx->inst, ctx->counters);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
 }
 
 template <bool BF16>
 int dispatch_nt(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
-                float *g, uint64_t seed, uint64_t step, uint64_t first_id) {
+                float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     switch (ctx->Dp / 16) {
-    case 1: return launch_mfma<1, BF16>(ctx, B, S, eval, logq, energy, g, seed, step, first_id);
-    case 2: return launch_mfma<2, BF16>(ctx, B, S, eval, logq, energy, g, seed, step, first_id);
-    case 3: return launch_mfma<3, BF16>(ctx, B, S, eval, logq, energy, g, seed, step, first_id);
-    case 4: return launch_mfma<4, BF16>(ctx, B, S, eval, logq, energy, g, seed, step, first_id);
+    case 1: return launch_mfma<1, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 2: return launch_mfma<2, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 3: return launch_mfma<3, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 4: return launch_mfma<4, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
     default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
     }
 }
 
 }  // namespace
 
-int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
-                int8_t *spins, bool eval, double *logq, double *energy) {
+int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
+                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy) {
     if (batch == 0) return TN_OK;
     if (ctx->Lx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
+    if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
     const int blocks = (batch + 15) / 16;
     const size_t need = (size_t)blocks * 2 * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
     int rc;
     if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, need))) return rc;
     float *g = (float *)ctx->gscr;
     if (ctx->prec == TN_BF16)
-        return dispatch_nt<true>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
-    return dispatch_nt<false>(ctx, batch, spins, eval, logq, energy, g, seed, step, first_id);
+        return dispatch_nt<true>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    return dispatch_nt<false>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
 }
