@@ -3,8 +3,11 @@ chain on a 64x64 open ferromagnet at beta = 0.4407 with D = 32 environments,
 4096 independent chains (one proposal per chain per step).
 
 One step = one proposal per chain drawn by the batched fp32 MFMA sampler plus
-the acceptance kernel; the environment build (fp64 QR/SVD) is done once before
-the timed region and reported separately.  The plain fp64 GPU path (per-row
+the acceptance kernel.  The proposals do not depend on the chains' state, so
+the sampler draws those of a few consecutive steps per launch (enough to give
+every compute unit two workgroups); the chains are bitwise those of one launch
+per step.  The environment build (fp64 QR/SVD) is done once before the timed
+region and reported separately.  The plain fp64 GPU path (per-row
 launches) runs the same chains from the same seeds for the comparison, and
 the FP64 CPU oracle is timed on a bounded sample of the same workload.
 
@@ -54,7 +57,16 @@ def tau_int(E, burn=0.1, c=6.0):
     return float(tau)
 
 
-def run_gpu(prec, inst, steps, warmup, env_state=None):
+def ahead_steps(chains):
+    """MH steps whose proposals share one sampler launch: enough 16-proposal
+    workgroups for two per compute unit (proposals do not depend on the
+    chains' state, Sec. 2, so drawing them ahead leaves the chains unchanged)."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return max(1, -(-2 * 16 * cus // chains))
+
+
+def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):
     import numpy as np
     import torch
     from paper_2104_13264_amd import Sampler
@@ -72,32 +84,54 @@ def run_gpu(prec, inst, steps, warmup, env_state=None):
         build_s = None
     C = inst.chains
     state = s.init_state(C)
-    prop = s.empty_batch(C)
+    m = max(1, ahead)
+    prop = (torch.empty((m, C, inst.Ly, inst.Lx), dtype=torch.int8, device=s.device),
+            torch.empty((m, C), dtype=torch.float64, device=s.device),
+            torch.empty((m, C), dtype=torch.float64, device=s.device))
     stream = torch.cuda.current_stream()
-    for t in range(warmup):
-        s.sample(C, inst.seed, step=t, out=prop)
-        s.mh_accept(prop, state, inst.seed, t)
+
+    def block(t, mm):
+        out = (prop[0][:mm], prop[1][:mm], prop[2][:mm])
+        s.sample_steps(C, mm, inst.seed, step0=t, out=out)
+
+    def accept(t, j):
+        s.mh_accept((prop[0][j], prop[1][j], prop[2][j]), state, inst.seed, t + j)
+
+    t = 0
+    while t < warmup:
+        mm = min(m, warmup - t)
+        block(t, mm)
+        for j in range(mm):
+            accept(t, j)
+        t += mm
     s.stats(reset=True)
     E_series = torch.empty((steps, C), dtype=torch.float64, device=s.device)
+    nl = -(-steps // m)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+          for _ in range(nl)]
+    launch_sizes = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for k in range(steps):
-        t = warmup + k
-        ev[k][0].record(stream)
-        s.sample(C, inst.seed, step=t, out=prop)
-        ev[k][1].record(stream)
-        s.mh_accept(prop, state, inst.seed, t)
-        E_series[k].copy_(state["energy"])
+    k = 0
+    for li in range(nl):
+        mm = min(m, steps - k)
+        ev[li][0].record(stream)
+        block(warmup + k, mm)
+        ev[li][1].record(stream)
+        launch_sizes.append(mm)
+        for j in range(mm):
+            accept(warmup + k, j)
+            E_series[k + j].copy_(state["energy"])
+        k += mm
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     kern_ms = [a.elapsed_time(b) for a, b in ev]
+    full = [ms for ms, mm in zip(kern_ms, launch_sizes) if mm == m]
     st = s.stats()
     E = E_series.cpu().numpy()
     s.close()
     return dict(wall=wall, accepted=st["accepted"], proposed=st["proposed"],
-                sampler_ms=float(np.mean(kern_ms)), sampler_ms_all=kern_ms,
+                sampler_ms=float(np.mean(full if full else kern_ms)), steps_per_launch=m,
                 build_s=build_s, logZ=logZ, E=E, near=st["near_threshold"],
                 clamps=st["clamps"]), env_state
 
@@ -158,6 +192,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
+    ap.add_argument("--ahead", type=int, default=None,
+                    help="MH steps per sampler launch (default: enough for two workgroups per CU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -180,10 +216,11 @@ def main():
         del x, y
     log(f"[bench] ferro 64x64 D={D} chains={C} steps={args.steps} warmup={args.warmup}")
 
-    res32, env_state = run_gpu(1, inst, args.steps, args.warmup)
+    m = ahead_steps(C) if args.ahead is None else args.ahead
+    res32, env_state = run_gpu(1, inst, args.steps, args.warmup, ahead=m)
     log(f"[bench] fp32 batched: {res32['wall']*1e3/args.steps:.3f} ms/step, "
-        f"sampler {res32['sampler_ms']:.3f} ms, acc {res32['accepted']}/{res32['proposed']}, "
-        f"env build {res32['build_s']:.2f} s")
+        f"sampler {res32['sampler_ms']:.3f} ms per launch of {m} steps, "
+        f"acc {res32['accepted']}/{res32['proposed']}, env build {res32['build_s']:.2f} s")
     res64 = None
     if not args.no_plain:
         res64, _ = run_gpu(0, inst, args.steps, args.warmup, env_state)
@@ -194,8 +231,9 @@ def main():
     ms_per_step = res32["wall"] * 1e3 / args.steps
     # algorithmic work of one sampler launch: per proposal and column, the
     # right sweep multiplies the two D x D matrices G_c(+-1) into its vectors
-    # and the left sweep one D x D matrix: 3 * 2 D^2 flops; L^2 columns.
-    flops_launch = 6.0 * D * D * L * L * C
+    # and the left sweep one D x D matrix: 3 * 2 D^2 flops; L^2 columns; a
+    # launch draws the proposals of `steps_per_launch` MH steps.
+    flops_launch = 6.0 * D * D * L * L * C * res32["steps_per_launch"]
     achieved = flops_launch / (res32["sampler_ms"] * 1e-3)
     traffic = measured_traffic()
     out = {
@@ -214,12 +252,14 @@ def main():
         "config": {"workload": "ferro64_D32: 64x64 open-boundary ferromagnet J=+1, h=0, "
                                "beta=0.4407, D=32 fp64 environments, 4096 chains from all-up, "
                                "one proposal per chain per step",
-                   "chains": C, "L": L, "D": D, "beta": inst.beta, "seed": inst.seed},
+                   "chains": C, "L": L, "D": D, "beta": inst.beta, "seed": inst.seed,
+                   "mh_steps_per_sampler_launch": res32["steps_per_launch"]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic,
                      "kernel": "k_sampler_mfma<2,false>",
                      "flops_per_launch": flops_launch,
+                     "proposals_per_launch": C * res32["steps_per_launch"],
                      "kernel_ms": res32["sampler_ms"]},
         "acceptance": res32["accepted"] / max(res32["proposed"], 1),
         "proposals_per_s": res32["proposed"] / res32["wall"],

@@ -148,6 +148,29 @@ int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                  const double *prop_energy, int8_t *state_spins, double *state_logq,
                  double *state_energy, uint8_t *accepted);
 
+/* Proposals of `nsteps` consecutive MH steps in one call: the candidate of
+ * Algorithm 1 is drawn from q alone, independently of the chain's state
+ * (Sec. 2), so the proposals of several steps can be drawn together.
+ * Proposal (t, j) has id first_id + j and step step0 + t and is bitwise the
+ * one tn_sample(batch = chains, step = step0 + t, first_id) draws.
+ *   spins (dev, int8 [nsteps][chains][Ly][Lx]), logq, energy (dev, fp64
+ *   [nsteps][chains]).  TN_EINVAL for nsteps < 1 or chains < 0. */
+int tn_sample_steps(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0,
+                    uint64_t first_id, int8_t *spins, double *logq, double *energy);
+
+/* `nsteps` steps of Algorithm 1 (steps step0 .. step0 + nsteps - 1) for
+ * `chains` chains: the proposals of several steps are drawn per sampler
+ * launch (tn_sample_steps, enough to fill the GPU), then accepted step by
+ * step exactly as tn_mh_step would; the chains end bitwise where nsteps calls
+ * of tn_mh_step leave them.
+ *   state_* as in tn_mh_step; accepted (dev, uint8 [nsteps][chains]);
+ *   energy_series (dev, fp64 [nsteps][chains], or NULL): the state energy
+ *   after each step.  Context-owned proposal buffers hold up to the launch's
+ *   steps. */
+int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0,
+              int8_t *state_spins, double *state_logq, double *state_energy,
+              uint8_t *accepted, double *energy_series);
+
 /* Derivative of ln Z~ with the truncation isometries frozen: every
  * compression step of the environment build is replaced by the orthogonal
  * projector onto the span kept at its leftmost truncated bond (the identity

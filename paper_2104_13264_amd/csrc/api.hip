@@ -288,6 +288,72 @@ int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *st
                             state_spins, state_logq, state_energy, accepted);
 }
 
+int tn_sample_steps(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0,
+                    uint64_t first_id, int8_t *spins, double *logq, double *energy) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (chains < 0 || nsteps < 1) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsteps < 1");
+    if ((size_t)chains * nsteps > (size_t)INT32_MAX / 2)
+        return tn_fail(ctx, TN_EINVAL, "chains * nsteps too large");
+    if (chains == 0) return TN_OK;
+    if (!spins || !logq || !energy) return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
+    const int batch = chains * nsteps;
+    if (ctx->prec == TN_FP64)
+        return tn_run_fp64(ctx, batch, seed, step0, chains, first_id, spins, false, logq, energy);
+    return tn_run_mfma(ctx, batch, seed, step0, chains, first_id, spins, false, logq, energy);
+}
+
+int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0,
+              int8_t *state_spins, double *state_logq, double *state_energy,
+              uint8_t *accepted, double *energy_series) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (chains < 0 || nsteps < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsteps < 0");
+    if (chains == 0 || nsteps == 0) return TN_OK;
+    if (!state_spins || !state_logq || !state_energy || !accepted)
+        return tn_fail(ctx, TN_EINVAL, "NULL state buffer");
+    // steps per sampler launch: two 16-proposal workgroups per compute unit
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+        cus = 256;
+    const long target = 2L * 16 * cus;
+    int m = (int)((target + chains - 1) / chains);
+    m = m < 1 ? 1 : (m > nsteps ? nsteps : m);
+    if ((size_t)chains * m > (size_t)INT32_MAX / 2) m = 1;
+    const size_t nsite = (size_t)ctx->Lx * ctx->Ly;
+    const size_t spin_bytes = ((m * chains * nsite + 255) / 256) * 256;
+    const size_t need = spin_bytes + 2 * (size_t)m * chains * sizeof(double);
+    if (need > ctx->pcap) {
+        void *p = ctx->pspins;
+        if ((rc = tn_ensure(ctx, &p, &ctx->pcap, need))) return rc;
+        ctx->pspins = (int8_t *)p;
+    }
+    ctx->plogq = (double *)(ctx->pspins + spin_bytes);
+    ctx->pE = ctx->plogq + (size_t)m * chains;
+    for (int t0 = 0; t0 < nsteps; t0 += m) {
+        const int mm = nsteps - t0 < m ? nsteps - t0 : m;
+        if ((rc = tn_sample_steps(ctx, chains, mm, seed, step0 + t0, 0, ctx->pspins, ctx->plogq,
+                                  ctx->pE)))
+            return rc;
+        for (int j = 0; j < mm; ++j) {
+            const size_t o = (size_t)j * chains;
+            if ((rc = tn_launch_accept(ctx, chains, seed, step0 + t0 + j, ctx->pspins + o * nsite,
+                                       ctx->plogq + o, ctx->pE + o, state_spins, state_logq,
+                                       state_energy, accepted + (size_t)(t0 + j) * chains)))
+                return rc;
+            if (energy_series)
+                TN_HIP(ctx, hipMemcpyAsync(energy_series + (size_t)(t0 + j) * chains, state_energy,
+                                           (size_t)chains * sizeof(double),
+                                           hipMemcpyDeviceToDevice, ctx->stream));
+        }
+    }
+    return TN_OK;
+}
+
 int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                  const int8_t *prop_spins, const double *prop_logq, const double *prop_energy,
                  int8_t *state_spins, double *state_logq, double *state_energy,

@@ -56,6 +56,8 @@ def lib():
         "tn_sample": (i, [vp, i, u64, u64, u64, vp, vp, vp]),
         "tn_eval_logq": (i, [vp, i, vp, vp, vp]),
         "tn_mh_step": (i, [vp, i, u64, u64, vp, vp, vp, vp]),
+        "tn_sample_steps": (i, [vp, i, i, u64, u64, u64, vp, vp, vp]),
+        "tn_mh_run": (i, [vp, i, i, u64, u64, vp, vp, vp, vp, vp]),
         "tn_mh_accept": (i, [vp, i, u64, u64, vp, vp, vp, vp, vp, vp, vp]),
         "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
@@ -71,7 +73,8 @@ def lib():
 def exported_symbols():
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_build_env", "tn_set_env",
             "tn_get_env", "tn_set_precision", "tn_set_instance", "tn_sample",
-            "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_grad", "tn_stats"]
+            "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
+            "tn_grad", "tn_stats"]
 
 
 def _ptr(t):
@@ -175,6 +178,18 @@ class Sampler:
                                     _ptr(s), _ptr(lq), _ptr(E)))
         return s, lq, E
 
+    def sample_steps(self, chains, nsteps, seed, step0=0, first_id=0, out=None):
+        """Proposals of nsteps MH steps at once: tensors [nsteps][chains]..."""
+        if out is None:
+            out = (torch.empty((nsteps, chains, self.Ly, self.Lx), dtype=torch.int8,
+                               device=self.device),
+                   torch.empty((nsteps, chains), dtype=torch.float64, device=self.device),
+                   torch.empty((nsteps, chains), dtype=torch.float64, device=self.device))
+        s, lq, E = out
+        self._check(lib().tn_sample_steps(self._ctx, int(chains), int(nsteps), int(seed),
+                                          int(step0), int(first_id), _ptr(s), _ptr(lq), _ptr(E)))
+        return s, lq, E
+
     def eval_logq(self, spins):
         spins = torch.as_tensor(spins, dtype=torch.int8, device=self.device).contiguous()
         B = spins.shape[0]
@@ -197,6 +212,18 @@ class Sampler:
                                      _ptr(state["logq"]), _ptr(state["energy"]),
                                      _ptr(state["accepted"])))
         return state["accepted"]
+
+    def mh_run(self, state, seed, step0, nsteps, energy_series=True):
+        """nsteps MH steps; returns (accepted [nsteps][chains], energies or None)."""
+        C = state["spins"].shape[0]
+        acc = torch.empty((nsteps, C), dtype=torch.uint8, device=self.device)
+        es = (torch.empty((nsteps, C), dtype=torch.float64, device=self.device)
+              if energy_series else None)
+        self._check(lib().tn_mh_run(self._ctx, C, int(nsteps), int(seed), int(step0),
+                                    _ptr(state["spins"]), _ptr(state["logq"]),
+                                    _ptr(state["energy"]), _ptr(acc),
+                                    _ptr(es) if es is not None else None))
+        return acc, es
 
     def mh_accept(self, proposal, state, seed, step):
         """Acceptance half of an MH step for proposals drawn with sample()."""

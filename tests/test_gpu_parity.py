@@ -258,3 +258,47 @@ def test_full_size_ferro64_sampled_parity():
     np.testing.assert_allclose(lq.cpu().numpy()[pick], ev['logq'], rtol=TOL_LOGQ_FP32)
     assert np.array_equal(E.cpu().numpy()[pick], ev['energy'])
     s.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, BF16], ids=["fp64", "fp32", "bf16"])
+def test_sample_steps_equals_per_step_sampling(prec):
+    # proposals of several MH steps in one launch are bitwise the per-step ones
+    # (ragged chain count: the steps split inside a 16-proposal workgroup)
+    inst = random_instance(7, 9, 0.6, 6, seed=51, field_scale=0.2)
+    log(f"[steps] 7x9 D6 prec {prec}")
+    s, envs = gpu_sampler_with_oracle_env(inst, 6, prec)
+    chains, nsteps, seed, step0, first = 37, 3, 99, 11, 5
+    sp, lq, E = s.sample_steps(chains, nsteps, seed, step0=step0, first_id=first)
+    for t in range(nsteps):
+        a, b, c = s.sample(chains, seed, step=step0 + t, first_id=first)
+        assert torch.equal(sp[t], a)
+        assert torch.equal(lq[t], b)
+        assert torch.equal(E[t], c)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+def test_mh_run_equals_mh_steps(prec):
+    inst = random_instance(6, 8, 0.7, 5, seed=52)
+    log(f"[mh_run] 6x8 D5 prec {prec}")
+    s, envs = gpu_sampler_with_oracle_env(inst, 5, prec)
+    chains, nsteps, seed = 45, 7, 123
+    st1 = s.init_state(chains)
+    st2 = s.init_state(chains)
+    acc, es = s.mh_run(st1, seed, 3, nsteps)
+    for t in range(nsteps):
+        s.mh_step(st2, seed, 3 + t)
+        assert torch.equal(acc[t], st2['accepted'])
+        assert torch.equal(es[t], st2['energy'])
+    for k in ("spins", "logq", "energy"):
+        assert torch.equal(st1[k], st2[k])
+    s.close()
+
+
+def test_sample_steps_rejects_bad_sizes():
+    from paper_2104_13264_amd import TNError
+    inst = random_instance(3, 4, 0.5, 4, seed=53)
+    s, _ = gpu_sampler_with_oracle_env(inst, 4, FP32)
+    with pytest.raises(TNError):
+        s.sample_steps(8, 0, 1)
+    s.close()
