@@ -166,16 +166,81 @@ __device__ __forceinline__ double tn_qleg(double K, int mu, int sidx) {
     return mu == 0 ? sqrt(cosh(K)) : sg * s * sqrt(fabs(sinh(K)));
 }
 
+// Wavefront reductions on the VALU: quad permutations, the half-row and row
+// mirrors (DPP) and the 16- and 32-lane swaps of gfx950, no LDS round trips.
+// Every lane ends with the same value, combined in the same order.
+namespace tn_detail {
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+struct Pair32 {
+    uint32_t a, b;
+};
+// the partner's value in each of the six combining steps
+template <int STEP>
+__device__ __forceinline__ uint32_t partner32(uint32_t v) {
+    if constexpr (STEP == 0) return dpp32<0xB1>(v);          // quad_perm [1,0,3,2]
+    else if constexpr (STEP == 1) return dpp32<0x4E>(v);     // quad_perm [2,3,0,1]
+    else if constexpr (STEP == 2) return dpp32<0x141>(v);    // row_half_mirror
+    else if constexpr (STEP == 3) return dpp32<0x140>(v);    // row_mirror
+    else if constexpr (STEP == 4) {
+        auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    }
+}
+template <int STEP>
+__device__ __forceinline__ float partner(float v) {
+    return __uint_as_float(partner32<STEP>(__float_as_uint(v)));
+}
+template <int STEP>
+__device__ __forceinline__ double partner(double v) {
+    const uint32_t lo = partner32<STEP>((uint32_t)__double2loint(v));
+    const uint32_t hi = partner32<STEP>((uint32_t)__double2hiint(v));
+    return __hiloint2double((int)hi, (int)lo);
+}
+template <int STEP>
+__device__ __forceinline__ int partner(int v) {
+    return (int)partner32<STEP>((uint32_t)v);
+}
+}  // namespace tn_detail
+
 template <typename T>
 __device__ __forceinline__ T tn_wave_sum(T v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    using namespace tn_detail;
+    v = v + partner<0>(v);
+    v = v + partner<1>(v);
+    v = v + partner<2>(v);
+    v = v + partner<3>(v);
+    v = v + partner<4>(v);
+    v = v + partner<5>(v);
     return v;
 }
 template <typename T>
 __device__ __forceinline__ T tn_wave_max(T v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    using namespace tn_detail;
+    v = fmax(v, partner<0>(v));
+    v = fmax(v, partner<1>(v));
+    v = fmax(v, partner<2>(v));
+    v = fmax(v, partner<3>(v));
+    v = fmax(v, partner<4>(v));
+    v = fmax(v, partner<5>(v));
+    return v;
+}
+
+// Sum over the 16 lanes of a row (lanes 16r .. 16r+15): quad permutations
+// and the half-row and row mirrors; every lane of the row ends with the same
+// value.
+template <typename T>
+__device__ __forceinline__ T tn_row16_sum(T v) {
+    using namespace tn_detail;
+    v = v + partner<0>(v);
+    v = v + partner<1>(v);
+    v = v + partner<2>(v);
+    v = v + partner<3>(v);
     return v;
 }
 

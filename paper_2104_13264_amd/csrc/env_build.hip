@@ -10,7 +10,6 @@
 //   xbox [c][i][u][j]     2D x 2 x 2D box per column: the MPO-MPS product
 //                         X_c[(a,l), u, (b,x)] and its canonical forms
 #include "common.hpp"
-#include "linalg.hpp"
 
 #include <chrono>
 #include <cmath>
@@ -73,64 +72,147 @@ k_mpo_apply(int k, int Lx, int Ly, int D, double beta, const double *__restrict_
     }
 }
 
-// One-sided (Hestenes) Jacobi on the rows of W [n][len]: plane rotations of
-// row pairs, in the parallel round-robin order, until every pair is
-// orthogonal to relative tolerance 4*len*eps; the same rotations are applied
-// to the rows of Ut [n][n] (so that M = Ut^T W holds throughout).  Rows whose
-// squared norm is below (len*eps)^2 ||W||_F^2 are numerically zero: they are
-// not rotated and *zero2 receives that threshold so the caller drops them.
-// Returns the number of sweeps, or -1 without convergence.
-__device__ int wg_jacobi(double *W, double *Ut, int n, int len, int *flag, double *red,
-                         double *zero2) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const double eps = 2.220446049250313e-16;
-    double f2 = 0.0;
-    for (int t = threadIdx.x; t < n * len; t += blockDim.x) f2 += W[t] * W[t];
-    f2 = tn_block_sum(f2, red);
-    const double small2 = f2 * (len * eps) * (len * eps);
-    *zero2 = small2;
+// The factorisations below split the workgroup into rows of 16 lanes: one
+// row of lanes per trailing column (QR) or per row pair (Jacobi), with
+// 16-lane reductions on the VALU, so that the four 16-lane rows of a
+// wavefront share every instruction.
+#define TN_QW (threadIdx.x >> 4)          // 16-lane row index within the workgroup
+#define TN_QL (threadIdx.x & 15)          // lane within the row
+#define TN_NQW ((int)(blockDim.x >> 4))
+
+// Householder QR of A (m x n, column-major, A[j*lda + i] = A(i, j)): R in
+// the upper triangle, reflector j = (1, A(j+1:, j)) with coefficient tau[j].
+// Column-major storage keeps the 16 lanes of a row on consecutive words.
+__device__ void qw_householder(double *A, int m, int n, int lda, double *tau) {
+    const int kk = min(m, n);
+    for (int j = 0; j < kk; ++j) {
+        double *Aj = A + (size_t)j * lda;
+        if (TN_QW == 0) {
+            double s2 = 0.0;
+            for (int i = j + 1 + TN_QL; i < m; i += 16) s2 += Aj[i] * Aj[i];
+            s2 = tn_row16_sum(s2);
+            const double alpha = Aj[j];
+            double t = 0.0, scl = 0.0, beta = alpha;
+            if (s2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+                t = (beta - alpha) / beta;
+                scl = 1.0 / (alpha - beta);
+            }
+            for (int i = j + 1 + TN_QL; i < m; i += 16) Aj[i] *= scl;
+            if (TN_QL == 0) {
+                Aj[j] = beta;
+                tau[j] = t;
+            }
+        }
+        __syncthreads();
+        const double t = tau[j];
+        if (t != 0.0) {
+            for (int l = j + 1 + TN_QW; l < n; l += TN_NQW) {
+                double *Al = A + (size_t)l * lda;
+                double dot = 0.0;
+                for (int i = j + TN_QL; i < m; i += 16) dot += (i == j ? 1.0 : Aj[i]) * Al[i];
+                dot = tn_row16_sum(dot) * t;
+                for (int i = j + TN_QL; i < m; i += 16) Al[i] -= dot * (i == j ? 1.0 : Aj[i]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Q (m x kk, column-major, ld ldq) = H_0 ... H_{kk-1} [I; 0] from the
+// reflectors in A (as left by qw_householder).
+__device__ void qw_form_q(const double *A, int m, int n, int lda, const double *tau, double *Q,
+                          int ldq) {
+    const int kk = min(m, n);
+    for (int t = threadIdx.x; t < m * kk; t += blockDim.x) {
+        const int l = t / m, i = t % m;
+        Q[(size_t)l * ldq + i] = (i == l) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = kk - 1; j >= 0; --j) {
+        const double tj = tau[j];
+        const double *Aj = A + (size_t)j * lda;
+        if (tj != 0.0) {
+            for (int l = j + TN_QW; l < kk; l += TN_NQW) {
+                double *Ql = Q + (size_t)l * ldq;
+                double dot = 0.0;
+                for (int i = j + TN_QL; i < m; i += 16) dot += (i == j ? 1.0 : Aj[i]) * Ql[i];
+                dot = tn_row16_sum(dot) * tj;
+                for (int i = j + TN_QL; i < m; i += 16) Ql[i] -= dot * (i == j ? 1.0 : Aj[i]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One-sided (Hestenes) Jacobi on the rows of W [n][len] (ld ldw, len <= 128):
+// plane rotations of row pairs in the parallel round-robin order, until every
+// pair is orthogonal to relative tolerance 4*len*eps.  Rows whose squared norm
+// is below small2 = (len*eps)^2 ||W||_F^2 are numerically zero and not rotated.
+// The squared row norms are recomputed at the start of every sweep and
+// updated exactly by each rotation (a - t g, b + t g), so a pair needs only its
+// inner product.  Returns the number of sweeps, or -1 without convergence.
+__device__ int qw_jacobi(double *W, int n, int len, int ldw, double small2, double *nrm,
+                         int *flag) {
     if (n <= 1) return 0;
-    const int npad = n + (n & 1);
-    const double tol = 4.0 * len * eps;
+    const int npad = n + (n & 1), nr = npad - 1;
+    const int nq = (len + 15) >> 4;   // 16-wide slices per row (rows are zero padded)
+    const double tol = 4.0 * len * 2.220446049250313e-16;
+    const double tol2 = tol * tol;
     for (int sweep = 0; sweep < 60; ++sweep) {
+        for (int i = TN_QW; i < n; i += TN_NQW) {
+            double s2 = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                const double v = W[i * ldw + TN_QL + 16 * q];
+                s2 += v * v;
+            }
+            s2 = tn_row16_sum(s2);
+            if (TN_QL == 0) nrm[i] = s2;
+        }
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
-        for (int t = 0; t < npad - 1; ++t) {
-            for (int p = w; p < npad / 2; p += nw) {
+        for (int t = 0; t < nr; ++t) {
+            for (int p = TN_QW; p < npad / 2; p += TN_NQW) {
                 int i, j;
                 if (p == 0) {
-                    i = npad - 1;
+                    i = nr;
                     j = t;
                 } else {
-                    i = (t + p) % (npad - 1);
-                    j = (t - p + npad - 1) % (npad - 1);
+                    i = t + p;
+                    if (i >= nr) i -= nr;
+                    j = t - p;
+                    if (j < 0) j += nr;
                 }
                 if (i >= n || j >= n) continue;
-                double a = 0.0, b = 0.0, g = 0.0;
-                for (int e = lane; e < len; e += 64) {
-                    const double x = W[i * len + e], y = W[j * len + e];
-                    a += x * x;
-                    b += y * y;
-                    g += x * y;
+                double x[8], y[8];
+                double g = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (q < nq) {   // uniform
+                        x[q] = W[i * ldw + TN_QL + 16 * q];
+                        y[q] = W[j * ldw + TN_QL + 16 * q];
+                        g += x[q] * y[q];
+                    }
                 }
-                a = tn_wave_sum(a);
-                b = tn_wave_sum(b);
-                g = tn_wave_sum(g);
-                if (a > small2 && b > small2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-                    const double zeta = (b - a) / (2.0 * g);
-                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-                    for (int e = lane; e < len; e += 64) {
-                        const double x = W[i * len + e], y = W[j * len + e];
-                        W[i * len + e] = cs * x - sn * y;
-                        W[j * len + e] = sn * x + cs * y;
+                g = tn_row16_sum(g);
+                const double a = nrm[i], b = nrm[j];
+                if (a > small2 && b > small2 && g * g > tol2 * a * b) {
+                    // t = tan of the angle that makes the pair orthogonal
+                    const double d = b - a;
+                    const double tt = copysign(1.0, d) * (2.0 * g) / (fabs(d) + sqrt(d * d + 4.0 * g * g));
+                    const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        if (q < nq) {
+                            W[i * ldw + TN_QL + 16 * q] = cs * x[q] - sn * y[q];
+                            W[j * ldw + TN_QL + 16 * q] = sn * x[q] + cs * y[q];
+                        }
                     }
-                    for (int e = lane; e < n; e += 64) {
-                        const double x = Ut[i * n + e], y = Ut[j * n + e];
-                        Ut[i * n + e] = cs * x - sn * y;
-                        Ut[j * n + e] = sn * x + cs * y;
+                    if (TN_QL == 0) {
+                        nrm[i] = fmax(a - tt * g, 0.0);
+                        nrm[j] = b + tt * g;
+                        *flag = 1;
                     }
-                    if (lane == 0) *flag = 1;
                 }
             }
             __syncthreads();
@@ -142,30 +224,49 @@ __device__ int wg_jacobi(double *W, double *Ut, int n, int len, int *flag, doubl
     return -1;
 }
 
+// Doubles of the SVD matrix (2D rows, zero padded to 16-wide slices, odd
+// leading dimension) and of one work area (an 4D x 2D matrix with an odd
+// leading dimension, or the SVD matrix and its copy).
+__host__ __device__ constexpr size_t tn_svd_area(int D) {
+    return (size_t)2 * D * ((((size_t)2 * D + 15) & ~(size_t)15) + 1);
+}
+__host__ __device__ constexpr size_t tn_qr_area(int D) {
+    return (size_t)8 * D * D + 4 * D > 2 * tn_svd_area(D) ? (size_t)8 * D * D + 4 * D
+                                                            : 2 * tn_svd_area(D);
+}
+
 // Compress the MPO-MPS product of row k held in xbox and store env k.
-// LDS layout (when it fits; else the same layout in global `gwork`):
-//   B1 [8 D^2]  QR matrix / SVD matrix (first 4D^2) + SVD product (last 4D^2)
-//   B2 [8 D^2]  explicit Q / R X product / U^T
+// Work areas (doubles): QA [8 D^2 + 4 D] the QR matrix, later the SVD matrix
+// W and a copy of it; QB (same size) Q, then the staged right neighbour,
+// later Z = U S and Y = X_{c-1} Z.  QLDS: QA and QB in LDS (D <= 32);
+// otherwise they are in global `gwork` and only W sits in LDS.
+template <bool QLDS>
 __global__ void __launch_bounds__(1024)
 k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict__ xdims,
                double *__restrict__ env, int *__restrict__ dims, double *__restrict__ ell,
-               double *__restrict__ gwork, int use_lds,
-               unsigned long long *__restrict__ counters, int *__restrict__ cst) {
+               double *__restrict__ gwork, unsigned long long *__restrict__ counters,
+               int *__restrict__ cst) {
     extern __shared__ double lds[];
     __shared__ double tau[2 * TN_MAX_D];
     __shared__ double sv[2 * TN_MAX_D];
+    __shared__ double nrm[2 * TN_MAX_D];
     __shared__ int idx[2 * TN_MAX_D];
     __shared__ int mX[4 * TN_MAX_D + 1], nX[4 * TN_MAX_D + 1];
     __shared__ double red[16];
     __shared__ int flag;
-    __shared__ double zero2;
     __shared__ int cmin;
     if (threadIdx.x == 0) cmin = -1;
 
-    double *B1 = use_lds ? lds : gwork;
-    double *B2 = B1 + 8 * D * D;
+    const size_t D2 = (size_t)D * D;
+    const size_t SZ = tn_qr_area(D);       // one work area, padded leading dimensions
+    double *QA = QLDS ? lds : gwork;
+    double *QB = QA + SZ;
+    double *W = lds;                       // SVD matrix (aliases QA when QLDS)
+    double *Worig = QA + tn_svd_area(D);   // its unrotated copy
+    double *Z = QB, *Y = QB + 2 * D2;
     const int ld = 2 * D;
-    const size_t box = (size_t)8 * D * D;
+    const size_t box = (size_t)8 * D2;
+    const double eps = 2.220446049250313e-16;
 
     for (int c = threadIdx.x; c < Lx; c += blockDim.x) {
         mX[c] = xdims[c];
@@ -177,30 +278,32 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
     for (int c = 0; c + 1 < Lx; ++c) {
         double *X = xbox + c * box, *Xn = xbox + (c + 1) * box;
         const int m = 2 * mX[c], n = nX[c], n1 = nX[c + 1];
+        const int lda = m | 1;   // odd leading dimension: lanes of a row on distinct banks
         for (int t = threadIdx.x; t < m * n; t += blockDim.x) {
             const int r = t / n, j = t % n;
-            B1[t] = X[r * ld + j];
+            QA[(size_t)j * lda + r] = X[r * ld + j];
         }
         __syncthreads();
-        wg_householder(B1, m, n, tau);
+        qw_householder(QA, m, n, lda, tau);
         const int kk = min(m, n);
-        wg_form_q(B1, m, n, tau, B2, kk);
+        qw_form_q(QA, m, n, lda, tau, QB, lda);
         for (int t = threadIdx.x; t < m * kk; t += blockDim.x) {
-            const int r = t / kk, p = t % kk;
-            X[r * ld + p] = B2[t];
+            const int r = t / kk, l = t % kk;
+            X[r * ld + l] = QB[(size_t)l * lda + r];
         }
         __syncthreads();
-        // T[p][(u,j)] = sum_{q >= p} R[p][q] X_{c+1}[q][u][j]
-        for (int t = threadIdx.x; t < kk * 2 * n1; t += blockDim.x) {
-            const int p = t / (2 * n1), rem = t % (2 * n1), u = rem / n1, j = rem % n1;
+        // stage X_{c+1} [q][(u, j)] (n rows), then T = R X_{c+1} into its first kk rows
+        const int w1 = 2 * n1;
+        for (int t = threadIdx.x; t < n * w1; t += blockDim.x) {
+            const int q = t / w1, e = t % w1;
+            QB[t] = Xn[(q * 2 + e / n1) * ld + e % n1];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < kk * w1; t += blockDim.x) {
+            const int p = t / w1, e = t % w1;
             double acc = 0.0;
-            for (int q = p; q < n; ++q) acc += B1[p * n + q] * Xn[(q * 2 + u) * ld + j];
-            B2[t] = acc;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < kk * 2 * n1; t += blockDim.x) {
-            const int p = t / (2 * n1), rem = t % (2 * n1), u = rem / n1, j = rem % n1;
-            Xn[(p * 2 + u) * ld + j] = B2[t];
+            for (int q = p; q < n; ++q) acc += QA[(size_t)q * lda + p] * QB[q * w1 + e];
+            Xn[(p * 2 + e / n1) * ld + e % n1] = acc;
         }
         if (threadIdx.x == 0) {
             mX[c + 1] = kk;
@@ -234,24 +337,25 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
     for (int c = Lx - 1; c >= 1; --c) {
         double *X = xbox + c * box, *Xp = xbox + (c - 1) * box;
         const int rows = mX[c], ncol = nX[c], len = 2 * ncol;
-        double *W = B1, *T = B1 + 4 * D * D, *Ut = B2;
-        for (int t = threadIdx.x; t < rows * len; t += blockDim.x) {
-            const int i = t / len, e = t % len, u = e / ncol, j = e % ncol;
-            W[t] = X[(i * 2 + u) * ld + j];
+        const int lenp = (len + 15) & ~15;   // zero padded to 16-wide slices
+        const int ldw = lenp | 1;            // odd: rows of W on distinct banks
+        double f2 = 0.0;
+        for (int t = threadIdx.x; t < rows * lenp; t += blockDim.x) {
+            const int i = t / lenp, e = t % lenp;
+            const double v = e < len ? X[(i * 2 + e / ncol) * ld + e % ncol] : 0.0;
+            W[i * ldw + e] = v;
+            Worig[i * ldw + e] = v;
+            f2 += v * v;
         }
-        for (int t = threadIdx.x; t < rows * rows; t += blockDim.x)
-            Ut[t] = (t / rows == t % rows) ? 1.0 : 0.0;
-        __syncthreads();
-        const int sweeps = wg_jacobi(W, Ut, rows, len, &flag, red, &zero2);
+        f2 = tn_block_sum(f2, red);
+        const double zero2 = f2 * (len * eps) * (len * eps);
+        const int sweeps = qw_jacobi(W, rows, len, ldw, zero2, nrm, &flag);
         if (sweeps < 0 && threadIdx.x == 0) atomicAdd(&counters[CNT_NOCONV], 1ull);
-        {
-            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-            for (int i = w; i < rows; i += nw) {
-                double s2 = 0.0;
-                for (int e = lane; e < len; e += 64) s2 += W[i * len + e] * W[i * len + e];
-                s2 = tn_wave_sum(s2);
-                if (lane == 0) sv[i] = s2 > zero2 ? sqrt(s2) : 0.0;
-            }
+        for (int i = TN_QW; i < rows; i += TN_NQW) {
+            double s2 = 0.0;
+            for (int e = TN_QL; e < lenp; e += 16) s2 += W[i * ldw + e] * W[i * ldw + e];
+            s2 = tn_row16_sum(s2);
+            if (TN_QL == 0) sv[i] = s2 > zero2 ? sqrt(s2) : 0.0;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < rows; i += blockDim.x) {
@@ -268,26 +372,35 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
             if (sv[idx[chi - 1]] - sv[idx[chi]] < 1e-12 * sv[idx[0]])
                 atomicAdd(&counters[CNT_DEGEN], 1ull);
         }
-        // X_{c-1} <- X_{c-1} U[:, :chi] S[:chi]   (into T first)
-        const int m1 = 2 * mX[c - 1];
-        for (int t = threadIdx.x; t < m1 * chi; t += blockDim.x) {
-            const int r = t / chi, kq = t % chi, ik = idx[kq];
-            double acc = 0.0;
-            for (int q = 0; q < rows; ++q) acc += Xp[r * ld + q] * Ut[ik * rows + q];
-            T[t] = acc * sv[ik];
-        }
-        // X_c <- V^T[:chi]
-        for (int t = threadIdx.x; t < chi * len; t += blockDim.x) {
-            const int kq = t / len, e = t % len, u = e / ncol, j = e % ncol;
-            const int ik = idx[kq];
+        // Z = U[:, :chi] S[:chi] = Worig W'[idx]^T / s  (the rotated rows are S V^T);
+        // consecutive threads take consecutive rows r of Worig for one kept row
+        for (int t = threadIdx.x; t < rows * chi; t += blockDim.x) {
+            const int kq = t / rows, r = t % rows, ik = idx[kq];
             const double s = sv[ik];
-            X[(kq * 2 + u) * ld + j] = s > 0.0 ? W[ik * len + e] / s : 0.0;
+            double acc = 0.0;
+            if (s > 0.0) {
+                for (int e = 0; e < len; ++e) acc += Worig[r * ldw + e] * W[ik * ldw + e];
+                acc /= s;
+            }
+            Z[r * chi + kq] = acc;
         }
         __syncthreads();
+        // Y = X_{c-1} Z, X_c <- V^T[:chi]
+        const int m1 = 2 * mX[c - 1];
         for (int t = threadIdx.x; t < m1 * chi; t += blockDim.x) {
             const int r = t / chi, kq = t % chi;
-            Xp[r * ld + kq] = T[t];
+            double acc = 0.0;
+            for (int q = 0; q < rows; ++q) acc += Xp[r * ld + q] * Z[q * chi + kq];
+            Y[t] = acc;
         }
+        for (int t = threadIdx.x; t < chi * len; t += blockDim.x) {
+            const int kq = t / len, e = t % len;
+            const int ik = idx[kq];
+            const double s = sv[ik];
+            X[(kq * 2 + e / ncol) * ld + e % ncol] = s > 0.0 ? W[ik * ldw + e] / s : 0.0;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < m1 * chi; t += blockDim.x) Xp[(t / chi) * ld + t % chi] = Y[t];
         if (threadIdx.x == 0) {
             mX[c] = chi;
             nX[c - 1] = chi;
@@ -421,8 +534,10 @@ int tn_env_build_device(tn_ctx *ctx, double *logZ_out) {
     int rc;
     if ((rc = tn_ensure(ctx, (void **)&ctx->xbox, &ctx->xbox_cap, Lx * box * sizeof(double))))
         return rc;
+    // QR work areas in LDS when they fit (D <= 32), else in global memory
+    // with the SVD matrix alone in LDS
     const bool use_lds = D <= 32;
-    const size_t work = (size_t)16 * D * D;
+    const size_t work = 2 * tn_qr_area(D);
     if (!use_lds &&
         (rc = tn_ensure(ctx, (void **)&ctx->wbuf, &ctx->wbuf_cap, work * sizeof(double))))
         return rc;
@@ -432,11 +547,17 @@ int tn_env_build_device(tn_ctx *ctx, double *logZ_out) {
     hipLaunchKernelGGL(k_fill_dims, dim3(1), dim3(256), 0, ctx->stream,
                        ctx->dims + (size_t)Ly * (Lx + 1), Lx + 1, 1);
     TN_HIP(ctx, hipGetLastError());
-    const size_t lds_bytes = use_lds ? work * sizeof(double) : 0;
+    const size_t lds_bytes = (use_lds ? work : tn_svd_area(D)) * sizeof(double);
     if (use_lds)
-        TN_HIP(ctx, hipFuncSetAttribute((const void *)k_truncate_row,
+        TN_HIP(ctx, hipFuncSetAttribute((const void *)k_truncate_row<true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)lds_bytes));
+    else
+        TN_HIP(ctx, hipFuncSetAttribute((const void *)k_truncate_row<false>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_bytes));
+    // one 16-lane row per row pair of the largest SVD matrix (2 D rows)
+    const int nthr = D <= 32 ? 512 : 1024;
     TN_HIP(ctx, hipMemsetAsync(ctx->counters + CNT_NOCONV, 0, sizeof(unsigned long long),
                                ctx->stream));
     for (int k = Ly - 1; k >= 1; --k) {
@@ -444,9 +565,14 @@ int tn_env_build_device(tn_ctx *ctx, double *logZ_out) {
                            ctx->beta, ctx->Jh, ctx->Jv, ctx->h, ctx->env, ctx->dims,
                            ctx->xbox, ctx->xdims);
         TN_HIP(ctx, hipGetLastError());
-        hipLaunchKernelGGL(k_truncate_row, dim3(1), dim3(1024), lds_bytes, ctx->stream, k, Lx,
-                           D, ctx->xbox, ctx->xdims, ctx->env, ctx->dims, ctx->ell,
-                           ctx->wbuf, use_lds ? 1 : 0, ctx->counters, ctx->cst);
+        if (use_lds)
+            hipLaunchKernelGGL(k_truncate_row<true>, dim3(1), dim3(nthr), lds_bytes, ctx->stream,
+                               k, Lx, D, ctx->xbox, ctx->xdims, ctx->env, ctx->dims, ctx->ell,
+                               nullptr, ctx->counters, ctx->cst);
+        else
+            hipLaunchKernelGGL(k_truncate_row<false>, dim3(1), dim3(nthr), lds_bytes, ctx->stream,
+                               k, Lx, D, ctx->xbox, ctx->xdims, ctx->env, ctx->dims, ctx->ell,
+                               ctx->wbuf, ctx->counters, ctx->cst);
         TN_HIP(ctx, hipGetLastError());
     }
     double logtop, sign;
