@@ -171,6 +171,52 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
               int8_t *state_spins, double *state_logq, double *state_energy,
               uint8_t *accepted, double *energy_series);
 
+/* ---- Batched uneven instances -------------------------------------------
+ * Many independent instances (lattice, couplings, beta, bond cap) sampled
+ * together: their environment builds run side by side (one workgroup per
+ * instance), and one MH step of all their chains is one sampler launch per
+ * bond class (D rounded up to 16) and one acceptance launch.  Instance i draws
+ * with Philox instance number i (counter word 3 = i << 2 | stream). */
+typedef struct {
+    int Lx, Ly, D;
+    double beta;
+    const double *Jh, *Jv, *h;   /* dev, fp64, as in tn_build_env (h may be NULL) */
+    int chains;                  /* chains of this instance in tn_mh_step_multi */
+} tn_instance;
+
+/* Build the environments of n instances (the batched context's own ones,
+ * replacing earlier ones); logZ_out (host, fp64 [n], may be NULL) receives
+ * ln Z~ per instance.  prec as in tn_build_env for all instances.  Errors name
+ * the first failing instance; synchronises. */
+int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, double *logZ_out);
+
+/* One MH step (Algorithm 1) of every chain of every instance: the arrays hold
+ * n host pointers each, entry i pointing to instance i's device state
+ * (spins int8 [chains_i][Ly_i][Lx_i], logq and energy fp64 [chains_i],
+ * accepted uint8 [chains_i]).  Chains are bitwise those tn_mh_step gives a
+ * single-instance context with the same instance number. */
+int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *state_spins,
+                     double *const *state_logq, double *const *state_energy,
+                     uint8_t *const *accepted);
+
+/* Instance i of a batched context as a context of its own, borrowed (owned
+ * and destroyed by ctx, valid until the next tn_build_env_multi): every
+ * single-instance call applies to it (tn_eval_logq for initial states,
+ * tn_sample, tn_mh_step, tn_stats, tn_grad).  NULL when i is out of range. */
+tn_ctx *tn_multi_instance(tn_ctx *ctx, int i);
+
+/* Capture the following tn_mh_step / tn_mh_step_multi calls of this context
+ * (consecutive steps) into a HIP graph instead of running them.  The context
+ * must have been created with a stream other than the legacy default one, and
+ * every captured call must have been made once before (same chain counts and
+ * state buffers: no allocation happens while capturing). */
+int tn_graph_begin(tn_ctx *ctx);
+
+/* End the capture and replay the graph n_replays times: replay r runs the
+ * captured steps shifted by r times their count, so the replays continue the
+ * captured sequence step by step (bitwise the eager calls). */
+int tn_graph_end_and_replay(tn_ctx *ctx, int n_replays);
+
 /* Derivative of ln Z~ with the truncation isometries frozen: every
  * compression step of the environment build is replaced by the orthogonal
  * projector onto the span kept at its leftmost truncated bond (the identity

@@ -34,12 +34,21 @@ int tn_ensure(tn_ctx *ctx, void **ptr, size_t *cap, size_t bytes) {
 namespace {
 
 void free_all(tn_ctx *ctx) {
+    for (tn_ctx *k : ctx->kids) {
+        free_all(k);
+        delete k;
+    }
+    ctx->kids.clear();
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
                     ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters,
-                    ctx->cst,   ctx->gradscr};
+                    ctx->cst,   ctx->gradscr, ctx->descs,
+                    ctx->own_dstep ? (void *)ctx->dstep : nullptr};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
+    for (void *p : ctx->mdesc) (void)hipFree(p);
+    ctx->mdesc.clear();
+    ctx->mdesc_host.clear();
 }
 
 int check_prec(tn_ctx *ctx, int prec) {
@@ -117,6 +126,8 @@ int tn_create(tn_ctx **out, void *hip_stream) {
     if (hipGetDevice(&ctx->device) != hipSuccess ||
         hipMalloc((void **)&ctx->counters, CNT_N * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void **)&ctx->scal, 16 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&ctx->dstep, sizeof(uint64_t)) != hipSuccess ||
+        hipMemset(ctx->dstep, 0, sizeof(uint64_t)) != hipSuccess ||
         hipMalloc((void **)&ctx->xdims, 4096 * sizeof(int)) != hipSuccess ||
         hipMemset(ctx->counters, 0, CNT_N * sizeof(unsigned long long)) != hipSuccess) {
         (void)hipGetLastError();
@@ -277,6 +288,8 @@ int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *st
     const size_t spin_bytes = ((chains * nsite + 255) / 256) * 256;
     const size_t need = spin_bytes + 2 * (size_t)chains * sizeof(double);
     if (need > ctx->pcap) {
+        if (ctx->capturing)
+            return tn_fail(ctx, TN_ESTATE, "buffers not allocated: run the step once before capture");
         void *p = ctx->pspins;
         if ((rc = tn_ensure(ctx, &p, &ctx->pcap, need))) return rc;
         ctx->pspins = (int8_t *)p;
@@ -284,8 +297,11 @@ int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *st
     ctx->plogq = (double *)(ctx->pspins + spin_bytes);
     ctx->pE = ctx->plogq + chains;
     if ((rc = tn_sample(ctx, chains, seed, step, 0, ctx->pspins, ctx->plogq, ctx->pE))) return rc;
-    return tn_launch_accept(ctx, chains, seed, step, ctx->pspins, ctx->plogq, ctx->pE,
-                            state_spins, state_logq, state_energy, accepted);
+    if ((rc = tn_launch_accept(ctx, chains, seed, step, ctx->pspins, ctx->plogq, ctx->pE,
+                               state_spins, state_logq, state_energy, accepted)))
+        return rc;
+    if (ctx->capturing) ++ctx->graph_steps;
+    return TN_OK;
 }
 
 int tn_sample_steps(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0,
@@ -369,6 +385,258 @@ int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
         return tn_fail(ctx, TN_EINVAL, "NULL buffer");
     return tn_launch_accept(ctx, chains, seed, step, prop_spins, prop_logq, prop_energy,
                             state_spins, state_logq, state_energy, accepted);
+}
+
+// ---- batched uneven instances -------------------------------------------
+
+int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, double *logZ_out) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
+    if (n < 1 || !inst) return tn_fail(ctx, TN_EINVAL, "need n >= 1 instances");
+    int rc;
+    if ((rc = check_prec(ctx, prec))) return rc;
+    for (int i = 0; i < n; ++i)
+        if (inst[i].chains < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0");
+    while ((int)ctx->kids.size() > n) {
+        tn_ctx *k = ctx->kids.back();
+        ctx->kids.pop_back();
+        free_all(k);
+        delete k;
+    }
+    while ((int)ctx->kids.size() < n) {
+        tn_ctx *k = new (std::nothrow) tn_ctx();
+        if (!k) return tn_fail(ctx, TN_ENOMEM, "out of host memory");
+        k->stream = ctx->stream;
+        k->device = ctx->device;
+        k->dstep = ctx->dstep;   // the instances follow the batched context's step base
+        k->own_dstep = false;
+        ctx->kids.push_back(k);
+        if (hipMalloc((void **)&k->counters, CNT_N * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc((void **)&k->scal, 16 * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&k->xdims, 4096 * sizeof(int)) != hipSuccess ||
+            hipMemset(k->counters, 0, CNT_N * sizeof(unsigned long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            return tn_fail(ctx, TN_ENOMEM, "device allocation failed");
+        }
+    }
+    ctx->has_multi = false;
+    ctx->kid_chains.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *k = ctx->kids[i];
+        k->err.clear();
+        k->has_env = false;
+        const tn_instance &I = inst[i];
+        if ((rc = set_instance(k, I.Lx, I.Ly, I.Jh, I.Jv, I.h, I.beta, I.D, prec)))
+            return tn_fail(ctx, rc, "instance " + std::to_string(i) + ": " + k->err);
+        k->inst = i;
+        ctx->kid_chains[i] = I.chains;
+    }
+    std::string e;
+    if ((rc = tn_env_build_many(ctx->kids.data(), n, ctx->stream, &e))) return tn_fail(ctx, rc, e);
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *k = ctx->kids[i];
+        if ((rc = tn_make_operands(k, prec)))
+            return tn_fail(ctx, rc, "instance " + std::to_string(i) + ": " + k->err);
+        k->has_env = true;
+        k->has_cst = true;
+        if (logZ_out) logZ_out[i] = k->logZ;
+    }
+    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (void *p : ctx->mdesc) (void)hipFree(p);
+    ctx->mdesc.clear();
+    ctx->mdesc_host.clear();
+    ctx->has_multi = true;
+    return TN_OK;
+}
+
+int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *state_spins,
+                     double *const *state_logq, double *const *state_energy,
+                     uint8_t *const *accepted) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (!ctx->has_multi) return tn_fail(ctx, TN_ESTATE, "no instances: call tn_build_env_multi first");
+    if (!state_spins || !state_logq || !state_energy || !accepted)
+        return tn_fail(ctx, TN_EINVAL, "NULL state array");
+    const int n = (int)ctx->kids.size();
+    int rc;
+    // proposal buffers and sampler scratch per instance (allocated on first use)
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *k = ctx->kids[i];
+        const int C = ctx->kid_chains[i];
+        if (C > 0 && (!state_spins[i] || !state_logq[i] || !state_energy[i] || !accepted[i]))
+            return tn_fail(ctx, TN_EINVAL, "NULL state buffer of instance " + std::to_string(i));
+        const size_t nsite = (size_t)k->Lx * k->Ly;
+        const size_t spin_bytes = (((size_t)C * nsite + 255) / 256) * 256;
+        const size_t need = spin_bytes + 2 * (size_t)C * sizeof(double);
+        const size_t gneed = k->prec == TN_FP64 ? (size_t)C * k->Lx * 2 * k->D * sizeof(double)
+                                                : tn_mfma_scratch_bytes(k, C);
+        if ((need > k->pcap || gneed > k->gscr_cap) && ctx->capturing)
+            return tn_fail(ctx, TN_ESTATE, "buffers not allocated: run the step once before capture");
+        if (need > k->pcap) {
+            void *p = k->pspins;
+            if ((rc = tn_ensure(k, &p, &k->pcap, need))) return tn_fail(ctx, rc, k->err);
+            k->pspins = (int8_t *)p;
+        }
+        if (gneed > k->gscr_cap && (rc = tn_ensure(k, &k->gscr, &k->gscr_cap, gneed)))
+            return tn_fail(ctx, rc, k->err);
+        k->plogq = (double *)(k->pspins + spin_bytes);
+        k->pE = k->plogq + C;
+    }
+    // descriptor tables: sampler descriptors grouped by (bond class, bf16), then
+    // the acceptance descriptors of all instances
+    struct Group {
+        int NT;
+        bool bf16;
+        int first, count, blocks, maxLx;
+    };
+    std::vector<tn_samp_desc> sd;
+    std::vector<Group> groups;
+    for (int bf = 0; bf < 2; ++bf)
+        for (int NT = 1; NT <= 4; ++NT) {
+            Group g{NT, bf == 1, (int)sd.size(), 0, 0, 1};
+            for (int i = 0; i < n; ++i) {
+                tn_ctx *k = ctx->kids[i];
+                const int C = ctx->kid_chains[i];
+                if (k->prec == TN_FP64 || C == 0 || k->Dp / 16 != NT || (k->prec == TN_BF16) != (bf == 1))
+                    continue;
+                tn_samp_desc A = tn_samp_desc_of(k, C, k->pspins, k->plogq, k->pE,
+                                                 (float *)k->gscr, C, 0);
+                A.blk0 = g.blocks;
+                g.blocks += (C + 15) / 16;
+                g.maxLx = k->Lx > g.maxLx ? k->Lx : g.maxLx;
+                sd.push_back(A);
+                ++g.count;
+            }
+            if (g.count) groups.push_back(g);
+        }
+    std::vector<tn_acc_desc> ad;
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *k = ctx->kids[i];
+        const int C = ctx->kid_chains[i];
+        if (C == 0) continue;
+        tn_acc_desc A;
+        A.chains = C;
+        A.nsite = k->Lx * k->Ly;
+        A.beta = k->beta;
+        A.inst = (uint32_t)k->inst;
+        A.blk0 = total;
+        A.pspins = k->pspins;
+        A.plogq = k->plogq;
+        A.pE = k->pE;
+        A.sspins = state_spins[i];
+        A.slogq = state_logq[i];
+        A.sE = state_energy[i];
+        A.accepted = accepted[i];
+        A.counters = k->counters;
+        ad.push_back(A);
+        total += C;
+    }
+    const size_t sbytes = sd.size() * sizeof(tn_samp_desc);
+    const size_t abytes = ad.size() * sizeof(tn_acc_desc);
+    std::vector<unsigned char> host(sbytes + abytes);
+    if (sbytes) memcpy(host.data(), sd.data(), sbytes);
+    if (abytes) memcpy(host.data() + sbytes, ad.data(), abytes);
+    int slot = -1;
+    for (size_t q = 0; q < ctx->mdesc_host.size(); ++q)
+        if (ctx->mdesc_host[q] == host) slot = (int)q;
+    if (slot < 0) {
+        if (ctx->capturing)
+            return tn_fail(ctx, TN_ESTATE,
+                           "state buffers not seen before capture: run the step once first");
+        if ((int)ctx->mdesc.size() >= TN_MDESC_SETS) {   // forget the oldest set
+            (void)hipFree(ctx->mdesc.front());
+            ctx->mdesc.erase(ctx->mdesc.begin());
+            ctx->mdesc_host.erase(ctx->mdesc_host.begin());
+        }
+        void *p = nullptr;
+        TN_HIP(ctx, hipMalloc(&p, host.size() ? host.size() : 16));
+        ctx->mdesc.push_back(p);
+        ctx->mdesc_host.push_back(host);
+        if (host.size())
+            TN_HIP(ctx, hipMemcpy(p, host.data(), host.size(), hipMemcpyHostToDevice));
+        slot = (int)ctx->mdesc.size() - 1;
+    }
+    const tn_samp_desc *sdev = (const tn_samp_desc *)ctx->mdesc[slot];
+    const tn_acc_desc *adev = (const tn_acc_desc *)((unsigned char *)ctx->mdesc[slot] + sbytes);
+    for (const Group &g : groups)
+        if ((rc = tn_run_mfma_multi(ctx, g.NT, g.bf16, sdev + g.first, g.count, g.blocks, g.maxLx,
+                                    seed, step)))
+            return rc;
+    for (int i = 0; i < n; ++i) {   // plain fp64 instances: one sampler launch each
+        tn_ctx *k = ctx->kids[i];
+        const int C = ctx->kid_chains[i];
+        if (k->prec != TN_FP64 || C == 0) continue;
+        if ((rc = tn_run_fp64(k, C, seed, step, C, 0, k->pspins, false, k->plogq, k->pE)))
+            return tn_fail(ctx, rc, k->err);
+    }
+    if ((rc = tn_launch_accept_multi(ctx, adev, (int)ad.size(), total, seed, step))) return rc;
+    if (ctx->capturing) ++ctx->graph_steps;
+    return TN_OK;
+}
+
+tn_ctx *tn_multi_instance(tn_ctx *ctx, int i) {
+    if (!ctx || i < 0 || i >= (int)ctx->kids.size() || !ctx->has_multi) return nullptr;
+    return ctx->kids[i];
+}
+
+namespace {
+__global__ void k_advance_step(unsigned long long *base, unsigned long long by) {
+    if (threadIdx.x == 0) atomicAdd(base, by);
+}
+}  // namespace
+
+int tn_graph_begin(tn_ctx *ctx) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "a capture is already open");
+    if (!ctx->stream)
+        return tn_fail(ctx, TN_EINVAL, "graph capture needs a context stream other than the default");
+    TN_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    ctx->graph_steps = 0;
+    return TN_OK;
+}
+
+int tn_graph_end_and_replay(tn_ctx *ctx, int n_replays) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (!ctx->capturing) return tn_fail(ctx, TN_ESTATE, "no capture is open");
+    // the last node moves the step base on by the captured step count
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, ctx->stream,
+                       (unsigned long long *)ctx->dstep, (unsigned long long)ctx->graph_steps);
+    const hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(ctx->stream, &graph);
+    ctx->capturing = false;
+    if (le != hipSuccess || ee != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return tn_fail(ctx, TN_EHIP, "graph capture failed");
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return tn_fail(ctx, TN_EHIP, "graph instantiation failed");
+    }
+    int rc = TN_OK;
+    if (n_replays < 0) rc = tn_fail(ctx, TN_EINVAL, "n_replays < 0");
+    // replays start from the captured steps; afterwards the base is 0 again
+    if (rc == TN_OK && hipMemsetAsync(ctx->dstep, 0, sizeof(uint64_t), ctx->stream) != hipSuccess)
+        rc = tn_fail(ctx, TN_EHIP, "step base reset failed");
+    for (int r = 0; rc == TN_OK && r < n_replays; ++r)
+        if (hipGraphLaunch(exec, ctx->stream) != hipSuccess) rc = tn_fail(ctx, TN_EHIP, "graph launch failed");
+    if (hipMemsetAsync(ctx->dstep, 0, sizeof(uint64_t), ctx->stream) != hipSuccess && rc == TN_OK)
+        rc = tn_fail(ctx, TN_EHIP, "step base reset failed");
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == TN_OK)
+        rc = tn_fail(ctx, TN_EHIP, "graph replay failed");
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return rc;
 }
 
 int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {

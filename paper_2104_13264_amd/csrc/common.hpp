@@ -5,10 +5,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 #include "../../include/tnmh.h"
 
 #define TN_MAX_D 64
+#define TN_MDESC_SETS 8
 
 // Device counters (uint64) kept per context.
 enum {
@@ -66,6 +68,22 @@ struct tn_ctx {
     double *xbox = nullptr;   // [Lx][2D][2][2D]
     double *wbuf = nullptr;   // global work buffers when LDS is too small
     double *scal = nullptr;   // small device scalars (top overlap result ...)
+    uint64_t *dstep = nullptr;  // device step base added to every MH step (graph replays)
+    bool own_dstep = true;      // false for the instances of a batched context
+
+    // batched uneven instances (tn_build_env_multi): one child context each
+    std::vector<tn_ctx *> kids;
+    std::vector<int> kid_chains;
+    // device descriptor tables of tn_mh_step_multi, one per distinct set of
+    // state buffers seen (at most TN_MDESC_SETS), with their host contents
+    std::vector<void *> mdesc;
+    std::vector<std::vector<unsigned char>> mdesc_host;
+    bool has_multi = false;
+    // graph capture (tn_graph_begin .. tn_graph_end_and_replay)
+    bool capturing = false;
+    int graph_steps = 0;
+    void *descs = nullptr;    // device descriptors of batched launches
+    size_t descs_cap = 0;
     int *xdims = nullptr;     // [2][Lx+1]
     size_t xbox_cap = 0, wbuf_cap = 0;
 
@@ -99,11 +117,76 @@ int tn_fail(tn_ctx *ctx, int code, const std::string &msg);
 int tn_ensure(tn_ctx *ctx, void **ptr, size_t *cap, size_t bytes);
 
 // environment build (env_build.hip)
+// One instance's environment build as the row kernels see it (device copy).
+struct tn_env_desc {
+    int Lx, Ly, D, pad;
+    double beta;
+    const double *Jh, *Jv, *h;
+    double *env;
+    int *dims;
+    double *ell;
+    int *cst;
+    double *xbox;
+    int *xdims;
+    double *wbuf;
+    double *scal;
+    unsigned long long *counters;
+};
+// Builds the environments of n instances together (one workgroup per
+// instance and row step); fills each ctx's logZ.  ctxs[i] must have its
+// instance set (couplings on the device).
+int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err);
 int tn_env_build_device(tn_ctx *ctx, double *logZ_out);
 int tn_make_operands(tn_ctx *ctx, int prec);
-int tn_top_overlap(tn_ctx *ctx, double *logtop, double *sign);
 
 // samplers
+// One instance's batched-sampler launch as the kernel sees it.  Block blk of
+// the instance draws proposals 16 blk .. 16 blk + 15; blk0 is the first block
+// of the instance in a launch over several instances.
+struct tn_samp_desc {
+    int B, Lx, Ly, per_step;
+    const double *Jh, *Jv, *h, *fac;
+    const void *GR, *GL;
+    int8_t *S;
+    double *logq, *energy;
+    float *gscr;
+    uint64_t first_id;
+    uint32_t inst;
+    int blk0;
+    unsigned long long *counters;
+};
+inline tn_samp_desc tn_samp_desc_of(tn_ctx *ctx, int B, int8_t *S, double *logq, double *energy,
+                                    float *gscr, int per_step, uint64_t first_id) {
+    tn_samp_desc A;
+    A.B = B;
+    A.Lx = ctx->Lx;
+    A.Ly = ctx->Ly;
+    A.per_step = per_step;
+    A.Jh = ctx->Jh;
+    A.Jv = ctx->Jv;
+    A.h = ctx->h;
+    A.fac = ctx->fac;
+    const bool bf16 = ctx->prec == TN_BF16;
+    A.GR = bf16 ? (const void *)ctx->G16R : (const void *)ctx->G32R;
+    A.GL = bf16 ? (const void *)ctx->G16L : (const void *)ctx->G32L;
+    A.S = S;
+    A.logq = logq;
+    A.energy = energy;
+    A.gscr = gscr;
+    A.first_id = first_id;
+    A.inst = (uint32_t)ctx->inst;
+    A.blk0 = 0;
+    A.counters = ctx->counters;
+    return A;
+}
+// Scratch bytes of the batched sampler for `batch` proposals.
+inline size_t tn_mfma_scratch_bytes(const tn_ctx *ctx, int batch) {
+    const int blocks = (batch + 15) / 16;
+    return (size_t)blocks * 2 * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
+}
+int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, const tn_samp_desc *descs, int n, int blocks,
+                      int maxLx, uint64_t seed, uint64_t step0);
+
 // Samplers: proposal j of a launch has id first_id + j % per_step and MH step
 // step0 + j / per_step.
 int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
@@ -114,6 +197,21 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
                 double *energy);
 
 // MH accept kernel launcher (mh.hip)
+// One instance's MH acceptance launch as the kernel sees it.
+struct tn_acc_desc {
+    int chains, nsite;
+    double beta;
+    uint32_t inst;
+    int blk0;
+    const int8_t *pspins;
+    const double *plogq, *pE;
+    int8_t *sspins;
+    double *slogq, *sE;
+    uint8_t *accepted;
+    unsigned long long *counters;
+};
+int tn_launch_accept_multi(tn_ctx *ctx, const tn_acc_desc *descs, int n, int total_chains,
+                           uint64_t seed, uint64_t step);
 int tn_launch_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                      const int8_t *prop_spins, const double *prop_logq,
                      const double *prop_energy, int8_t *state_spins, double *state_logq,

@@ -23,52 +23,54 @@ __global__ void k_fill_dims(int *dims, int n, int v) {
 }
 
 // X_c = sum_d env_{k+1,c}[a,d,b] M_{k,c}[l,u,d,x],  M = sum_s of the site
-// tensor of App. A Eq. (tensor-general) with the field factor exp(beta h s).
-__global__ void __launch_bounds__(256)
-k_mpo_apply(int k, int Lx, int Ly, int D, double beta, const double *__restrict__ Jh,
-            const double *__restrict__ Jv, const double *__restrict__ h,
-            const double *__restrict__ env, const int *__restrict__ dims,
-            double *__restrict__ xbox, int *__restrict__ xdims) {
-    const int c = blockIdx.x;
+// tensor of App. A Eq. (tensor-general) with the field factor exp(beta h s);
+// every column of row k, by the whole workgroup.
+__device__ void mpo_apply_row(const tn_env_desc &dsc, int k) {
     __shared__ double M[2][2][2][2];   // [l][u][d][x]
-    const int lw = c > 0 ? 2 : 1, xw = c < Lx - 1 ? 2 : 1, dw = k < Ly - 1 ? 2 : 1;
-    const bool triv = (k == Ly - 1);
-    const int Dl = triv ? 1 : dims[(k + 1) * (Lx + 1) + c];
-    const int Dr = triv ? 1 : dims[(k + 1) * (Lx + 1) + c + 1];
-    if (threadIdx.x < 16) {
-        const int l = (threadIdx.x >> 3) & 1, u = (threadIdx.x >> 2) & 1;
-        const int d = (threadIdx.x >> 1) & 1, x = threadIdx.x & 1;
-        double acc = 0.0;
-        if (l < lw && d < dw && x < xw) {
-            const double hv = h ? h[k * Lx + c] : 0.0;
-            for (int s = 0; s < 2; ++s) {
-                const double f = exp(beta * hv * (s ? -1.0 : 1.0));
-                const double ql = c > 0 ? tn_qleg(beta * Jh[k * (Lx - 1) + c - 1], l, s) : 1.0;
-                const double pr = c < Lx - 1 ? tn_pleg(beta * Jh[k * (Lx - 1) + c], s, x) : 1.0;
-                const double qu = tn_qleg(beta * Jv[(k - 1) * Lx + c], u, s);
-                const double pd = k < Ly - 1 ? tn_pleg(beta * Jv[k * Lx + c], s, d) : 1.0;
-                acc += f * ql * pr * qu * pd;
+    const int Lx = dsc.Lx, Ly = dsc.Ly, D = dsc.D;
+    const double beta = dsc.beta;
+    const double *Jh = dsc.Jh, *Jv = dsc.Jv, *h = dsc.h;
+    for (int c = 0; c < Lx; ++c) {
+        const int lw = c > 0 ? 2 : 1, xw = c < Lx - 1 ? 2 : 1, dw = k < Ly - 1 ? 2 : 1;
+        const bool triv = (k == Ly - 1);
+        const int Dl = triv ? 1 : dsc.dims[(k + 1) * (Lx + 1) + c];
+        const int Dr = triv ? 1 : dsc.dims[(k + 1) * (Lx + 1) + c + 1];
+        if (threadIdx.x < 16) {
+            const int l = (threadIdx.x >> 3) & 1, u = (threadIdx.x >> 2) & 1;
+            const int d = (threadIdx.x >> 1) & 1, x = threadIdx.x & 1;
+            double acc = 0.0;
+            if (l < lw && d < dw && x < xw) {
+                const double hv = h ? h[k * Lx + c] : 0.0;
+                for (int s = 0; s < 2; ++s) {
+                    const double f = exp(beta * hv * (s ? -1.0 : 1.0));
+                    const double ql = c > 0 ? tn_qleg(beta * Jh[k * (Lx - 1) + c - 1], l, s) : 1.0;
+                    const double pr = c < Lx - 1 ? tn_pleg(beta * Jh[k * (Lx - 1) + c], s, x) : 1.0;
+                    const double qu = tn_qleg(beta * Jv[(k - 1) * Lx + c], u, s);
+                    const double pd = k < Ly - 1 ? tn_pleg(beta * Jv[k * Lx + c], s, d) : 1.0;
+                    acc += f * ql * pr * qu * pd;
+                }
             }
+            M[l][u][d][x] = acc;
         }
-        M[l][u][d][x] = acc;
-    }
-    __syncthreads();
-    double *X = xbox + (size_t)c * 8 * D * D;
-    const int m = Dl * lw, n = Dr * xw, ld = 2 * D;
-    const double *E = env + ((size_t)(k + 1) * Lx + c) * 2 * D * D;
-    for (int t = threadIdx.x; t < m * 2 * n; t += blockDim.x) {
-        const int j = t % n, rest = t / n, u = rest & 1, i = rest >> 1;
-        const int a = i / lw, l = i % lw, b = j / xw, x = j % xw;
-        double acc = 0.0;
-        for (int d = 0; d < dw; ++d) {
-            const double e = triv ? 1.0 : E[a * 2 * D + d * D + b];
-            acc += e * M[l][u][d][x];
+        __syncthreads();
+        double *X = dsc.xbox + (size_t)c * 8 * D * D;
+        const int m = Dl * lw, n = Dr * xw, ld = 2 * D;
+        const double *E = dsc.env + ((size_t)(k + 1) * Lx + c) * 2 * D * D;
+        for (int t = threadIdx.x; t < m * 2 * n; t += blockDim.x) {
+            const int j = t % n, rest = t / n, u = rest & 1, i = rest >> 1;
+            const int a = i / lw, l = i % lw, b = j / xw, x = j % xw;
+            double acc = 0.0;
+            for (int d = 0; d < dw; ++d) {
+                const double e = triv ? 1.0 : E[a * 2 * D + d * D + b];
+                acc += e * M[l][u][d][x];
+            }
+            X[(i * 2 + u) * ld + j] = acc;
         }
-        X[(i * 2 + u) * ld + j] = acc;
-    }
-    if (threadIdx.x == 0) {
-        xdims[c] = m;
-        xdims[Lx + 1 + c] = n;
+        if (threadIdx.x == 0) {
+            dsc.xdims[c] = m;
+            dsc.xdims[Lx + 1 + c] = n;
+        }
+        __syncthreads();
     }
 }
 
@@ -241,12 +243,11 @@ __host__ __device__ constexpr size_t tn_qr_area(int D) {
 // later Z = U S and Y = X_{c-1} Z.  QLDS: QA and QB in LDS (D <= 32);
 // otherwise they are in global `gwork` and only W sits in LDS.
 template <bool QLDS>
-__global__ void __launch_bounds__(1024)
-k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict__ xdims,
-               double *__restrict__ env, int *__restrict__ dims, double *__restrict__ ell,
-               double *__restrict__ gwork, unsigned long long *__restrict__ counters,
-               int *__restrict__ cst) {
-    extern __shared__ double lds[];
+__device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
+    const int Lx = dsc.Lx, D = dsc.D;
+    double *xbox = dsc.xbox, *env = dsc.env, *ell = dsc.ell, *gwork = dsc.wbuf;
+    int *xdims = dsc.xdims, *dims = dsc.dims, *cst = dsc.cst;
+    unsigned long long *counters = dsc.counters;
     __shared__ double tau[2 * TN_MAX_D];
     __shared__ double sv[2 * TN_MAX_D];
     __shared__ double nrm[2 * TN_MAX_D];
@@ -441,16 +442,35 @@ k_truncate_row(int k, int Lx, int D, double *__restrict__ xbox, int *__restrict_
         ell[k] = lognorm;
         cst[k] = cmin;
     }
+    __syncthreads();
+}
+
+// Row step `step` of every instance (row k = Ly - 1 - step; the instances
+// that have no such row return at once): the MPO application and the
+// compression of row k.
+__global__ void __launch_bounds__(1024) k_env_row(const tn_env_desc *__restrict__ descs, int step) {
+    extern __shared__ double lds[];
+    const tn_env_desc dsc = descs[blockIdx.x];
+    const int k = dsc.Ly - 1 - step;
+    if (k < 1) return;
+    if (step == 0)   // trivial env below the last row: bond 1 everywhere
+        for (int c = threadIdx.x; c <= dsc.Lx; c += blockDim.x) dsc.dims[(size_t)dsc.Ly * (dsc.Lx + 1) + c] = 1;
+    mpo_apply_row(dsc, k);
+    if (dsc.D <= 32)
+        truncate_row<true>(dsc, k, lds);
+    else
+        truncate_row<false>(dsc, k, lds);
 }
 
 // ln <top|env_1>: row 0 (no up legs) contracted with env 1 left to right,
 // rescaled by its largest entry after every column.  out[0] = ln|value|,
 // out[1] = sign.
-__global__ void __launch_bounds__(256)
-k_top_overlap(int Lx, int Ly, int D, double beta, const double *__restrict__ Jh,
-              const double *__restrict__ Jv, const double *__restrict__ h,
-              const double *__restrict__ env, const int *__restrict__ dims,
-              double *__restrict__ out) {
+__device__ void top_overlap(const tn_env_desc &dsc) {
+    const int Lx = dsc.Lx, Ly = dsc.Ly, D = dsc.D;
+    const double beta = dsc.beta;
+    const double *Jh = dsc.Jh, *Jv = dsc.Jv, *h = dsc.h, *env = dsc.env;
+    const int *dims = dsc.dims;
+    double *out = dsc.scal;
     __shared__ double st[2][TN_MAX_D], nst[2][TN_MAX_D];
     __shared__ double M[2][2][2];   // [l][d][x]
     __shared__ double red[4];
@@ -512,84 +532,126 @@ k_top_overlap(int Lx, int Ly, int D, double beta, const double *__restrict__ Jh,
     }
 }
 
+__global__ void __launch_bounds__(256) k_env_top(const tn_env_desc *__restrict__ descs) {
+    const tn_env_desc dsc = descs[blockIdx.x];
+    if (dsc.Ly == 1) {   // trivial env below the only row
+        for (int c = threadIdx.x; c <= dsc.Lx; c += blockDim.x) dsc.dims[(size_t)dsc.Ly * (dsc.Lx + 1) + c] = 1;
+        __syncthreads();
+    }
+    top_overlap(dsc);
+}
+
 }  // namespace
 
-int tn_top_overlap(tn_ctx *ctx, double *logtop, double *sign) {
-    const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
-    hipLaunchKernelGGL(k_top_overlap, dim3(1), dim3(256), 0, ctx->stream, Lx, Ly, D,
-                       ctx->beta, ctx->Jh, ctx->Jv, ctx->h, ctx->env, ctx->dims, ctx->scal);
-    TN_HIP(ctx, hipGetLastError());
-    double hbuf[2];
-    TN_HIP(ctx, hipMemcpyAsync(hbuf, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    *logtop = hbuf[0];
-    *sign = hbuf[1];
-    return TN_OK;
+int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err) {
+    if (n <= 0) return TN_OK;
+    tn_ctx *c0 = ctxs[0];
+    auto fail = [&](int code, const std::string &msg) {
+        if (err) *err = msg;
+        return code;
+    };
+    std::vector<tn_env_desc> ds(n);
+    int maxLy = 1, maxD = 1;
+    size_t lds_dbl = 0;
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *ctx = ctxs[i];
+        const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
+        int rc;
+        if ((rc = tn_ensure(ctx, (void **)&ctx->xbox, &ctx->xbox_cap,
+                            (size_t)Lx * 8 * D * D * sizeof(double))))
+            return fail(rc, ctx->err);
+        if (D > 32 && (rc = tn_ensure(ctx, (void **)&ctx->wbuf, &ctx->wbuf_cap,
+                                      2 * tn_qr_area(D) * sizeof(double))))
+            return fail(rc, ctx->err);
+        if (!ctx->xdims &&
+            hipMalloc((void **)&ctx->xdims, 2 * (4 * TN_MAX_D + 1) * sizeof(int) +
+                                                2 * 1024 * sizeof(int)) != hipSuccess)
+            return fail(TN_ENOMEM, "hipMalloc failed");
+        tn_env_desc &d = ds[i];
+        d.Lx = Lx;
+        d.Ly = Ly;
+        d.D = D;
+        d.pad = 0;
+        d.beta = ctx->beta;
+        d.Jh = ctx->Jh;
+        d.Jv = ctx->Jv;
+        d.h = ctx->h;
+        d.env = ctx->env;
+        d.dims = ctx->dims;
+        d.ell = ctx->ell;
+        d.cst = ctx->cst;
+        d.xbox = ctx->xbox;
+        d.xdims = ctx->xdims;
+        d.wbuf = ctx->wbuf;
+        d.scal = ctx->scal;
+        d.counters = ctx->counters;
+        maxLy = Ly > maxLy ? Ly : maxLy;
+        maxD = D > maxD ? D : maxD;
+        const size_t need = D <= 32 ? 2 * tn_qr_area(D) : tn_svd_area(D);
+        lds_dbl = need > lds_dbl ? need : lds_dbl;
+    }
+    int rc;
+    if ((rc = tn_ensure(c0, (void **)&c0->descs, &c0->descs_cap, n * sizeof(tn_env_desc))))
+        return fail(rc, c0->err);
+    tn_env_desc *dd = (tn_env_desc *)c0->descs;
+    if (hipMemcpyAsync(dd, ds.data(), n * sizeof(tn_env_desc), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+        return fail(TN_EHIP, "descriptor copy failed");
+    for (int i = 0; i < n; ++i)
+        if (hipMemsetAsync(ctxs[i]->counters + CNT_NOCONV, 0, sizeof(unsigned long long), stream) !=
+            hipSuccess)
+            return fail(TN_EHIP, "counter reset failed");
+    const size_t lds_bytes = lds_dbl * sizeof(double);
+    if (hipFuncSetAttribute((const void *)k_env_row, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes) != hipSuccess)
+        return fail(TN_EHIP, "LDS size not accepted");
+    // one 16-lane row per row pair of the largest SVD matrix (2 D rows)
+    const int nthr = maxD <= 32 ? 512 : 1024;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int step = 0; step + 1 < maxLy; ++step) {
+        hipLaunchKernelGGL(k_env_row, dim3(n), dim3(nthr), lds_bytes, stream, dd, step);
+        if (hipGetLastError() != hipSuccess) return fail(TN_EHIP, "row kernel launch failed");
+    }
+    hipLaunchKernelGGL(k_env_top, dim3(n), dim3(256), 0, stream, dd);
+    if (hipGetLastError() != hipSuccess) return fail(TN_EHIP, "top kernel launch failed");
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(TN_EHIP, "environment build failed");
+    auto t1 = std::chrono::steady_clock::now();
+    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    int first_bad = TN_OK;
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *ctx = ctxs[i];
+        const int Ly = ctx->Ly;
+        double top[2];
+        std::vector<double> ell(Ly + 1, 0.0);
+        unsigned long long noconv = 0;
+        if (hipMemcpy(top, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(ell.data(), ctx->ell, (Ly + 1) * sizeof(double), hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemcpy(&noconv, ctx->counters + CNT_NOCONV, sizeof(noconv), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return fail(TN_EHIP, "result copy failed");
+        double lz = top[0];
+        for (int k = 1; k < Ly; ++k) lz += ell[k];
+        ctx->logZ = lz;
+        ctx->env_build_ms = ms;
+        if (first_bad == TN_OK) {
+            if (noconv) {
+                first_bad = TN_ENOCONV;
+                if (err) *err = "Jacobi SVD did not converge in 60 sweeps (instance " + std::to_string(i) + ")";
+            } else if (!(top[1] > 0.0) || !std::isfinite(lz)) {
+                first_bad = TN_ENONPOS;
+                if (err) *err = "approximate partition function is not positive (instance " + std::to_string(i) + ")";
+            }
+        }
+    }
+    return first_bad;
 }
 
 int tn_env_build_device(tn_ctx *ctx, double *logZ_out) {
-    const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
-    const size_t box = (size_t)8 * D * D;
-    int rc;
-    if ((rc = tn_ensure(ctx, (void **)&ctx->xbox, &ctx->xbox_cap, Lx * box * sizeof(double))))
-        return rc;
-    // QR work areas in LDS when they fit (D <= 32), else in global memory
-    // with the SVD matrix alone in LDS
-    const bool use_lds = D <= 32;
-    const size_t work = 2 * tn_qr_area(D);
-    if (!use_lds &&
-        (rc = tn_ensure(ctx, (void **)&ctx->wbuf, &ctx->wbuf_cap, work * sizeof(double))))
-        return rc;
-    if (!ctx->xdims) TN_HIP(ctx, hipMalloc((void **)&ctx->xdims, 2 * (4 * TN_MAX_D + 1) * sizeof(int) + 2 * 1024 * sizeof(int)));
-    auto t0 = std::chrono::steady_clock::now();
-    // trivial env below the last row: bond 1 everywhere
-    hipLaunchKernelGGL(k_fill_dims, dim3(1), dim3(256), 0, ctx->stream,
-                       ctx->dims + (size_t)Ly * (Lx + 1), Lx + 1, 1);
-    TN_HIP(ctx, hipGetLastError());
-    const size_t lds_bytes = (use_lds ? work : tn_svd_area(D)) * sizeof(double);
-    if (use_lds)
-        TN_HIP(ctx, hipFuncSetAttribute((const void *)k_truncate_row<true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds_bytes));
-    else
-        TN_HIP(ctx, hipFuncSetAttribute((const void *)k_truncate_row<false>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds_bytes));
-    // one 16-lane row per row pair of the largest SVD matrix (2 D rows)
-    const int nthr = D <= 32 ? 512 : 1024;
-    TN_HIP(ctx, hipMemsetAsync(ctx->counters + CNT_NOCONV, 0, sizeof(unsigned long long),
-                               ctx->stream));
-    for (int k = Ly - 1; k >= 1; --k) {
-        hipLaunchKernelGGL(k_mpo_apply, dim3(Lx), dim3(256), 0, ctx->stream, k, Lx, Ly, D,
-                           ctx->beta, ctx->Jh, ctx->Jv, ctx->h, ctx->env, ctx->dims,
-                           ctx->xbox, ctx->xdims);
-        TN_HIP(ctx, hipGetLastError());
-        if (use_lds)
-            hipLaunchKernelGGL(k_truncate_row<true>, dim3(1), dim3(nthr), lds_bytes, ctx->stream,
-                               k, Lx, D, ctx->xbox, ctx->xdims, ctx->env, ctx->dims, ctx->ell,
-                               nullptr, ctx->counters, ctx->cst);
-        else
-            hipLaunchKernelGGL(k_truncate_row<false>, dim3(1), dim3(nthr), lds_bytes, ctx->stream,
-                               k, Lx, D, ctx->xbox, ctx->xdims, ctx->env, ctx->dims, ctx->ell,
-                               ctx->wbuf, ctx->counters, ctx->cst);
-        TN_HIP(ctx, hipGetLastError());
-    }
-    double logtop, sign;
-    if ((rc = tn_top_overlap(ctx, &logtop, &sign))) return rc;
-    std::vector<double> ell(Ly + 1, 0.0);
-    TN_HIP(ctx, hipMemcpy(ell.data(), ctx->ell, (Ly + 1) * sizeof(double), hipMemcpyDeviceToHost));
-    unsigned long long noconv = 0;
-    TN_HIP(ctx, hipMemcpy(&noconv, ctx->counters + CNT_NOCONV, sizeof(noconv),
-                          hipMemcpyDeviceToHost));
-    auto t1 = std::chrono::steady_clock::now();
-    ctx->env_build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    double lz = logtop;
-    for (int k = 1; k < Ly; ++k) lz += ell[k];
-    ctx->logZ = lz;
-    if (logZ_out) *logZ_out = lz;
-    if (noconv) return tn_fail(ctx, TN_ENOCONV, "Jacobi SVD did not converge in 60 sweeps");
-    if (!(sign > 0.0) || !std::isfinite(lz))
-        return tn_fail(ctx, TN_ENONPOS, "approximate partition function is not positive");
+    tn_ctx *one[1] = {ctx};
+    std::string e;
+    const int rc = tn_env_build_many(one, 1, ctx->stream, &e);
+    if (rc != TN_OK) return tn_fail(ctx, rc, e);
+    if (logZ_out) *logZ_out = ctx->logZ;
     return TN_OK;
 }

@@ -48,7 +48,8 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
            const double *__restrict__ G64r, const double *__restrict__ G64c,
            int8_t *__restrict__ S, int eval, double *__restrict__ logq,
            double *__restrict__ energy, double *__restrict__ gscr, uint32_t k0, uint32_t k1,
-           uint64_t first_id, uint64_t step0, int per_step, uint32_t inst,
+           uint64_t first_id, uint64_t step0, const uint64_t *__restrict__ step_base,
+           int per_step, uint32_t inst,
            unsigned long long *__restrict__ counters) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = tid / T, j = tid % T;
@@ -150,7 +151,7 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
             if ((i >> 2) != blk_id) {
                 blk_id = i >> 2;
                 const uint64_t id = first_id + (uint64_t)b % (uint64_t)per_step;
-                const uint32_t st = (uint32_t)(step0 + (uint64_t)b / (uint64_t)per_step);
+                const uint32_t st = (uint32_t)(step0 + *step_base + (uint64_t)b / (uint64_t)per_step);
                 blk = tn_philox(make_uint4((uint32_t)blk_id, (uint32_t)id, st, (inst << 2) | 0u),
                                 k0, k1);
             }
@@ -206,7 +207,7 @@ int launch_rows(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
                            ctx->Lx, ctx->Ly, ctx->D, ctx->Jh, ctx->Jv, ctx->h, ctx->fac,
                            ctx->dims, ctx->G64r, ctx->G64c, S, eval ? 1 : 0, logq, energy,
                            gscr, (uint32_t)seed, (uint32_t)(seed >> 32), first_id, step0,
-                           per_step, (uint32_t)ctx->inst, ctx->counters);
+                           ctx->dstep, per_step, (uint32_t)ctx->inst, ctx->counters);
         TN_HIP(ctx, hipGetLastError());
     }
     return TN_OK;

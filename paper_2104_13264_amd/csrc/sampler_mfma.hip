@@ -188,22 +188,30 @@ struct SmemLayout {
 constexpr int RS = 4;   // rescale (and ln q renormalisation) period in columns
 
 template <int NT, bool BF16>
-__global__ void __launch_bounds__(256)
-k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
-               const double *__restrict__ Jv, const double *__restrict__ h,
-               const double *__restrict__ fac, const void *__restrict__ GRv,
-               const void *__restrict__ GLv, int8_t *__restrict__ S, int eval,
-               double *__restrict__ logq, double *__restrict__ energy,
-               float *__restrict__ gscr, uint32_t k0, uint32_t k1, uint64_t first_id,
-               uint64_t step0, int per_step, uint32_t inst,
-               unsigned long long *__restrict__ counters) {
+__device__ __forceinline__ void sampler_body(const tn_samp_desc &A, const int blk, const int eval,
+                                             const uint32_t k0, const uint32_t k1,
+                                             const uint64_t step0) {
+    const int B = A.B, Lx = A.Lx, Ly = A.Ly, per_step = A.per_step;
+    const double *__restrict__ Jh = A.Jh;
+    const double *__restrict__ Jv = A.Jv;
+    const double *__restrict__ h = A.h;
+    const double *__restrict__ fac = A.fac;
+    const void *__restrict__ GRv = A.GR;
+    const void *__restrict__ GLv = A.GL;
+    int8_t *__restrict__ S = A.S;
+    double *__restrict__ logq = A.logq;
+    double *__restrict__ energy = A.energy;
+    float *__restrict__ gscr = A.gscr;
+    const uint64_t first_id = A.first_id;
+    const uint32_t inst = A.inst;
+    unsigned long long *__restrict__ counters = A.counters;
     constexpr int PF = prefetch_depth<NT, BF16>();
     using AT = ATiles<NT, BF16>;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int gp = w >> 1, sw = w & 1;
     const int n = lane & 15, grp = lane >> 4;
-    const int b = blockIdx.x * 16 + n;
+    const int b = blk * 16 + n;
     const bool valid = b < B;
     const bool leader = (sw == 0 && grp == 0);        // one lane per proposal per group
 
@@ -222,7 +230,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
     auto rowbuf = [&](int par) { return (int8_t(*)[16])(smem + L.rows + par * Lx * 16); };
 
     const uint32_t gstride = 2u * NT * 64 * 16;       // bytes of stored y tiles per column
-    float *gwg = gscr + ((size_t)blockIdx.x * 2 + gp) * Lx * (gstride / 4);
+    float *gwg = gscr + ((size_t)blk * 2 + gp) * Lx * (gstride / 4);
     const __amdgpu_buffer_rsrc_t grs = make_rsrc(gwg, (uint32_t)Lx * gstride);
     const int NTH = blockDim.x;
 
@@ -270,7 +278,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
             for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                 const int c = t >> 4, nn = t & 15;
                 const int i = rS * Lx + c;
-                const uint32_t j = blockIdx.x * 16 + nn;
+                const uint32_t j = blk * 16 + nn;
                 const uint64_t id = first_id + j % (uint32_t)per_step;
                 const uint32_t st = (uint32_t)(step0 + j / (uint32_t)per_step);
                 const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2), (uint32_t)id, st,
@@ -282,7 +290,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
             int8_t(*r1)[16] = rowbuf(rS & 1);
             for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                 const int nn = t / Lx, c = t % Lx;
-                const int bb = blockIdx.x * 16 + nn;
+                const int bb = blk * 16 + nn;
                 r1[c][nn] = bb < B ? S[((size_t)bb * Ly + rS) * Lx + c] : (int8_t)1;
             }
         }
@@ -492,7 +500,7 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
             if (!eval) {
                 for (int t = threadIdx.x; t < 16 * Lx; t += NTH) {
                     const int nn = t / Lx, c = t % Lx;
-                    const int bb = blockIdx.x * 16 + nn;
+                    const int bb = blk * 16 + nn;
                     if (bb < B) S[((size_t)bb * Ly + rS) * Lx + c] = cur[c][nn];
                 }
             }
@@ -521,21 +529,56 @@ k_sampler_mfma(int B, int Lx, int Ly, const double *__restrict__ Jh,
     }
 }
 
+// One instance: the arguments by value; the MH step is step0 + *step_base.
+template <int NT, bool BF16>
+__global__ void __launch_bounds__(256)
+k_sampler_mfma(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step0,
+               const uint64_t *__restrict__ step_base) {
+    sampler_body<NT, BF16>(A, blockIdx.x, eval, k0, k1, step0 + *step_base);
+}
+
+// Several instances in one launch: instance i owns the blocks from
+// descs[i].blk0 (ascending) on.
+template <int NT, bool BF16>
+__global__ void __launch_bounds__(256)
+k_sampler_mfma_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0, uint32_t k1,
+                     uint64_t step0, const uint64_t *__restrict__ step_base) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {   // last instance whose first block is <= blockIdx.x
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].blk0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const tn_samp_desc A = descs[lo];
+    sampler_body<NT, BF16>(A, (int)blockIdx.x - A.blk0, 0, k0, k1, step0 + *step_base);
+}
+
 template <int NT, bool BF16>
 int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     const int blocks = (B + 15) / 16;
-    const void *GR = BF16 ? (const void *)ctx->G16R : (const void *)ctx->G32R;
-    const void *GL = BF16 ? (const void *)ctx->G16L : (const void *)ctx->G32L;
     const SmemLayout<NT> L(ctx->Lx);
     auto kern = k_sampler_mfma<NT, BF16>;
     if (L.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, L.total));
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), L.total, ctx->stream, B, ctx->Lx, ctx->Ly,
-                       ctx->Jh, ctx->Jv, ctx->h, ctx->fac, GR, GL, S, eval ? 1 : 0, logq, energy,
-                       g, (uint32_t)seed, (uint32_t)(seed >> 32), first_id, step0, per_step,
-                       (uint32_t)ctx->inst, ctx->counters);
+    const tn_samp_desc A = tn_samp_desc_of(ctx, B, S, logq, energy, g, per_step, first_id);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), L.total, ctx->stream, A, eval ? 1 : 0,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
+    TN_HIP(ctx, hipGetLastError());
+    return TN_OK;
+}
+
+template <int NT, bool BF16>
+int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks, int maxLx,
+                      uint64_t seed, uint64_t step0) {
+    const SmemLayout<NT> L(maxLx);
+    auto kern = k_sampler_mfma_multi<NT, BF16>;
+    if (L.total > 65536)
+        TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, L.total));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), L.total, ctx->stream, descs, n,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
 }
@@ -567,4 +610,21 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
     if (ctx->prec == TN_BF16)
         return dispatch_nt<true>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
     return dispatch_nt<false>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+}
+
+int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, const tn_samp_desc *descs, int n, int blocks,
+                      int maxLx, uint64_t seed, uint64_t step0) {
+    if (blocks == 0) return TN_OK;
+    if (maxLx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
+    switch (NT * 2 + (bf16 ? 1 : 0)) {
+    case 2: return launch_mfma_multi<1, false>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 3: return launch_mfma_multi<1, true>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 4: return launch_mfma_multi<2, false>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 5: return launch_mfma_multi<2, true>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 6: return launch_mfma_multi<3, false>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 7: return launch_mfma_multi<3, true>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 8: return launch_mfma_multi<4, false>(ctx, descs, n, blocks, maxLx, seed, step0);
+    case 9: return launch_mfma_multi<4, true>(ctx, descs, n, blocks, maxLx, seed, step0);
+    default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
+    }
 }

@@ -21,6 +21,12 @@ _STATUS = {0: "TN_OK", -1: "TN_EINVAL", -2: "TN_ENOMEM", -3: "TN_EHIP",
            -4: "TN_ENONPOS", -5: "TN_ENOCONV", -6: "TN_ESTATE"}
 
 
+class _Instance(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("D", ctypes.c_int),
+                ("beta", ctypes.c_double), ("Jh", ctypes.c_void_p), ("Jv", ctypes.c_void_p),
+                ("h", ctypes.c_void_p), ("chains", ctypes.c_int)]
+
+
 class TNError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_STATUS.get(code, code)}: {msg}")
@@ -57,6 +63,11 @@ def lib():
         "tn_eval_logq": (i, [vp, i, vp, vp, vp]),
         "tn_mh_step": (i, [vp, i, u64, u64, vp, vp, vp, vp]),
         "tn_sample_steps": (i, [vp, i, i, u64, u64, u64, vp, vp, vp]),
+        "tn_build_env_multi": (i, [vp, i, vp, i, vp]),
+        "tn_mh_step_multi": (i, [vp, u64, u64, vp, vp, vp, vp]),
+        "tn_multi_instance": (vp, [vp, i]),
+        "tn_graph_begin": (i, [vp]),
+        "tn_graph_end_and_replay": (i, [vp, i]),
         "tn_mh_run": (i, [vp, i, i, u64, u64, vp, vp, vp, vp, vp]),
         "tn_mh_accept": (i, [vp, i, u64, u64, vp, vp, vp, vp, vp, vp, vp]),
         "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
@@ -74,7 +85,8 @@ def exported_symbols():
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_build_env", "tn_set_env",
             "tn_get_env", "tn_set_precision", "tn_set_instance", "tn_sample",
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
-            "tn_grad", "tn_stats"]
+            "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
+            "tn_graph_end_and_replay", "tn_grad", "tn_stats"]
 
 
 def _ptr(t):
@@ -213,6 +225,50 @@ class Sampler:
                                      _ptr(state["accepted"])))
         return state["accepted"]
 
+    # -- batched uneven instances -----------------------------------------
+    def build_env_multi(self, instances, prec=FP32):
+        """instances: sequence of dicts with Jh, Jv, h (or None), beta, D, chains.
+        Returns ln Z~ per instance; self.instance(i) gives instance i."""
+        n = len(instances)
+        arr = (_Instance * n)()
+        keep = []
+        for k, it in enumerate(instances):
+            Jh, Jv, h = (_dev64(it.get(x), self.device) for x in ("Jh", "Jv", "h"))
+            keep.append((Jh, Jv, h))
+            Ly, Lx = Jv.shape[0] + 1, Jh.shape[1] + 1
+            arr[k] = _Instance(Lx, Ly, int(it["D"]), float(it["beta"]),
+                               Jh.data_ptr() if Jh.numel() else None,
+                               Jv.data_ptr() if Jv.numel() else None,
+                               h.data_ptr() if h is not None else None, int(it["chains"]))
+        self._keep_multi = keep
+        lz = (ctypes.c_double * n)()
+        self._check(lib().tn_build_env_multi(self._ctx, n, arr, int(prec), lz))
+        self._multi = [(arr[k].Lx, arr[k].Ly, arr[k].D, arr[k].beta) for k in range(n)]
+        return list(lz)
+
+    def instance(self, i):
+        """Instance i of the batched context (a borrowed Sampler)."""
+        p = lib().tn_multi_instance(self._ctx, int(i))
+        if not p:
+            raise TNError(-1, f"no instance {i}")
+        Lx, Ly, D, beta = self._multi[i]
+        return _BorrowedSampler(self, p, Lx, Ly, D, beta)
+
+    def mh_step_multi(self, states, seed, step):
+        n = len(states)
+        P = ctypes.c_void_p * n
+        sp = P(*[s["spins"].data_ptr() for s in states])
+        lq = P(*[s["logq"].data_ptr() for s in states])
+        en = P(*[s["energy"].data_ptr() for s in states])
+        ac = P(*[s["accepted"].data_ptr() for s in states])
+        self._check(lib().tn_mh_step_multi(self._ctx, int(seed), int(step), sp, lq, en, ac))
+
+    def graph_begin(self):
+        self._check(lib().tn_graph_begin(self._ctx))
+
+    def graph_end_and_replay(self, n_replays):
+        self._check(lib().tn_graph_end_and_replay(self._ctx, int(n_replays)))
+
     def mh_run(self, state, seed, step0, nsteps, energy_series=True):
         """nsteps MH steps; returns (accepted [nsteps][chains], energies or None)."""
         C = state["spins"].shape[0]
@@ -245,3 +301,18 @@ class Sampler:
         st = _Stats()
         self._check(lib().tn_stats(self._ctx, ctypes.byref(st), 1 if reset else 0))
         return {name: getattr(st, name) for name, _ in _Stats._fields_}
+
+
+class _BorrowedSampler(Sampler):
+    """One instance of a batched context: every single-instance method, on a
+    context the batched one owns (close() does not destroy it)."""
+
+    def __init__(self, parent, ptr, Lx, Ly, D, beta):
+        self.device = parent.device
+        self.stream = parent.stream
+        self._ctx = ctypes.c_void_p(ptr)
+        self._parent = parent
+        self.Lx, self.Ly, self.D, self.beta = Lx, Ly, D, beta
+
+    def close(self):
+        self._ctx = ctypes.c_void_p()

@@ -1,0 +1,142 @@
+"""Batched uneven instances (tn_build_env_multi, tn_mh_step_multi) and HIP
+graph replay (tn_graph_begin / tn_graph_end_and_replay).
+
+ln Z~ of every instance within 1e-9 relative of the oracle; batched MH steps
+bitwise the per-instance steps on the same environments; graph replays
+bitwise the eager steps, every replay checked.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bmps
+from workloads import random_instance, ea_pm, ferro
+from bridge import model_of, TOL_LOGZ_FP64
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32, BF16 = 0, 1, 2
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def mixed_instances():
+    # uneven sizes, bond caps in all four 16-wide classes, betas, fields, chains
+    out = [
+        (random_instance(6, 9, 0.7, 5, seed=61, field_scale=0.2), 5, 37),
+        (ea_pm(10, 1.0, 12, seed=62), 12, 21),
+        (random_instance(9, 7, 0.5, 24, seed=63), 24, 16),
+        (ferro(8, 0.4407, 40), 40, 9),
+        (ea_pm(7, 2.0, 50, seed=64), 50, 18),
+    ]
+    return out
+
+
+def as_dicts(items):
+    return [dict(Jh=i.Jh, Jv=i.Jv, h=i.h, beta=i.beta, D=D, chains=C) for i, D, C in items]
+
+
+def clone(st):
+    return {k: v.clone() for k, v in st.items()}
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_multi_env_matches_oracle_and_steps_match_single(prec):
+    from paper_2104_13264_amd import Sampler
+    items = mixed_instances()
+    log(f"[multi] {len(items)} instances prec {prec}")
+    s = Sampler()
+    lz = s.build_env_multi(as_dicts(items), prec)
+    for (inst, D, C), z in zip(items, lz):
+        ref = bmps.build_envs(model_of(inst), D)['logZ']
+        assert abs(z - ref) <= TOL_LOGZ_FP64 * abs(ref), (inst.Ly, inst.Lx, D, z, ref)
+    subs = [s.instance(i) for i in range(len(items))]
+    sa = [sub.init_state(C) for sub, (_, _, C) in zip(subs, items)]
+    sb = [clone(x) for x in sa]
+    seed = 7
+    for t in range(4):
+        s.mh_step_multi(sa, seed, t)
+        for sub, st in zip(subs, sb):
+            sub.mh_step(st, seed, t)
+        for x, y in zip(sa, sb):
+            for k in ("spins", "logq", "energy", "accepted"):
+                assert torch.equal(x[k], y[k])
+    s.close()
+
+
+def test_multi_graph_replays_match_eager():
+    from paper_2104_13264_amd import Sampler
+    items = mixed_instances()[:3]
+    stream = torch.cuda.Stream()
+    s = Sampler(stream=stream)
+    s.build_env_multi(as_dicts(items), FP32)
+    subs = [s.instance(i) for i in range(len(items))]
+    with torch.cuda.stream(stream):
+        ga = [sub.init_state(C) for sub, (_, _, C) in zip(subs, items)]
+        ea = [clone(x) for x in ga]
+    stream.synchronize()
+    seed, t = 11, 0
+    # eager first call with the same buffers (allocations happen here)
+    s.mh_step_multi(ga, seed, t)
+    s.mh_step_multi(ea, seed, t)
+    t += 1
+    for cycle, (nstep, nrep) in enumerate([(2, 1), (1, 1), (2, 3)]):
+        log(f"[graph] cycle {cycle}: {nstep} captured steps x {nrep} replays")
+        s.graph_begin()
+        for j in range(nstep):
+            s.mh_step_multi(ga, seed, t + j)
+        s.graph_end_and_replay(nrep)
+        for j in range(nstep * nrep):
+            s.mh_step_multi(ea, seed, t + j)
+        stream.synchronize()
+        for x, y in zip(ga, ea):
+            for k in ("spins", "logq", "energy", "accepted"):
+                assert torch.equal(x[k], y[k])
+        t += nstep * nrep
+    s.close()
+
+
+def test_single_instance_graph_replay_matches_eager():
+    from paper_2104_13264_amd import Sampler
+    inst = random_instance(8, 8, 0.6, 8, seed=65)
+    stream = torch.cuda.Stream()
+    s = Sampler(stream=stream)
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 8, FP32)
+    with torch.cuda.stream(stream):
+        a = s.init_state(50)
+        b = clone(a)
+    stream.synchronize()
+    s.mh_step(a, 3, 0)
+    s.mh_step(b, 3, 0)
+    for rep in range(2):
+        s.graph_begin()
+        s.mh_step(a, 3, 1 + 3 * rep)
+        s.graph_end_and_replay(3)
+        for j in range(3):
+            s.mh_step(b, 3, 1 + 3 * rep + j)
+        stream.synchronize()
+        for k in ("spins", "logq", "energy", "accepted"):
+            assert torch.equal(a[k], b[k])
+    s.close()
+
+
+def test_graph_capture_refuses_allocation():
+    from paper_2104_13264_amd import Sampler, TNError
+    inst = random_instance(5, 6, 0.6, 4, seed=66)
+    stream = torch.cuda.Stream()
+    s = Sampler(stream=stream)
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 4, FP32)
+    with torch.cuda.stream(stream):
+        a = s.init_state(20)
+    stream.synchronize()
+    s.graph_begin()
+    with pytest.raises(TNError):
+        s.mh_step(a, 1, 0)   # first call: its buffers would be allocated
+    s.graph_end_and_replay(0)   # closes the (empty) capture
+    with pytest.raises(TNError):
+        s.graph_end_and_replay(1)   # no capture open
+    s.mh_step(a, 1, 0)   # eager works again
+    stream.synchronize()
+    s.close()
