@@ -171,9 +171,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(proposals_per_launch):
     """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source."""
+    they were taken on the current kernel source and launch size."""
     p = os.path.join(ROOT, "profiles", "sampler_mfma_ferro64_traffic.json")
     try:
         with open(p) as fh:
@@ -181,6 +181,8 @@ def measured_traffic():
     except OSError:
         return None
     if d.get("source_hash") != kernel_source_hash():
+        return None
+    if d.get("proposals_per_launch") != proposals_per_launch:
         return None
     return d.get("bytes_per_launch")
 
@@ -235,7 +237,7 @@ def main():
     # launch draws the proposals of `steps_per_launch` MH steps.
     flops_launch = 6.0 * D * D * L * L * C * res32["steps_per_launch"]
     achieved = flops_launch / (res32["sampler_ms"] * 1e-3)
-    traffic = measured_traffic()
+    traffic = measured_traffic(C * res32["steps_per_launch"])
     out = {
         "metric": METRIC,
         "value": value,

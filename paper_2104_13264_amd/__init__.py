@@ -3,8 +3,8 @@ models (arXiv:2104.13264): boundary-MPS environments, sequential proposals
 with their log-probability, MH acceptance and d ln Z~ / dJ, as HIP kernels
 behind the C ABI of include/tnmh.h.
 """
-from .tnmh import (BF16, FP32, FP64, PREC, Sampler, TNError, exported_symbols, lib,
-                   LIB_PATH)
+from .tnmh import (BF16, FP32, FP64, PREC, LogZ, Sampler, TNError, exported_symbols, lib,
+                   log_z, LIB_PATH)
 
-__all__ = ["Sampler", "TNError", "FP64", "FP32", "BF16", "PREC", "lib", "LIB_PATH",
-           "exported_symbols"]
+__all__ = ["Sampler", "TNError", "LogZ", "log_z", "FP64", "FP32", "BF16", "PREC", "lib",
+           "LIB_PATH", "exported_symbols"]

@@ -316,3 +316,34 @@ class _BorrowedSampler(Sampler):
 
     def close(self):
         self._ctx = ctypes.c_void_p()
+
+
+class LogZ(torch.autograd.Function):
+    """ln Z~ of the boundary-MPS contraction as a differentiable function of
+    the couplings and beta.  The forward builds the environments (tn_build_env,
+    fp64); the backward is tn_grad: the derivative with the truncation
+    isometries frozen (exact where nothing was truncated), i.e. beta times the
+    bond correlations for dJ and minus the energy for d beta."""
+
+    @staticmethod
+    def forward(ctx, Jh, Jv, beta, D, h=None):
+        s = Sampler(device=Jh.device)
+        b = float(beta.item() if torch.is_tensor(beta) else beta)
+        lz = s.build_env(Jh.detach(), Jv.detach(), None if h is None else h.detach(), b, int(D),
+                         FP64)
+        ctx.sampler = s
+        return torch.tensor(lz, dtype=torch.float64, device=Jh.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        s = ctx.sampler
+        dJh, dJv, db = s.grad()
+        s.close()
+        ctx.sampler = None
+        g = g.to(torch.float64)
+        return g * dJh, g * dJv, g * torch.tensor(db, dtype=torch.float64, device=dJh.device), None, None
+
+
+def log_z(Jh, Jv, beta, D, h=None):
+    """Differentiable ln Z~ (see LogZ); the field h is held fixed."""
+    return LogZ.apply(Jh, Jv, beta, D, h)

@@ -6,6 +6,7 @@ element.  Tolerance: 1e-9 absolute on d ln Z~/dJ (entries are O(beta)),
 1e-9 relative on d ln Z~/d beta.
 """
 import numpy as np
+import torch
 import pytest
 
 from oracle import bmps, exact, grad, ising
@@ -77,3 +78,22 @@ def test_grad_rejects_zero_coupling_and_installed_env():
         t.grad()
     s.close()
     t.close()
+
+
+def test_autograd_function_matches_tn_grad_and_brute_force():
+    from paper_2104_13264_amd import Sampler, log_z
+    inst = random_instance(4, 4, 0.7, 8, seed=12)
+    Jh = torch.tensor(inst.Jh, dtype=torch.float64, device='cuda', requires_grad=True)
+    Jv = torch.tensor(inst.Jv, dtype=torch.float64, device='cuda', requires_grad=True)
+    beta = torch.tensor(inst.beta, dtype=torch.float64, device='cuda', requires_grad=True)
+    lz = log_z(Jh, Jv, beta, 8)
+    gJh, gJv, gb = torch.autograd.grad(2.0 * lz, (Jh, Jv, beta))
+    s = Sampler()
+    s.build_env(inst.Jh, inst.Jv, None, inst.beta, 8)
+    dJh, dJv, db = s.grad()
+    assert torch.equal(gJh, 2.0 * dJh) and torch.equal(gJv, 2.0 * dJv)
+    assert float(gb) == 2.0 * db
+    # untruncated: d ln Z / d beta = -<E> exactly (brute force)
+    cfg, E, _, lp = exact.brute_force(inst.Jh, inst.Jv, None, inst.beta)
+    assert abs(float(gb) / 2.0 + float(np.dot(np.exp(lp), E))) < 1e-10
+    s.close()
