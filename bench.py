@@ -163,6 +163,174 @@ def run_cpu_oracle(inst, budget_s=12.0):
                 proposals_per_s=steps * chains / dt)
 
 
+def run_ea_mix(steps, warmup):
+    """64 uneven +-J instances: one MH step of all of them per captured graph
+    replay (batched build, one sampler launch per bond class, one acceptance
+    launch)."""
+    import torch
+    from paper_2104_13264_amd import Sampler, FP32
+    from workloads import ea_mix, SEED
+    insts = ea_mix()
+    stream = torch.cuda.Stream()
+    s = Sampler(stream=stream)
+    t0 = time.perf_counter()
+    lz = s.build_env_multi([dict(Jh=i.Jh, Jv=i.Jv, h=i.h, beta=i.beta, D=i.D, chains=i.chains)
+                            for i in insts], FP32)
+    build_s = time.perf_counter() - t0
+    log(f"[bench] ea_mix: {len(insts)} environments built in {build_s:.2f} s")
+    subs = [s.instance(k) for k in range(len(insts))]
+    with torch.cuda.stream(stream):
+        states = [sub.init_state(i.chains) for sub, i in zip(subs, insts)]
+    stream.synchronize()
+    for t in range(warmup):
+        s.mh_step_multi(states, SEED, t)
+    stream.synchronize()
+    for sub in subs:
+        sub.stats(reset=True)
+    t0 = time.perf_counter()
+    s.graph_begin()
+    s.mh_step_multi(states, SEED, warmup)
+    s.graph_end_and_replay(steps)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    st = [sub.stats() for sub in subs]
+    acc = sum(x["accepted"] for x in st)
+    prop = sum(x["proposed"] for x in st)
+    flops_step = sum(6.0 * i.D * i.D * i.Lx * i.Ly * i.chains for i in insts)
+    by_L = {}
+    for i, x in zip(insts, st):
+        a = by_L.setdefault(i.Lx, [0, 0])
+        a[0] += x["accepted"]
+        a[1] += x["proposed"]
+    s.close()
+    return {"metric": "accepted MH proposals/s, 64 mixed +-J instances (batched, captured graph)",
+            "value": acc / wall, "unit": UNIT, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+            "config": {"workload": "ea_mix: 64 Edwards-Anderson +-J instances, L in {16,24,32,48} "
+                                   "(16 each), beta [1,2,3][i mod 3], D 16/32/32/64, 1024 chains "
+                                   "each, one captured graph per MH step"},
+            "acceptance": acc / max(prop, 1),
+            "acceptance_by_L": {str(L): a[0] / max(a[1], 1) for L, a in sorted(by_L.items())},
+            "achieved_tflops_algorithmic": flops_step * steps / wall / 1e12,
+            "env_build_s": build_s, "logZ_first": lz[0]}
+
+
+def run_antiferro256(steps, warmup, n_eval=2048):
+    """256x256 antiferromagnet, D = 64, BF16 operands with fp32 accumulation,
+    16384 proposals per step; |ln q_BF16 - ln q_FP64| per sample on the drawn
+    spins (fp64 eval of the same spins by the plain path)."""
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler, FP64, FP32, BF16
+    from workloads import antiferro_256
+    inst = antiferro_256()
+    s = Sampler()
+    t0 = time.perf_counter()
+    lz = s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, inst.D, BF16,
+                     progress=lambda d, tot: log(f"[bench] env rows {d}/{tot} "
+                                                 f"({time.perf_counter() - t0:.0f} s)"),
+                     rows_per_call=24)
+    build_s = time.perf_counter() - t0
+    C = inst.chains
+    out = {}
+    for name, prec in (("bf16", BF16), ("fp32", FP32)):
+        s.set_precision(prec)
+        state = s.init_state(C)
+        prop = s.empty_batch(C)
+        for t in range(warmup):
+            s.sample(C, inst.seed, step=t, out=prop)
+            s.mh_accept(prop, state, inst.seed, t)
+        s.stats(reset=True)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        stream = torch.cuda.current_stream()
+        t1 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            s.sample(C, inst.seed, step=warmup + k, out=prop)
+            ev[k][1].record(stream)
+            s.mh_accept(prop, state, inst.seed, warmup + k)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        st = s.stats()
+        kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        out[name] = dict(value=st["accepted"] / wall, ms_per_step=wall * 1e3 / steps,
+                         sampler_ms=kms, acceptance=st["accepted"] / max(st["proposed"], 1),
+                         spins=prop[0][:n_eval].clone(), logq=prop[1][:n_eval].clone())
+        log(f"[bench] antiferro256 {name}: {wall * 1e3 / steps:.1f} ms/step, sampler {kms:.1f} ms, "
+            f"acceptance {out[name]['acceptance']:.4f}")
+    # fp64 eval (plain path) of the last drawn spins of both paths
+    s.set_precision(FP64)
+    dev = {}
+    for name in ("bf16", "fp32"):
+        lq64, _ = s.eval_logq(out[name]["spins"])
+        d = (out[name]["logq"] - lq64).abs().cpu().numpy()
+        dev[name] = dict(max=float(d.max()), mean=float(d.mean()),
+                         rel_max=float((d / lq64.abs().cpu().numpy()).max()))
+    s.close()
+    flops = 6.0 * inst.D ** 2 * inst.Lx * inst.Ly * C
+    return {"metric": "accepted MH proposals/s, 2D Ising L=256 D=64: batched BF16 (and FP32)",
+            "value": out["bf16"]["value"], "unit": UNIT, "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": out["bf16"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "antiferro256_D64: 256x256 open antiferromagnet J=-1, h=0, "
+                                   "beta=0.4407, D=64 (fp64 build), 16384 chains from all-up"},
+            "acceptance": out["bf16"]["acceptance"],
+            "roofline": {"bound": "mfma", "achieved": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 1e12,
+                         "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
+                         "traffic": None, "kernel": "k_sampler_mfma<4,true>",
+                         "kernel_ms": out["bf16"]["sampler_ms"]},
+            "fp32": {k: v for k, v in out["fp32"].items() if k not in ("spins", "logq")},
+            "abs_logq_minus_fp64": dev, "n_eval": n_eval,
+            "env_build_s": build_s, "logZ": lz}
+
+
+def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8):
+    """128x128 fully frustrated lattice, beta = 1, D = 32: d ln Z~ / dJ and
+    d ln Z~ / d beta (tn_grad), timed, beside the chain's own estimates of
+    beta <s_i s_j> on a few bonds and of -<E>."""
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler, FP32
+    from workloads import frustrated_128, SEED
+    inst = frustrated_128()
+    s = Sampler()
+    t0 = time.perf_counter()
+    lz = s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, inst.D, FP32,
+                     progress=lambda d, tot: log(f"[bench] env rows {d}/{tot}"), rows_per_call=32)
+    build_s = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    dJh, dJv, db = s.grad()
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t1
+    log(f"[bench] frustrated128: build {build_s:.1f} s, gradient {grad_s:.1f} s")
+    state = s.init_state(chains)
+    rng = np.random.default_rng(SEED)
+    pick = [(int(rng.integers(0, 128)), int(rng.integers(0, 127))) for _ in range(bonds)]
+    corr = np.zeros(bonds)
+    e_sum = 0.0
+    n = 0
+    for t in range(warmup + steps):
+        s.mh_step(state, SEED, t)
+        if t >= warmup:
+            sp = state["spins"].double()
+            for k, (r, c) in enumerate(pick):
+                corr[k] += float((sp[:, r, c] * sp[:, r, c + 1]).mean())
+            e_sum += float(state["energy"].mean())
+            n += 1
+    st = s.stats()
+    s.close()
+    g = dJh.cpu().numpy()
+    return {"workload": "frustrated128_D32", "env_build_s": build_s, "grad_s": grad_s, "logZ": lz,
+            "dlogZ_dbeta": db, "chain_minus_mean_energy": -e_sum / n,
+            "bonds": pick, "grad_dJh": [float(g[r, c]) for r, c in pick],
+            "chain_beta_corr": [float(inst.beta * x / n) for x in corr],
+            "acceptance": st["accepted"] / max(st["proposed"], 1), "chains": chains, "steps": steps}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ["sampler_mfma.hip", "operands.hip", "common.hpp"]:
@@ -198,11 +366,23 @@ def main():
                     help="MH steps per sampler launch (default: enough for two workgroups per CU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--workload", default="ferro64",
+                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128"],
+                    help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler "
               "shards by chains, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "ferro64":
+        if args.workload == "ea_mix":
+            out = run_ea_mix(args.steps, args.warmup)
+        elif args.workload == "antiferro256":
+            out = run_antiferro256(min(args.steps, 20), min(args.warmup, 2))
+        else:
+            out = run_frustrated128()
+        print(json.dumps(out), flush=True)
+        return
     import numpy as np
     import torch
     from workloads import ferro_64

@@ -83,6 +83,17 @@ const char *tn_last_error(const tn_ctx *ctx);
 int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                  const double *h, double beta, int D, int prec, double *logZ_out);
 
+/* tn_build_env in three calls, for builds long enough to report progress:
+ * begin records the instance (as tn_build_env) and prepares the build; each
+ * tn_build_env_rows call builds the next `nrows` rows bottom-up and returns
+ * when they are done (rows_left, host, may be NULL: rows still to build);
+ * end builds what remains, the top overlap and the sampler operands and
+ * gives ln Z~.  Other calls on the context fail with TN_ESTATE in between. */
+int tn_build_env_begin(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
+                       const double *h, double beta, int D, int prec);
+int tn_build_env_rows(tn_ctx *ctx, int nrows, int *rows_left);
+int tn_build_env_end(tn_ctx *ctx, double *logZ_out);
+
 /* Install an environment computed elsewhere (or saved by tn_get_env) instead
  * of building it.  Couplings as in tn_build_env (dev).  Host arrays:
  *   env   [(Ly-1)][Lx][D][2][D] fp64: env k=1..Ly-1, tensor E[a][u][b] of column

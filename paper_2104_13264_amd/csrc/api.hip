@@ -49,6 +49,8 @@ void free_all(tn_ctx *ctx) {
     for (void *p : ctx->mdesc) (void)hipFree(p);
     ctx->mdesc.clear();
     ctx->mdesc_host.clear();
+    delete (tn_build_plan *)ctx->build_plan;
+    ctx->build_plan = nullptr;
 }
 
 int check_prec(tn_ctx *ctx, int prec) {
@@ -60,6 +62,7 @@ int check_prec(tn_ctx *ctx, int prec) {
 // Copy the couplings into context-owned buffers and record the instance.
 int set_instance(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                  const double *h, double beta, int D, int prec) {
+    ctx->building = false;   // a new instance abandons an open incremental build
     if (Lx < 1 || Ly < 1) return tn_fail(ctx, TN_EINVAL, "Lx and Ly must be >= 1");
     if (Lx > 256) return tn_fail(ctx, TN_EINVAL, "Lx above 256 is not supported");
     if (D < 1 || D > TN_MAX_D) return tn_fail(ctx, TN_EINVAL, "D must be in 1..64");
@@ -167,6 +170,65 @@ int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv
         TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
         *logZ_out = lz;
     }
+    return TN_OK;
+}
+
+int tn_build_env_begin(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
+                       const double *h, double beta, int D, int prec) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
+    int rc;
+    ctx->building = false;
+    if ((rc = set_instance(ctx, Lx, Ly, Jh, Jv, h, beta, D, prec))) return rc;
+    if (!ctx->build_plan) ctx->build_plan = new (std::nothrow) tn_build_plan();
+    if (!ctx->build_plan) return tn_fail(ctx, TN_ENOMEM, "out of host memory");
+    tn_ctx *one[1] = {ctx};
+    std::string e;
+    if ((rc = tn_env_build_prepare(one, 1, ctx->stream, &e, (tn_build_plan *)ctx->build_plan)))
+        return tn_fail(ctx, rc, e);
+    ctx->build_step = 0;
+    ctx->building = true;
+    return TN_OK;
+}
+
+int tn_build_env_rows(tn_ctx *ctx, int nrows, int *rows_left) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (!ctx->building) return tn_fail(ctx, TN_ESTATE, "no build open: call tn_build_env_begin");
+    if (nrows < 0) return tn_fail(ctx, TN_EINVAL, "nrows < 0");
+    tn_build_plan *plan = (tn_build_plan *)ctx->build_plan;
+    const int total = plan->maxLy - 1;
+    const int s1 = ctx->build_step + nrows < total ? ctx->build_step + nrows : total;
+    std::string e;
+    int rc;
+    if ((rc = tn_env_build_steps(plan, ctx->build_step, s1, ctx->stream, &e))) {
+        ctx->building = false;
+        return tn_fail(ctx, rc, e);
+    }
+    ctx->build_step = s1;
+    if (rows_left) *rows_left = total - s1;
+    return TN_OK;
+}
+
+int tn_build_env_end(tn_ctx *ctx, double *logZ_out) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (!ctx->building) return tn_fail(ctx, TN_ESTATE, "no build open: call tn_build_env_begin");
+    int rc, left = 0;
+    if ((rc = tn_build_env_rows(ctx, 1 << 30, &left))) return rc;
+    ctx->building = false;
+    tn_ctx *one[1] = {ctx};
+    std::string e;
+    if ((rc = tn_env_build_finish(one, 1, (tn_build_plan *)ctx->build_plan, ctx->stream, &e)))
+        return tn_fail(ctx, rc, e);
+    if ((rc = tn_make_operands(ctx, ctx->prec))) return rc;
+    ctx->has_env = true;
+    ctx->has_cst = true;
+    if (logZ_out) *logZ_out = ctx->logZ;
     return TN_OK;
 }
 

@@ -79,6 +79,10 @@ struct tn_ctx {
     std::vector<void *> mdesc;
     std::vector<std::vector<unsigned char>> mdesc_host;
     bool has_multi = false;
+    // incremental environment build (tn_build_env_begin .. _end)
+    bool building = false;
+    int build_step = 0;
+    void *build_plan = nullptr;   // tn_build_plan, owned
     // graph capture (tn_graph_begin .. tn_graph_end_and_replay)
     bool capturing = false;
     int graph_steps = 0;
@@ -136,6 +140,19 @@ struct tn_env_desc {
 // instance and row step); fills each ctx's logZ.  ctxs[i] must have its
 // instance set (couplings on the device).
 int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err);
+// The same in three parts (row steps s0..s1-1 per call, synchronised), for a
+// build reported row chunk by row chunk.
+struct tn_build_plan {
+    int n = 0, maxLy = 0, nthr = 0;
+    size_t lds_bytes = 0;
+    tn_env_desc *dd = nullptr;
+    double ms = 0.0;
+};
+int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err,
+                         tn_build_plan *plan);
+int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err);
+int tn_env_build_finish(tn_ctx *const *ctxs, int n, tn_build_plan *plan, hipStream_t stream,
+                        std::string *err);
 int tn_env_build_device(tn_ctx *ctx, double *logZ_out);
 int tn_make_operands(tn_ctx *ctx, int prec);
 

@@ -543,7 +543,8 @@ __global__ void __launch_bounds__(256) k_env_top(const tn_env_desc *__restrict__
 
 }  // namespace
 
-int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err) {
+int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err,
+                         tn_build_plan *plan) {
     if (n <= 0) return TN_OK;
     tn_ctx *c0 = ctxs[0];
     auto fail = [&](int code, const std::string &msg) {
@@ -607,16 +608,46 @@ int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::strin
         return fail(TN_EHIP, "LDS size not accepted");
     // one 16-lane row per row pair of the largest SVD matrix (2 D rows)
     const int nthr = maxD <= 32 ? 512 : 1024;
+    plan->n = n;
+    plan->maxLy = maxLy;
+    plan->nthr = nthr;
+    plan->lds_bytes = lds_bytes;
+    plan->dd = dd;
+    plan->ms = 0.0;
+    return TN_OK;
+}
+
+int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err) {
     auto t0 = std::chrono::steady_clock::now();
-    for (int step = 0; step + 1 < maxLy; ++step) {
-        hipLaunchKernelGGL(k_env_row, dim3(n), dim3(nthr), lds_bytes, stream, dd, step);
-        if (hipGetLastError() != hipSuccess) return fail(TN_EHIP, "row kernel launch failed");
+    for (int step = s0; step < s1 && step + 1 < plan->maxLy; ++step) {
+        hipLaunchKernelGGL(k_env_row, dim3(plan->n), dim3(plan->nthr), plan->lds_bytes, stream,
+                           plan->dd, step);
+        if (hipGetLastError() != hipSuccess) {
+            if (err) *err = "row kernel launch failed";
+            return TN_EHIP;
+        }
     }
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        if (err) *err = "environment build failed";
+        return TN_EHIP;
+    }
+    plan->ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return TN_OK;
+}
+
+int tn_env_build_finish(tn_ctx *const *ctxs, int n, tn_build_plan *plan, hipStream_t stream,
+                        std::string *err) {
+    auto fail = [&](int code, const std::string &msg) {
+        if (err) *err = msg;
+        return code;
+    };
+    const tn_env_desc *dd = plan->dd;
+    auto t0 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_env_top, dim3(n), dim3(256), 0, stream, dd);
     if (hipGetLastError() != hipSuccess) return fail(TN_EHIP, "top kernel launch failed");
     if (hipStreamSynchronize(stream) != hipSuccess) return fail(TN_EHIP, "environment build failed");
-    auto t1 = std::chrono::steady_clock::now();
-    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    plan->ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const double ms = plan->ms;
     int first_bad = TN_OK;
     for (int i = 0; i < n; ++i) {
         tn_ctx *ctx = ctxs[i];
@@ -645,6 +676,16 @@ int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::strin
         }
     }
     return first_bad;
+}
+
+
+int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err) {
+    if (n <= 0) return TN_OK;
+    tn_build_plan plan;
+    int rc;
+    if ((rc = tn_env_build_prepare(ctxs, n, stream, err, &plan))) return rc;
+    if ((rc = tn_env_build_steps(&plan, 0, plan.maxLy - 1, stream, err))) return rc;
+    return tn_env_build_finish(ctxs, n, &plan, stream, err);
 }
 
 int tn_env_build_device(tn_ctx *ctx, double *logZ_out) {

@@ -63,6 +63,9 @@ def lib():
         "tn_eval_logq": (i, [vp, i, vp, vp, vp]),
         "tn_mh_step": (i, [vp, i, u64, u64, vp, vp, vp, vp]),
         "tn_sample_steps": (i, [vp, i, i, u64, u64, u64, vp, vp, vp]),
+        "tn_build_env_begin": (i, [vp, i, i, vp, vp, vp, d, i, i]),
+        "tn_build_env_rows": (i, [vp, i, ctypes.POINTER(i)]),
+        "tn_build_env_end": (i, [vp, ctypes.POINTER(d)]),
         "tn_build_env_multi": (i, [vp, i, vp, i, vp]),
         "tn_mh_step_multi": (i, [vp, u64, u64, vp, vp, vp, vp]),
         "tn_multi_instance": (vp, [vp, i]),
@@ -83,7 +86,8 @@ def lib():
 
 def exported_symbols():
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_build_env", "tn_set_env",
-            "tn_get_env", "tn_set_precision", "tn_set_instance", "tn_sample",
+            "tn_get_env", "tn_set_precision", "tn_set_instance", "tn_build_env_begin",
+            "tn_build_env_rows", "tn_build_env_end", "tn_sample",
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
             "tn_graph_end_and_replay", "tn_grad", "tn_stats"]
@@ -133,14 +137,26 @@ class Sampler:
             pass
 
     # -- environments -------------------------------------------------------
-    def build_env(self, Jh, Jv, h, beta, D, prec=FP64):
-        """Build the boundary-MPS environments; returns ln Z~."""
+    def build_env(self, Jh, Jv, h, beta, D, prec=FP64, progress=None, rows_per_call=16):
+        """Build the boundary-MPS environments; returns ln Z~.  With
+        progress(rows_done, rows_total), the rows are built in chunks of
+        rows_per_call and progress is called after each chunk."""
         Jh, Jv, h = (_dev64(x, self.device) for x in (Jh, Jv, h))
         Ly, Lx = Jv.shape[0] + 1, Jh.shape[1] + 1
         self._keep = (Jh, Jv, h)
         logZ = ctypes.c_double()
-        self._check(lib().tn_build_env(self._ctx, Lx, Ly, _ptr(Jh), _ptr(Jv), _ptr(h),
-                                       float(beta), int(D), int(prec), ctypes.byref(logZ)))
+        if progress is None:
+            self._check(lib().tn_build_env(self._ctx, Lx, Ly, _ptr(Jh), _ptr(Jv), _ptr(h),
+                                           float(beta), int(D), int(prec), ctypes.byref(logZ)))
+        else:
+            self._check(lib().tn_build_env_begin(self._ctx, Lx, Ly, _ptr(Jh), _ptr(Jv), _ptr(h),
+                                                 float(beta), int(D), int(prec)))
+            left = ctypes.c_int(Ly - 1)
+            while left.value > 0:
+                self._check(lib().tn_build_env_rows(self._ctx, int(rows_per_call),
+                                                    ctypes.byref(left)))
+                progress(Ly - 1 - left.value, Ly - 1)
+            self._check(lib().tn_build_env_end(self._ctx, ctypes.byref(logZ)))
         self.Lx, self.Ly, self.D, self.beta = Lx, Ly, int(D), float(beta)
         return logZ.value
 

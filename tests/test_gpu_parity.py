@@ -64,6 +64,7 @@ SAMPLER_CASES = [
     ("frustrated 10 D33", lambda: fully_frustrated(10, 1.0, 33), 33, 21),
     ("strip 1x9", lambda: random_instance(1, 9, 0.8, 4, seed=14), 4, 17),
     ("column 7x1", lambda: random_instance(7, 1, 0.8, 4, seed=15), 4, 17),
+    ("ea 12 D64", lambda: ea_pm(12, 1.0, 64, seed=16), 64, 19),
 ]
 
 
@@ -301,4 +302,63 @@ def test_sample_steps_rejects_bad_sizes():
     s, _ = gpu_sampler_with_oracle_env(inst, 4, FP32)
     with pytest.raises(TNError):
         s.sample_steps(8, 0, 1)
+    s.close()
+
+
+def test_incremental_build_equals_one_call():
+    from paper_2104_13264_amd import Sampler, TNError
+    inst = random_instance(9, 8, 0.7, 6, seed=54, field_scale=0.1)
+    a = Sampler()
+    lza = a.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 6, FP32)
+    b = Sampler()
+    seen = []
+    lzb = b.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 6, FP32,
+                      progress=lambda done, tot: seen.append((done, tot)), rows_per_call=3)
+    assert lza == lzb and seen[-1] == (8, 8) and len(seen) == 3
+    for x, y in zip(a.get_env()[:3], b.get_env()[:3]):
+        assert np.array_equal(x, y)
+    pa, pb = a.sample(20, 3), b.sample(20, 3)
+    for x, y in zip(pa, pb):
+        assert torch.equal(x, y)
+    # calls on a context whose build is open fail
+    from paper_2104_13264_amd.tnmh import lib, _ptr, _dev64
+    Jh, Jv = _dev64(inst.Jh, b.device), _dev64(inst.Jv, b.device)
+    assert lib().tn_build_env_begin(b._ctx, 8, 9, _ptr(Jh), _ptr(Jv), None, 0.7, 6, FP32) == 0
+    with pytest.raises(TNError):
+        b.sample(4, 1)
+    a.close()
+    b.close()
+
+
+BF16_CASES = [
+    ("ragged 9x11 D5", lambda: random_instance(9, 11, 0.7, 5, seed=12, field_scale=0.2), 5, 53),
+    ("ea 12 D20", lambda: ea_pm(12, 1.0, 20, seed=13), 20, 33),
+    ("frustrated 10 D33", lambda: fully_frustrated(10, 1.0, 33), 33, 21),
+    ("ea 12 D64", lambda: ea_pm(12, 1.0, 64, seed=16), 64, 19),
+]
+
+
+@pytest.mark.parametrize("name,mk,D,B", BF16_CASES, ids=[c[0] for c in BF16_CASES])
+def test_bf16_sampler_against_oracle(name, mk, D, B):
+    # BF16 operands (8 significant bits, unit roundoff u = 2^-8) with fp32
+    # accumulation: every column step rounds the carried row vector and the
+    # environment tiles once, so over the 2*Lx*Ly roundings along a
+    # configuration the ln q error behaves like u*sqrt(2*Lx*Ly) when the
+    # rounding errors are independent; the bound below allows 8 times that.
+    # What must hold exactly: ln q of a drawn configuration is the value the
+    # BF16 arithmetic gives when it evaluates that configuration again.
+    inst = mk()
+    log(f"[bf16 sampler] {name} Ly={inst.Ly} Lx={inst.Lx} D={D} B={B}")
+    s, envs = gpu_sampler_with_oracle_env(inst, D, BF16)
+    m = model_of(inst)
+    sp, lq, E = s.sample(B, 777, step=2, first_id=9)
+    lq2, E2 = s.eval_logq(sp)
+    assert torch.equal(lq2, lq) and torch.equal(E2, E)
+    sp, lq, E = sp.cpu().numpy(), lq.cpu().numpy(), E.cpu().numpy()
+    ev = sampler.eval_logq(m, envs, sp)
+    np.testing.assert_allclose(E, ev['energy'], rtol=1e-13, atol=1e-12)
+    bound = 8 * 2.0 ** -8 * np.sqrt(2 * inst.Lx * inst.Ly)
+    dev = np.abs(lq - ev['logq'])
+    log(f"  max |ln q_bf16 - ln q_fp64| {dev.max():.3e} (mean {dev.mean():.3e}, bound {bound:.3e})")
+    assert np.all(np.isfinite(lq)) and dev.max() <= bound
     s.close()
