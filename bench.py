@@ -288,7 +288,7 @@ def run_antiferro256(steps, warmup, n_eval=2048):
             "env_build_s": build_s, "logZ": lz}
 
 
-def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8):
+def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8, fd_bonds=2):
     """128x128 fully frustrated lattice, beta = 1, D = 32: d ln Z~ / dJ and
     d ln Z~ / d beta (tn_grad), timed, beside the chain's own estimates of
     beta <s_i s_j> on a few bonds and of -<E>."""
@@ -310,24 +310,37 @@ def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8):
     state = s.init_state(chains)
     rng = np.random.default_rng(SEED)
     pick = [(int(rng.integers(0, 128)), int(rng.integers(0, 127))) for _ in range(bonds)]
-    corr = np.zeros(bonds)
-    e_sum = 0.0
-    n = 0
+    corr = [[] for _ in range(bonds)]
+    en = []
     for t in range(warmup + steps):
         s.mh_step(state, SEED, t)
         if t >= warmup:
             sp = state["spins"].double()
             for k, (r, c) in enumerate(pick):
-                corr[k] += float((sp[:, r, c] * sp[:, r, c + 1]).mean())
-            e_sum += float(state["energy"].mean())
-            n += 1
+                corr[k].append(float((sp[:, r, c] * sp[:, r, c + 1]).mean()))
+            en.append(float(state["energy"].mean()))
     st = s.stats()
-    s.close()
     g = dJh.cpu().numpy()
+    # central differences of the rebuilt ln Z~ (truncations free to move) on
+    # the first fd_bonds bonds, step 1e-4
+    fd = []
+    for k, (r, c) in enumerate(pick[:fd_bonds]):
+        vals = []
+        for sgn in (1.0, -1.0):
+            Jh = inst.Jh.copy()
+            Jh[r, c] += sgn * 1e-4
+            vals.append(s.build_env(Jh, inst.Jv, inst.h, inst.beta, inst.D, FP32))
+        fd.append((vals[0] - vals[1]) / 2e-4)
+        log(f"[bench] frustrated128: finite difference {k + 1}/{fd_bonds}")
+    s.close()
+    err = lambda xs: float(np.std(xs) / np.sqrt(len(xs)))
     return {"workload": "frustrated128_D32", "env_build_s": build_s, "grad_s": grad_s, "logZ": lz,
-            "dlogZ_dbeta": db, "chain_minus_mean_energy": -e_sum / n,
+            "dlogZ_dbeta": db, "chain_minus_mean_energy": -float(np.mean(en)),
+            "chain_minus_mean_energy_err": err(en),
             "bonds": pick, "grad_dJh": [float(g[r, c]) for r, c in pick],
-            "chain_beta_corr": [float(inst.beta * x / n) for x in corr],
+            "chain_beta_corr": [float(inst.beta * np.mean(x)) for x in corr],
+            "chain_beta_corr_err": [inst.beta * err(x) for x in corr],
+            "fd_dJh": fd, "grad_finite": bool(np.isfinite(g).all()),
             "acceptance": st["accepted"] / max(st["proposed"], 1), "chains": chains, "steps": steps}
 
 

@@ -53,14 +53,22 @@ def compress(X, D):
     """
     X = [x.copy() for x in X]
     Lx = len(X)
-    # left-to-right QR sweep: X_c <- Q, X_{c+1} <- R X_{c+1}
+    # left-to-right QR sweep: X_c <- Q, X_{c+1} <- R X_{c+1}; the carried
+    # factor is brought back to unit norm at every step and its norm logged
+    # (a row's weight can pass the fp64 range before the sweep ends)
+    lognorm = 0.0
     for c in range(Lx - 1):
         a, u, b = X[c].shape
         q, r = np.linalg.qr(X[c].reshape(a * u, b))
         X[c] = q.reshape(a, u, q.shape[1])
         X[c + 1] = np.einsum('ij,jub->iub', r, X[c + 1])
+        s = np.linalg.norm(X[c + 1])
+        if s > 0.0:
+            X[c + 1] = X[c + 1] / s
+            lognorm += np.log(s)
     n = np.linalg.norm(X[Lx - 1])
     X[Lx - 1] = X[Lx - 1] / n
+    lognorm += np.log(n)
     truncated = []
     # right-to-left SVD sweep with truncation to D
     for c in range(Lx - 1, 0, -1):
@@ -73,7 +81,7 @@ def compress(X, D):
         X[c - 1] = np.einsum('aub,bk->auk', X[c - 1], U[:, :chi] * S[:chi])
     m = np.linalg.norm(X[0])
     X[0] = X[0] / m
-    return X, np.log(n) + np.log(m), truncated
+    return X, lognorm + np.log(m), truncated
 
 
 def row_overlap(model, r, env_below):

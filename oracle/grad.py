@@ -46,17 +46,24 @@ def cstar(envs):
 def project(X, E, c0):
     """P_{c0} applied to the MPS X (list of [a,u,b]): overlap of columns
     c0.. with the right-isometric env tensors E[c0..], absorbed into column
-    c0-1.  c0 = None is the identity."""
+    c0-1.  c0 = None is the identity.  Returns (tensors, ln scale): the
+    overlap is kept at unit largest entry while it is carried and the removed
+    scale is returned in logs (it can pass the fp64 range)."""
     if c0 is None:
-        return [x.copy() for x in X]
+        return [x.copy() for x in X], 0.0
     Lx = len(X)
     O = np.ones((1, 1))
+    logscale = 0.0
     for c in range(Lx - 1, c0 - 1, -1):
         O = np.einsum('aub,eud,bd->ae', X[c], E[c], O)
+        m = np.abs(O).max()
+        if m > 0.0:
+            O = O / m
+            logscale += np.log(m)
     out = [X[c].copy() for c in range(c0 - 1)]
     out.append(np.einsum('aub,be->aue', X[c0 - 1], O))
     out.extend(E[c].copy() for c in range(c0, Lx))
-    return out
+    return out, logscale
 
 
 def exact_compress(X):
@@ -75,9 +82,9 @@ def frozen_logZ(model, envs, cs=None):
     logs = 0.0
     for k in range(Ly - 1, 0, -1):
         X = bmps.apply_row(model, k, phi)
-        X = project(X, envs['env'][k], cs[k])
+        X, lp = project(X, envs['env'][k], cs[k])
         phi, ln = exact_compress(X)
-        logs += ln
+        logs += ln + lp
     lo, sign = bmps.row_overlap(model, 0, phi)
     return logs + lo
 
@@ -258,7 +265,7 @@ def grad_frozen(model, envs):
             t = np.einsum('yuz,ludx->yldzx', U[c], M)
             y_, l_, d_, z_, x_ = t.shape
             Y.append(t.reshape(y_ * l_, d_, z_ * x_))
-        Y = project(Y, envs['env'][k + 1], cs[k + 1])
+        Y, _ = project(Y, envs['env'][k + 1], cs[k + 1])
         U, _ = exact_compress(Y)
     r0 = max(kb - 1, 0)
     g = strip_site_envs(model, r0, U)

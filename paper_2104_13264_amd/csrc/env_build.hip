@@ -275,16 +275,25 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
     }
     __syncthreads();
 
-    // ---- left-to-right QR sweep: X_c <- Q, X_{c+1} <- R X_{c+1}
+    // ---- left-to-right QR sweep: X_c <- Q, X_{c+1} <- R X_{c+1} / |X_c|.
+    // The carried factor is kept at unit norm and its norm logged: a row's
+    // weight can pass the fp64 range before the sweep ends.
+    double lognorm = 0.0;
     for (int c = 0; c + 1 < Lx; ++c) {
         double *X = xbox + c * box, *Xn = xbox + (c + 1) * box;
         const int m = 2 * mX[c], n = nX[c], n1 = nX[c + 1];
         const int lda = m | 1;   // odd leading dimension: lanes of a row on distinct banks
+        double x2 = 0.0;
         for (int t = threadIdx.x; t < m * n; t += blockDim.x) {
             const int r = t / n, j = t % n;
-            QA[(size_t)j * lda + r] = X[r * ld + j];
+            const double v = X[r * ld + j];
+            QA[(size_t)j * lda + r] = v;
+            x2 += v * v;
         }
-        __syncthreads();
+        x2 = tn_block_sum(x2, red);   // ends with a barrier: QA is complete
+        const double xn = sqrt(x2);
+        const double xinv = xn > 0.0 ? 1.0 / xn : 1.0;
+        if (xn > 0.0) lognorm += log(xn);
         qw_householder(QA, m, n, lda, tau);
         const int kk = min(m, n);
         qw_form_q(QA, m, n, lda, tau, QB, lda);
@@ -304,7 +313,7 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
             const int p = t / w1, e = t % w1;
             double acc = 0.0;
             for (int q = p; q < n; ++q) acc += QA[(size_t)q * lda + p] * QB[q * w1 + e];
-            Xn[(p * 2 + e / n1) * ld + e % n1] = acc;
+            Xn[(p * 2 + e / n1) * ld + e % n1] = acc * xinv;
         }
         if (threadIdx.x == 0) {
             mX[c + 1] = kk;
@@ -313,8 +322,8 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
         __syncthreads();
     }
 
-    // ---- normalise the last column (its norm is the norm of the state)
-    double lognorm;
+    // ---- normalise the last column (with the logged factors, its norm is
+    // the norm of the state)
     {
         double *X = xbox + (Lx - 1) * box;
         const int m = mX[Lx - 1], n = nX[Lx - 1];
@@ -330,7 +339,7 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
             const int r = t / n, j = t % n;
             X[r * ld + j] *= inv;
         }
-        lognorm = log(nrm);
+        lognorm += log(nrm);
         __syncthreads();
     }
 

@@ -379,6 +379,7 @@ k_project_qr(int kenv, int cs, int Lx, int D, const double *__restrict__ env,
              int *__restrict__ status) {
     __shared__ int mY[TN_MAX_LX_G + 1], nY[TN_MAX_LX_G + 1];
     __shared__ double tau[2 * UM];
+    __shared__ double red[16];
     const int ld = 2 * UM;
     const size_t box = (size_t)8 * UM * UM;
     for (int c = threadIdx.x; c < Lx; c += blockDim.x) {
@@ -416,6 +417,14 @@ k_project_qr(int kenv, int cs, int Lx, int D, const double *__restrict__ env,
                         acc += T[(a * 2 + u) * dOr + e2] * E[e * 2 * D + u * D + e2];
                 On[a * UM + e] = acc;
             }
+            __syncthreads();
+            // keep the carried overlap at unit scale (the scale is free)
+            double om = 0.0;
+            for (int t = threadIdx.x; t < a_n * eL; t += blockDim.x)
+                om = fmax(om, fabs(On[(t / eL) * UM + t % eL]));
+            om = tn_block_max(om, red);
+            if (om > 0.0)
+                for (int t = threadIdx.x; t < a_n * eL; t += blockDim.x) On[(t / eL) * UM + t % eL] /= om;
             __syncthreads();
             double *tmp = O;
             O = On;
@@ -473,9 +482,13 @@ k_project_qr(int kenv, int cs, int Lx, int D, const double *__restrict__ env,
             Q[t] = acc;
         }
         __syncthreads();
+        double xm = 0.0;
+        for (int t = threadIdx.x; t < kk * 2 * n1; t += blockDim.x) xm = fmax(xm, fabs(Q[t]));
+        xm = tn_block_max(xm, red);
+        const double xinv = xm > 0.0 ? 1.0 / xm : 1.0;
         for (int t = threadIdx.x; t < kk * 2 * n1; t += blockDim.x) {
             const int p = t / (2 * n1), rem = t % (2 * n1), u = rem / n1, j = rem % n1;
-            Xn[(p * 2 + u) * ld + j] = Q[t];
+            Xn[(p * 2 + u) * ld + j] = Q[t] * xinv;
         }
         if (threadIdx.x == 0) {
             mY[c + 1] = kk;
@@ -491,22 +504,26 @@ k_project_qr(int kenv, int cs, int Lx, int D, const double *__restrict__ env,
     }
     __syncthreads();
     if (!status[0]) return;
-    // U <- Y, rescaled by its largest entry
-    __shared__ double red[16];
+    // U <- Y.  After the sweep the columns left of m - 1 are isometries and
+    // those from m on are env tensors, so the state's scale sits in column
+    // m - 1 alone: divide that column by its largest entry.  The derivative
+    // is a ratio of two contractions of the same upper state, so the scale is
+    // free; without it the state grows by the row's partition-function ratio
+    // every row and leaves the fp64 range.
+    const int cn = m - 1;
     double mx = 0.0;
-    for (int c = 0; c < Lx; ++c)
-        for (int t = threadIdx.x; t < mY[c] * 2 * nY[c]; t += blockDim.x) {
-            const int j = t % nY[c], r = t / nY[c];
-            mx = fmax(mx, fabs(Y[c * box + r * ld + j]));
-        }
+    for (int t = threadIdx.x; t < mY[cn] * 2 * nY[cn]; t += blockDim.x) {
+        const int j = t % nY[cn], r = t / nY[cn];
+        mx = fmax(mx, fabs(Y[cn * box + r * ld + j]));
+    }
     mx = tn_block_max(mx, red);
-    (void)mx;
+    const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
     for (size_t t = threadIdx.x; t < (size_t)Lx * 2 * UM * UM; t += blockDim.x) {
         const int c = (int)(t / (2 * UM * UM));
         const int rem = (int)(t % (2 * UM * UM));
         const int y = rem / (2 * UM), u = (rem / UM) & 1, z = rem % UM;
         double v = 0.0;
-        if (y < mY[c] && z < nY[c]) v = Y[c * box + (y * 2 + u) * ld + z];
+        if (y < mY[c] && z < nY[c]) v = Y[c * box + (y * 2 + u) * ld + z] * (c == cn ? inv : 1.0);
         U[t] = v;
     }
     for (int c = threadIdx.x; c <= Lx; c += blockDim.x) ud[c] = c < Lx ? mY[c] : 1;

@@ -24,6 +24,11 @@ CASES = [
     ("ragged 11x7 D5 field", lambda: random_instance(11, 7, 0.6, 5, seed=9, field_scale=0.2), 5),
     ("strip 1x6", lambda: random_instance(1, 6, 0.6, 4, seed=10), 4),
     ("column 6x1", lambda: random_instance(6, 1, 0.6, 4, seed=11), 4),
+    # ln Z~ beyond the fp64 exponent range: the upper state must stay rescaled
+    ("ferro 20x12 beta3 D4", lambda: ferro(20, 3.0, 4, Lx=12), 4),
+    ("frustrated 26x14 beta2 D6", lambda: fully_frustrated(26, 2.0, 6, Lx=14), 6),
+    ("frustrated 6x128 beta3 D4", lambda: fully_frustrated(6, 3.0, 4, Lx=128), 4),
+    ("frustrated 16x48 beta1 D8", lambda: fully_frustrated(16, 1.0, 8, Lx=48), 8),
 ]
 
 

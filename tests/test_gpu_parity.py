@@ -39,6 +39,9 @@ ENV_CASES = [
     ("column 7x1", lambda: random_instance(7, 1, 0.8, 4, seed=5), 4),
     ("beta0 6x5", lambda: random_instance(6, 5, 0.0, 3, seed=6), 3),
     ("ea 10 D40", lambda: ea_pm(10, 0.7, 40, seed=8), 40),
+    # row weights past the fp64 range (e^400 .. e^765 a row)
+    ("ferro 3x128 beta3 D4", lambda: ferro(3, 3.0, 4, Lx=128), 4),
+    ("frustrated 6x128 beta3 D4", lambda: fully_frustrated(6, 3.0, 4, Lx=128), 4),
 ]
 
 
@@ -65,6 +68,7 @@ SAMPLER_CASES = [
     ("strip 1x9", lambda: random_instance(1, 9, 0.8, 4, seed=14), 4, 17),
     ("column 7x1", lambda: random_instance(7, 1, 0.8, 4, seed=15), 4, 17),
     ("ea 12 D64", lambda: ea_pm(12, 1.0, 64, seed=16), 64, 19),
+    ("frustrated 6x128 beta3 D4", lambda: fully_frustrated(6, 3.0, 4, Lx=128), 4, 9),
 ]
 
 

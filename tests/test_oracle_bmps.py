@@ -28,6 +28,19 @@ def test_untruncated_8x8_equals_transfer_matrix():
     assert abs(env['logZ'] - exact.transfer_logZ(Jh, Jv, None, 0.44)) < 1e-12 * 60
 
 
+def test_row_weight_beyond_fp64_range():
+    # 3 x 128 ferromagnet at beta = 3: one row carries about e^765, past the
+    # largest double; untruncated at D = 4, so ln Z~ is the exact value (the
+    # transfer matrix runs along the transposed lattice, 3 spins wide)
+    Ly, Lx, beta = 3, 128, 3.0
+    Jh, Jv = uniform(Ly, Lx, 1.0)
+    env = bmps.build_envs(ising.Model(Jh, Jv, None, beta), 4)
+    assert not any(env['trunc'])
+    lz = exact.transfer_logZ(Jv.T.copy(), Jh.T.copy(), None, beta)
+    assert lz > 1800
+    assert abs(env['logZ'] - lz) < 1e-12 * lz
+
+
 def test_truncation_error_shrinks_with_D():
     inst = random_instance(8, 8, 1.0, 1, seed=5)
     lz = exact.transfer_logZ(inst.Jh, inst.Jv, None, inst.beta)

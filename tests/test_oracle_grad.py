@@ -76,6 +76,36 @@ def test_truncated_derivative_matches_finite_differences(mk, D):
     assert abs(fd(mb, env) - g['dbeta']) < 1e-7
 
 
+def test_derivative_with_row_weights_beyond_fp64_range():
+    # 6 x 128 fully frustrated lattice at beta = 3 with D = 4: each row weighs
+    # about e^400 and ln Z~ is about 2460.  The derivative must stay finite
+    # and match central differences of the frozen contraction.  Rounding of
+    # ln Z~ ~ 2460 limits the difference quotient: at eps = 1e-4 it is good to
+    # a few 1e-7 (at 1e-5 the rounding term is ten times larger).
+    inst = fully_frustrated(6, 3.0, 4, Lx=128)
+    m = model_of(inst)
+    env = bmps.build_envs(m, 4)
+    assert any(env['trunc']) and env['logZ'] > 2000
+    g = grad.grad_frozen(m, env)
+    assert np.isfinite(g['dJh']).all() and np.isfinite(g['dJv']).all()
+    rng = np.random.default_rng(2)
+    for _ in range(4):
+        r, c = rng.integers(inst.Ly), rng.integers(inst.Lx - 1)
+
+        def mh(e, r=r, c=c):
+            Jh = inst.Jh.copy()
+            Jh[r, c] += e
+            return ising.Model(Jh, inst.Jv, inst.h, inst.beta)
+        assert abs(fd(mh, env, 1e-4) - g['dJh'][r, c]) < 5e-7
+        r, c = rng.integers(inst.Ly - 1), rng.integers(inst.Lx)
+
+        def mv(e, r=r, c=c):
+            Jv = inst.Jv.copy()
+            Jv[r, c] += e
+            return ising.Model(inst.Jh, Jv, inst.h, inst.beta)
+        assert abs(fd(mv, env, 1e-4) - g['dJv'][r, c]) < 5e-7
+
+
 def test_beta_identity_without_field():
     # Z~_frozen depends on beta and J only through K = beta J: beta d_beta = sum J d_J
     inst = random_instance(8, 7, 0.9, 3, seed=12)
