@@ -307,6 +307,11 @@ def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8, fd_bonds=2):
     torch.cuda.synchronize()
     grad_s = time.perf_counter() - t1
     log(f"[bench] frustrated128: build {build_s:.1f} s, gradient {grad_s:.1f} s")
+    t1 = time.perf_counter()
+    tJh, tJv, tdb = s.grad(two_sided=True)
+    torch.cuda.synchronize()
+    two_s = time.perf_counter() - t1
+    log(f"[bench] frustrated128: two-sided estimate {two_s:.1f} s (with the upside-down build)")
     state = s.init_state(chains)
     rng = np.random.default_rng(SEED)
     pick = [(int(rng.integers(0, 128)), int(rng.integers(0, 127))) for _ in range(bonds)]
@@ -321,6 +326,7 @@ def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8, fd_bonds=2):
             en.append(float(state["energy"].mean()))
     st = s.stats()
     g = dJh.cpu().numpy()
+    g2 = tJh.cpu().numpy()
     # central differences of the rebuilt ln Z~ (truncations free to move) on
     # the first fd_bonds bonds, step 1e-4
     fd = []
@@ -341,6 +347,8 @@ def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8, fd_bonds=2):
             "chain_beta_corr": [float(inst.beta * np.mean(x)) for x in corr],
             "chain_beta_corr_err": [inst.beta * err(x) for x in corr],
             "fd_dJh": fd, "grad_finite": bool(np.isfinite(g).all()),
+            "two_sided_s": two_s, "two_sided_dJh": [float(g2[r, c]) for r, c in pick],
+            "two_sided_dlogZ_dbeta": tdb,
             "acceptance": st["accepted"] / max(st["proposed"], 1), "chains": chains, "steps": steps}
 
 

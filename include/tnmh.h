@@ -239,6 +239,22 @@ int tn_graph_end_and_replay(tn_ctx *ctx, int n_replays);
  * Synchronises the stream. */
 int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
 
+/* Two-sided estimate of d ln Z / dJ and d ln Z / d beta, i.e. of beta times
+ * the bond correlations and of minus the mean energy (Sec. 4 compares energies
+ * from derivatives of the approximate contraction with sampled ones).  Every
+ * site's environment is the exact contraction of its row between the
+ * top-down boundary MPS of the rows above and the stored bottom-up
+ * environment of the rows below (App. A's recursion run from both sides),
+ * divided by that row's value.  Exact without truncation; with truncation it
+ * is not the derivative of ln Z~ (tn_grad is) but tracks the exact
+ * derivative far more closely on frustrated lattices.  The top-down boundary
+ * is the environment build of the upside-down lattice, made on the first call
+ * after a tn_build_env / tn_set_env and kept with the context.
+ *   dJh (dev, fp64 [Ly][Lx-1]), dJv (dev, fp64 [Ly-1][Lx]), dbeta (host, may
+ *   be NULL), as in tn_grad.  Errors: TN_ESTATE without an environment or
+ *   while capturing; TN_EINVAL for beta*J = 0.  Synchronises the stream. */
+int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
+
 typedef struct {
     uint64_t clamps;        /* conditional weights clamped to 0 */
     uint64_t both_nonpos;   /* sites drawn with p+ = 1/2 */

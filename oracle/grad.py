@@ -272,6 +272,14 @@ def grad_frozen(model, envs):
     for (r, c), gg in g.items():
         add(site_derivatives(model, r, c, gg))
 
+    out = _assemble(model, dK)
+    out.update(kb=kb, cstar=cs)
+    return out
+
+
+def _assemble(model, dK):
+    """d/dK and d/d(beta h) per bond and site -> dJh, dJv, d beta, dH."""
+    Ly, Lx, beta = model.Ly, model.Lx, model.beta
     dJh = np.zeros((Ly, Lx - 1))
     dJv = np.zeros((Ly - 1, Lx))
     dH = np.zeros((Ly, Lx))
@@ -285,4 +293,44 @@ def grad_frozen(model, envs):
     dbeta = ((dJh * model.Jh).sum() + (dJv * model.Jv).sum()) / beta if beta != 0 else 0.0
     if model.h is not None:
         dbeta += (dH * model.h).sum()
-    return dict(dJh=dJh, dJv=dJv, dbeta=dbeta, dH=dH, kb=kb, cstar=cs)
+    return dict(dJh=dJh, dJv=dJv, dbeta=dbeta, dH=dH)
+
+
+# ---------------------------------------------------------------------------
+# two-sided estimate: upper boundary built top-down, lower boundary bottom-up
+
+def upper_envs(model, D):
+    """Top-down boundary MPS: U[r] approximates rows 0..r-1 with their down
+    legs open (U[0] is the trivial boundary), built by the same
+    apply-and-compress step as the bottom-up environments (App. A), with the
+    row MPO applied from above."""
+    Ly, Lx = model.Ly, model.Lx
+    U = [None] * Ly
+    U[0] = bmps.trivial_env(Lx)
+    for r in range(1, Ly):
+        X = []
+        for c in range(Lx):
+            M = model.site_tensor(r - 1, c).sum(axis=0)    # [l,u,d,x]
+            t = np.einsum('aub,ludx->aldbx', U[r - 1][c], M)
+            a, l, d, b, x = t.shape
+            X.append(t.reshape(a * l, d, b * x))
+        U[r], _, _ = bmps.compress(X, D)
+    return U
+
+
+def grad_two_sided(model, envs, D=None):
+    """Estimate of d ln Z / dJh, dJv, d beta and d(beta h) from two
+    boundaries: every site's environment is the exact contraction of its row
+    between the top-down boundary of the rows above and the stored bottom-up
+    env of the rows below, divided by that row's value.  Exact when nothing
+    is truncated; it is not the derivative of ln Z~ (the frozen form is)."""
+    D = envs['D'] if D is None else D
+    Ly, Lx = model.Ly, model.Lx
+    U = upper_envs(model, D)
+    dK = {}
+    for r in range(Ly):
+        g = row_site_envs(model, r, U[r], envs['env'][r + 1])
+        for c in range(Lx):
+            for key, val in site_derivatives(model, r, c, g[c]).items():
+                dK[key] = dK.get(key, 0.0) + val
+    return _assemble(model, dK)

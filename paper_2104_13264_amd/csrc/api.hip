@@ -38,6 +38,11 @@ void free_all(tn_ctx *ctx) {
         free_all(k);
         delete k;
     }
+    if (ctx->flip) {
+        free_all(ctx->flip);
+        delete ctx->flip;
+        ctx->flip = nullptr;
+    }
     ctx->kids.clear();
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
@@ -63,6 +68,7 @@ int check_prec(tn_ctx *ctx, int prec) {
 int set_instance(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                  const double *h, double beta, int D, int prec) {
     ctx->building = false;   // a new instance abandons an open incremental build
+    ++ctx->env_gen;
     if (Lx < 1 || Ly < 1) return tn_fail(ctx, TN_EINVAL, "Lx and Ly must be >= 1");
     if (Lx > 256) return tn_fail(ctx, TN_EINVAL, "Lx above 256 is not supported");
     if (D < 1 || D > TN_MAX_D) return tn_fail(ctx, TN_EINVAL, "D must be in 1..64");
@@ -708,7 +714,65 @@ int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
     ctx->err.clear();
     if ((ctx->Lx > 1 && !dJh) || (ctx->Ly > 1 && !dJv))
         return tn_fail(ctx, TN_EINVAL, "NULL gradient buffer");
-    return tn_grad_device(ctx, dJh, dJv, dbeta);
+    return tn_grad_device(ctx, nullptr, dJh, dJv, dbeta);
+}
+
+int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
+    if ((ctx->Lx > 1 && !dJh) || (ctx->Ly > 1 && !dJv))
+        return tn_fail(ctx, TN_EINVAL, "NULL gradient buffer");
+    const int Lx = ctx->Lx, Ly = ctx->Ly;
+    if (ctx->flip_gen != ctx->env_gen) {
+        if (!ctx->flip) {
+            ctx->flip = new (std::nothrow) tn_ctx();
+            if (!ctx->flip) return tn_fail(ctx, TN_ENOMEM, "out of host memory");
+            tn_ctx *f = ctx->flip;
+            f->stream = ctx->stream;
+            f->device = ctx->device;
+            if (hipMalloc((void **)&f->counters, CNT_N * sizeof(unsigned long long)) != hipSuccess ||
+                hipMalloc((void **)&f->scal, 16 * sizeof(double)) != hipSuccess ||
+                hipMalloc((void **)&f->dstep, sizeof(uint64_t)) != hipSuccess ||
+                hipMalloc((void **)&f->xdims, 4096 * sizeof(int)) != hipSuccess ||
+                hipMemset(f->counters, 0, CNT_N * sizeof(unsigned long long)) != hipSuccess) {
+                (void)hipGetLastError();
+                free_all(f);
+                delete f;
+                ctx->flip = nullptr;
+                return tn_fail(ctx, TN_ENOMEM, "allocation for the upside-down build failed");
+            }
+        }
+        // the same couplings with the rows in reverse order
+        const size_t nh = (size_t)Ly * (Lx - 1), nv = (size_t)(Ly - 1) * Lx;
+        std::vector<double> hJh(nh), hJv(nv), fJh(nh), fJv(nv), hh, fh;
+        TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (nh) TN_HIP(ctx, hipMemcpy(hJh.data(), ctx->Jh, nh * sizeof(double), hipMemcpyDeviceToHost));
+        if (nv) TN_HIP(ctx, hipMemcpy(hJv.data(), ctx->Jv, nv * sizeof(double), hipMemcpyDeviceToHost));
+        for (int r = 0; r < Ly; ++r)
+            for (int c = 0; c + 1 < Lx; ++c) fJh[(size_t)r * (Lx - 1) + c] = hJh[(size_t)(Ly - 1 - r) * (Lx - 1) + c];
+        for (int r = 0; r + 1 < Ly; ++r)
+            for (int c = 0; c < Lx; ++c) fJv[(size_t)r * Lx + c] = hJv[(size_t)(Ly - 2 - r) * Lx + c];
+        if (ctx->h) {
+            hh.resize((size_t)Ly * Lx);
+            fh.resize(hh.size());
+            TN_HIP(ctx, hipMemcpy(hh.data(), ctx->h, hh.size() * sizeof(double), hipMemcpyDeviceToHost));
+            for (int r = 0; r < Ly; ++r)
+                for (int c = 0; c < Lx; ++c) fh[(size_t)r * Lx + c] = hh[(size_t)(Ly - 1 - r) * Lx + c];
+        }
+        tn_ctx *f = ctx->flip;
+        f->err.clear();
+        rc = set_instance(f, Lx, Ly, nh ? fJh.data() : nullptr, nv ? fJv.data() : nullptr,
+                          ctx->h ? fh.data() : nullptr, ctx->beta, ctx->D, TN_FP64);
+        if (rc == TN_OK) rc = tn_env_build_device(f, nullptr);
+        // set_instance copied from these host vectors on the stream
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == TN_OK) rc = TN_EHIP;
+        if (rc != TN_OK) return tn_fail(ctx, rc, "upside-down build: " + f->err);
+        ctx->flip_gen = ctx->env_gen;
+    }
+    return tn_grad_device(ctx, ctx->flip, dJh, dJv, dbeta);
 }
 
 int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset) {

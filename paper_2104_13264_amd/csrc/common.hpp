@@ -83,6 +83,10 @@ struct tn_ctx {
     bool building = false;
     int build_step = 0;
     void *build_plan = nullptr;   // tn_build_plan, owned
+    // two-sided derivative: the environments of the upside-down lattice,
+    // built on demand and kept while the instance (env_gen) is unchanged
+    tn_ctx *flip = nullptr;       // owned
+    uint64_t env_gen = 0, flip_gen = ~0ull;
     // graph capture (tn_graph_begin .. tn_graph_end_and_replay)
     bool capturing = false;
     int graph_steps = 0;
@@ -235,7 +239,9 @@ int tn_launch_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                      double *state_energy, uint8_t *accepted);
 
 // adjoint (grad.hip)
-int tn_grad_device(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
+// upper == nullptr: the frozen-truncation derivative of ln Z~; otherwise the
+// two-sided estimate with `upper` holding the upside-down lattice's envs.
+int tn_grad_device(tn_ctx *ctx, const tn_ctx *upper, double *dJh, double *dJv, double *dbeta);
 
 // ---------------------------------------------------------------------------
 // device helpers

@@ -529,6 +529,32 @@ k_project_qr(int kenv, int cs, int Lx, int D, const double *__restrict__ env,
     for (int c = threadIdx.x; c <= Lx; c += blockDim.x) ud[c] = c < Lx ? mY[c] : 1;
 }
 
+// Upper state of row r for the two-sided estimate: env kf of the upside-down
+// lattice (its rows 0..r-1, kf = Ly - r), one column per workgroup.  Upside
+// down, the vertical bond above row r has its P factor on the row-r site and
+// Q on the row r-1 site, so the open leg carries Q(mu, s_{r-1}); row r's own
+// tensor carries Q(mu, s_r) on its up leg.  P(s, mu) = sign(K)^mu Q(mu, s), so
+// multiplying leg mu = 1 by sign(K) restores the bond weight exp(K s s').
+__global__ void k_upper_from_flipped(int Lx, int D, int kf, const double *__restrict__ envf,
+                                     const int *__restrict__ dimsf, const double *__restrict__ Jv,
+                                     double beta, int r, double *__restrict__ U,
+                                     int *__restrict__ ud) {
+    const int c = blockIdx.x;
+    const int dl = dimsf[kf * (Lx + 1) + c], dr = dimsf[kf * (Lx + 1) + c + 1];
+    const double sg = beta * Jv[(size_t)(r - 1) * Lx + c] >= 0.0 ? 1.0 : -1.0;
+    const double *E = envf + ((size_t)kf * Lx + c) * 2 * D * D;
+    for (int t = threadIdx.x; t < 2 * UM * UM; t += blockDim.x) {
+        const int y = t / (2 * UM), u = (t / UM) & 1, z = t % UM;
+        double v = 0.0;
+        if (y < dl && z < dr) v = E[y * 2 * D + u * D + z] * (u ? sg : 1.0);
+        U[(size_t)c * 2 * UM * UM + t] = v;
+    }
+    if (threadIdx.x == 0) {
+        ud[c] = dl;
+        if (c == Lx - 1) ud[Lx] = 1;
+    }
+}
+
 __global__ void k_trivial_upper(int Lx, double *__restrict__ U, int *__restrict__ ud) {
     for (size_t t = blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)Lx * 2 * UM * UM;
          t += gridDim.x * blockDim.x) {
@@ -554,8 +580,9 @@ __global__ void k_grad_reduce(int Lx, int Ly, double beta, const double *__restr
 
 }  // namespace
 
-int tn_grad_device(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
-    if (!ctx->has_cst)
+int tn_grad_device(tn_ctx *ctx, const tn_ctx *upper, double *dJh, double *dJv, double *dbeta) {
+    const bool two = upper != nullptr;
+    if (!two && !ctx->has_cst)
         return tn_fail(ctx, TN_ESTATE, "tn_grad needs an environment built by tn_build_env");
     const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
     const double beta = ctx->beta;
@@ -571,20 +598,22 @@ int tn_grad_device(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
         hh.resize((size_t)Ly * Lx);
         TN_HIP(ctx, hipMemcpy(hh.data(), ctx->h, hh.size() * sizeof(double), hipMemcpyDeviceToHost));
     }
-    TN_HIP(ctx, hipMemcpy(cst.data(), ctx->cst, (Ly + 1) * sizeof(int), hipMemcpyDeviceToHost));
+    if (!two)
+        TN_HIP(ctx, hipMemcpy(cst.data(), ctx->cst, (Ly + 1) * sizeof(int), hipMemcpyDeviceToHost));
     for (double J : hJh)
         if (beta * J == 0.0) return tn_fail(ctx, TN_EINVAL, "a bond with beta*J = 0 has no derivative");
     for (double J : hJv)
         if (beta * J == 0.0) return tn_fail(ctx, TN_EINVAL, "a bond with beta*J = 0 has no derivative");
     if (Lx > TN_MAX_LX_G) return tn_fail(ctx, TN_EINVAL, "tn_grad supports Lx <= 256");
-    // bottom region: rows kb-1 .. Ly-1 with all envs below untruncated
+    // bottom region: rows kb-1 .. Ly-1 with all envs below untruncated (the
+    // two-sided estimate takes every row on its own: one-row strips only)
     int kb = Ly;
-    for (int k = Ly - 1; k >= 1; --k) {
+    for (int k = Ly - 1; k >= 1 && !two; --k) {
         if (cst[k] >= 0) break;
         kb = k;
     }
     const int r0 = kb - 1 < 0 ? 0 : kb - 1;
-    const int hb = Ly - r0;
+    const int hb = two ? 1 : Ly - r0;
     if (hb > TN_MAX_STRIP)
         return tn_fail(ctx, TN_EINVAL, "tn_grad: the untruncated bottom region is too tall ("
                                            + std::to_string(hb) + " rows)");
@@ -639,6 +668,19 @@ int tn_grad_device(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
         return TN_OK;
     };
 
+    if (two) {
+        // row r between the top-down boundary of rows 0..r-1 (env Ly - r of
+        // the upside-down lattice) and env r + 1 of this one
+        for (int r = 0; r < Ly; ++r) {
+            if (r > 0) {
+                hipLaunchKernelGGL(k_upper_from_flipped, dim3(Lx), dim3(256), 0, ctx->stream, Lx, D,
+                                   Ly - r, upper->env, upper->dims, ctx->Jv, beta, r, U, ud);
+                TN_HIP(ctx, hipGetLastError());
+            }
+            if ((rc = run_strip(r, 1, r + 1 < Ly ? r + 1 : -1))) return rc;
+        }
+        kb = 0;   // skips the frozen rows and the bottom strip below
+    }
     for (int k = 0; k + 1 < kb; ++k) {
         if ((rc = run_strip(k, 1, k + 1))) return rc;
         hipLaunchKernelGGL(k_bra_apply, dim3(Lx), dim3(256), 0, ctx->stream, k, Lx, Ly, beta,
@@ -654,7 +696,7 @@ int tn_grad_device(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
             return tn_fail(ctx, TN_EINVAL, "tn_grad: upper-state bond above 64 at row " +
                                                std::to_string(k + 1));
     }
-    if ((rc = run_strip(r0, hb, -1))) return rc;
+    if (!two && (rc = run_strip(r0, hb, -1))) return rc;
     const int nb = Ly * (Lx - 1) + (Ly - 1) * Lx;
     if (nb > 0) {
         hipLaunchKernelGGL(k_grad_reduce, dim3((nb + 255) / 256), dim3(256), 0, ctx->stream, Lx, Ly,

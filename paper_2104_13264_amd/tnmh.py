@@ -74,6 +74,7 @@ def lib():
         "tn_mh_run": (i, [vp, i, i, u64, u64, vp, vp, vp, vp, vp]),
         "tn_mh_accept": (i, [vp, i, u64, u64, vp, vp, vp, vp, vp, vp, vp]),
         "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
+        "tn_grad_two_sided": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
     }
     for name, (res, args) in sig.items():
@@ -90,7 +91,7 @@ def exported_symbols():
             "tn_build_env_rows", "tn_build_env_end", "tn_sample",
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
-            "tn_graph_end_and_replay", "tn_grad", "tn_stats"]
+            "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats"]
 
 
 def _ptr(t):
@@ -306,11 +307,15 @@ class Sampler:
                                        _ptr(state["energy"]), _ptr(state["accepted"])))
         return state["accepted"]
 
-    def grad(self):
+    def grad(self, two_sided=False):
+        """(dJh, dJv, dbeta): the frozen-truncation derivative of ln Z~
+        (tn_grad), or with two_sided=True the two-sided estimate of the
+        derivative of ln Z (tn_grad_two_sided)."""
         dJh = torch.zeros((self.Ly, self.Lx - 1), dtype=torch.float64, device=self.device)
         dJv = torch.zeros((self.Ly - 1, self.Lx), dtype=torch.float64, device=self.device)
         db = ctypes.c_double()
-        self._check(lib().tn_grad(self._ctx, _ptr(dJh), _ptr(dJv), ctypes.byref(db)))
+        fn = lib().tn_grad_two_sided if two_sided else lib().tn_grad
+        self._check(fn(self._ctx, _ptr(dJh), _ptr(dJv), ctypes.byref(db)))
         return dJh, dJv, db.value
 
     def stats(self, reset=False):

@@ -102,3 +102,50 @@ def test_autograd_function_matches_tn_grad_and_brute_force():
     cfg, E, _, lp = exact.brute_force(inst.Jh, inst.Jv, None, inst.beta)
     assert abs(float(gb) / 2.0 + float(np.dot(np.exp(lp), E))) < 1e-10
     s.close()
+
+
+TWO_SIDED_CASES = [
+    ("4x4 untruncated field", lambda: random_instance(4, 4, 0.8, 8, seed=31, field_scale=0.3), 8),
+    ("9x10 D4", lambda: random_instance(9, 10, 0.7, 4, seed=32), 4),
+    ("ragged 11x7 D5 field", lambda: random_instance(11, 7, 0.6, 5, seed=33, field_scale=0.2), 5),
+    ("frustrated 14x12 D4", lambda: fully_frustrated(14, 1.0, 4, Lx=12), 4),
+    ("ea 12 D8", lambda: ea_pm(12, 1.0, 8, seed=34), 8),
+    ("strip 1x6", lambda: random_instance(1, 6, 0.6, 4, seed=35), 4),
+    ("column 6x1", lambda: random_instance(6, 1, 0.6, 4, seed=36), 4),
+    ("frustrated 6x128 beta3 D4", lambda: fully_frustrated(6, 3.0, 4, Lx=128), 4),
+]
+
+
+@pytest.mark.parametrize("name,mk,D", TWO_SIDED_CASES, ids=[c[0] for c in TWO_SIDED_CASES])
+def test_two_sided_matches_oracle(name, mk, D):
+    # same tolerances as the frozen derivative: fp64 contractions on both
+    # sides, the top-down boundary built by the upside-down build on the GPU
+    # and by a top-down recursion in the oracle (equal up to a +-1 leg gauge)
+    from paper_2104_13264_amd import Sampler
+    inst = mk()
+    print(f"[grad two-sided] {name} Ly={inst.Ly} Lx={inst.Lx} D={D}", flush=True)
+    m = ising.Model(inst.Jh, inst.Jv, inst.h, inst.beta)
+    ref = grad.grad_two_sided(m, bmps.build_envs(m, D))
+    s = Sampler()
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, D)
+    for _ in range(2):      # the second call reuses the upside-down build
+        dJh, dJv, db = s.grad(two_sided=True)
+        np.testing.assert_allclose(dJh.cpu().numpy(), ref['dJh'], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(dJv.cpu().numpy(), ref['dJv'], rtol=0, atol=1e-9)
+        assert abs(db - ref['dbeta']) <= 1e-9 * max(1.0, abs(ref['dbeta']))
+    s.close()
+
+
+def test_two_sided_follows_a_new_instance():
+    from paper_2104_13264_amd import Sampler
+    a = random_instance(5, 6, 0.7, 3, seed=37)
+    b = random_instance(5, 6, 0.9, 3, seed=38)
+    s = Sampler()
+    s.build_env(a.Jh, a.Jv, None, a.beta, 3)
+    s.grad(two_sided=True)
+    s.build_env(b.Jh, b.Jv, None, b.beta, 3)
+    dJh, _, _ = s.grad(two_sided=True)
+    m = ising.Model(b.Jh, b.Jv, None, b.beta)
+    ref = grad.grad_two_sided(m, bmps.build_envs(m, 3))
+    np.testing.assert_allclose(dJh.cpu().numpy(), ref['dJh'], rtol=0, atol=1e-9)
+    s.close()
