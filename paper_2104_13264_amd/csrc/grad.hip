@@ -81,7 +81,7 @@ __device__ void site_tensor(int r, int c, int Lx, int Ly, double beta, const dou
             Dd[m] = hd ? tn_pleg(Kd, s, m) : (m == 0 ? 1.0 : 0.0);
         }
         // d/dK of P(s,0) = Q(0,s) = sqrt(cosh K): sinh K / (2 sqrt(cosh K));
-        // of P(s,1) = sign(K) s sqrt|sinh K|: sign(K) s cosh K / (2 sqrt|sinh K|);
+        // of P(s,1) = s sqrt|sinh K|: sign(K) s cosh K / (2 sqrt|sinh K|);
         // of Q(1,s) = sign(K) s sqrt|sinh K|: s cosh K / (2 sqrt|sinh K|)
         auto d0 = [](double K) { return sinh(K) / (2.0 * sqrt(cosh(K))); };
         auto d1 = [](double K) { return cosh(K) / (2.0 * sqrt(fabs(sinh(K)))); };
