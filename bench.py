@@ -59,11 +59,12 @@ def tau_int(E, burn=0.1, c=6.0):
 
 def ahead_steps(chains):
     """MH steps whose proposals share one sampler launch: enough 16-proposal
-    workgroups for two per compute unit (proposals do not depend on the
-    chains' state, Sec. 2, so drawing them ahead leaves the chains unchanged)."""
+    wavefronts for two per SIMD (two four-wave teams per compute unit;
+    proposals do not depend on the chains' state, Sec. 2, so drawing them
+    ahead leaves the chains unchanged)."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    return max(1, -(-2 * 16 * cus // chains))
+    return max(1, -(-8 * 16 * cus // chains))
 
 
 def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):
@@ -127,6 +128,9 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):
     wall = time.perf_counter() - t_start
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     full = [ms for ms, mm in zip(kern_ms, launch_sizes) if mm == m]
+    if full:
+        log(f"[bench] sampler launches: min {min(full):.3f} median {float(np.median(full)):.3f} "
+            f"max {max(full):.3f} ms ({len(full)} launches of {m} steps)")
     st = s.stats()
     E = E_series.cpu().numpy()
     s.close()
@@ -363,7 +367,7 @@ def kernel_source_hash():
 def measured_traffic(proposals_per_launch):
     """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
     they were taken on the current kernel source and launch size."""
-    p = os.path.join(ROOT, "profiles", "sampler_mfma_ferro64_traffic.json")
+    p = os.path.join(ROOT, "profiles", "sampler_team_ferro64_traffic.json")
     try:
         with open(p) as fh:
             d = json.load(fh)
@@ -384,7 +388,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
     ap.add_argument("--ahead", type=int, default=None,
-                    help="MH steps per sampler launch (default: enough for two workgroups per CU)")
+                    help="MH steps per sampler launch (default: enough for two four-wave teams per CU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="ferro64",
@@ -460,7 +464,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic,
-                     "kernel": "k_sampler_mfma<2,false>",
+                     "kernel": "k_sampler_team<2,false>",
                      "flops_per_launch": flops_launch,
                      "proposals_per_launch": C * res32["steps_per_launch"],
                      "kernel_ms": res32["sampler_ms"]},

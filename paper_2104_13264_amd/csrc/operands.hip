@@ -11,10 +11,11 @@
 //   G32R, G32L                              fp32 MFMA A-operand tiles of G and
 //   G16R, G16L                              G^T (bf16 for the bf16 path)
 // Tile layout for v_mfma_f32_16x16x4f32 with padded bond Dp = 16*NT:
-//   index ((((r*Lx + c)*2 + s)*NT + mo)*NQ + q)*64 + lane,  NQ = Dp/4,
-//   q = 4*mt + i, lane -> row 16*mo + lane%16, col 16*mt + 4*(lane/16) + i,
+//   index (((((r*Lx + c)*2 + s)*NT + mo)*NT + mt)*64 + lane)*4 + i,
+//   k-chunk q = 4*mt + i, lane -> row 16*mo + lane%16, col 16*mt + 4*(lane/16) + i,
 // which makes the k-chunk q of the next product equal to accumulator register
-// i of output tile mt, so chained products need no data movement.
+// i of output tile mt, so chained products need no data movement; a lane's
+// four chunks of one (mo, mt) are 16 contiguous bytes (one load).
 // The bf16 tiles (v_mfma_f32_16x16x16_bf16) use chunk q = mt, lane -> row
 // 16*mo + lane%16, cols 16*mt + 4*(lane/16) + i for i = 0..3 packed in 8 bytes.
 //
@@ -64,11 +65,13 @@ k_make_ops(int Lx, int Ly, int D, int Dp, double beta, const double *__restrict_
             G64c[site * 2 * D * D + (s * D + b) * D + a] = gsh[(s * Dp + a) * Dp + b];
         }
     }
-    const int NT = Dp / 16, NQ = Dp / 4;
+    const int NT = Dp / 16;
     if (G32R) {
+        // [s][mo][mt][lane][i]: lane holds k-chunks q = 4 mt + i (i = 0..3) of
+        // output block mo, 16 contiguous bytes
         for (int t = threadIdx.x; t < 2 * Dp * Dp; t += blockDim.x) {
-            const int lane = t & 63, q = (t >> 6) % NQ, mo = (t >> 6) / NQ % NT, s = t / (Dp * Dp);
-            const int mt = q >> 2, i = q & 3;
+            const int i = t & 3, lane = (t >> 2) & 63, mt = (t >> 8) % NT, mo = (t >> 8) / NT % NT;
+            const int s = t / (Dp * Dp);
             const int row = 16 * mo + (lane & 15), col = 16 * mt + 4 * (lane >> 4) + i;
             G32R[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + row) * Dp + col];
             G32L[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + col) * Dp + row];

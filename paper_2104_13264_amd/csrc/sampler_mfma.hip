@@ -55,6 +55,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
 
+// The same pointer or offset as a wave-uniform (scalar) value: buffer
+// resources and scalar offsets must be uniform, and the compiler cannot
+// always prove it.
+__device__ __forceinline__ const char *uniform_ptr(const void *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const char *)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // A operands of one spin's product for one column: every 16-row output block
 // mo = 0..NT-1, each the 4 NT k-chunks of the fp32 16x16x4 product or the NT
 // chunks of the bf16 16x16x16 product.  The NT accumulation chains are
@@ -66,15 +77,21 @@ template <int NT>
 struct ATiles<NT, false> {
     static constexpr int NQ = 4 * NT;
     static constexpr size_t SITE_BYTES = (size_t)2 * NT * NQ * 64 * 4;
+    static constexpr uint32_t LANE_BYTES = 16;   // a lane's 4 consecutive k-chunks
     float a[NT][NQ];
-    // vbase: byte offset of (spin s_w, lane) within a site; soff: site offset
+    // vbase: byte offset of (spin s_w, lane) within a site; soff: site offset.
+    // Tile layout per spin: [mo][mt][64 lanes][4 chunks], one 16-byte load
+    // per lane for the chunks q = 4 mt .. 4 mt + 3.
     __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t vbase, uint32_t soff) {
 #pragma unroll
         for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                a[mo][q] = __builtin_bit_cast(
-                    float, __builtin_amdgcn_raw_buffer_load_b32(r, vbase + (mo * NQ + q) * 256, soff, 0));
+            for (int mt = 0; mt < NT; ++mt) {
+                const floatx4 v = __builtin_bit_cast(
+                    floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, vbase + (mo * NT + mt) * 1024, soff, 0));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[mo][4 * mt + i] = v[i];
+            }
     }
     __device__ __forceinline__ void mul(const floatx4 (&x)[NT], floatx4 (&acc)[NT]) const {
 #pragma unroll
@@ -90,6 +107,7 @@ struct ATiles<NT, false> {
 template <int NT>
 struct ATiles<NT, true> {
     static constexpr size_t SITE_BYTES = (size_t)2 * NT * NT * 64 * 8;
+    static constexpr uint32_t LANE_BYTES = 8;
     shortx4 a[NT][NT];
     __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t vbase, uint32_t soff) {
 #pragma unroll
@@ -302,7 +320,7 @@ __device__ __forceinline__ void sampler_body(const tn_samp_desc &A, const int bl
         // environment tiles of this phase's row; per-lane offset of spin s_w's tiles
         const __amdgpu_buffer_rsrc_t ars =
             make_rsrc((const char *)Gph + rbase * AT::SITE_BYTES, (uint32_t)(Lx * AT::SITE_BYTES));
-        const uint32_t avb = (uint32_t)(sw * (AT::SITE_BYTES / 2) + lane * (BF16 ? 8 : 4));
+        const uint32_t avb = (uint32_t)(sw * (AT::SITE_BYTES / 2) + lane * AT::LANE_BYTES);
         floatx4 vec[NT];   // r_{s_w} (environment sweep) or Lam (drawing)
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) vec[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -529,6 +547,438 @@ __device__ __forceinline__ void sampler_body(const tn_samp_desc &A, const int bl
     }
 }
 
+// ---------------------------------------------------------------------------
+// Used where both spins' operands and vectors fit one wave's registers without
+// spilling at two waves per SIMD (D <= 32).
+template <int NT, bool BF16>
+constexpr bool team_kernel_fits() { return NT <= 2; }
+
+// Products of both spins' tiles, the four (2 NT) accumulation chains
+// interleaved: acc[s] = A[s] x[s].
+template <int NT, bool BF16>
+__device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const floatx4 (&x0)[NT],
+                                         const floatx4 (&x1)[NT], floatx4 (&acc)[2][NT]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int mo = 0; mo < NT; ++mo) acc[sp][mo] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (BF16) {
+        shortx4 b0[NT], b1[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                b0[mt][i] = bf16_rne(x0[mt][i]);
+                b1[mt][i] = bf16_rne(x1[mt][i]);
+            }
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo) {
+                acc[0][mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0].a[mo][mt], b0[mt], acc[0][mo], 0, 0, 0);
+                acc[1][mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1].a[mo][mt], b1[mt], acc[1][mo], 0, 0, 0);
+            }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4 * NT; ++q)
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo) {
+                acc[0][mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0].a[mo][q], x0[q >> 2][q & 3], acc[0][mo], 0, 0, 0);
+                acc[1][mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1].a[mo][q], x1[q >> 2][q & 3], acc[1][mo], 0, 0, 0);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Teams of TW wavefronts, 16 proposals each, sharing the environment tiles.
+//
+// Each wave keeps both spins' operands and vectors in registers and runs the
+// environment sweep of a row and then its drawing, row after row, for its own
+// 16 proposals: per column the sweep chains 2 NT independent MFMA
+// accumulations (both spins), stores y_s and mixes r_s' = sum_s W(s', s)
+// v_c(s) y_s in place; the drawing multiplies Lam by both G_c(s)^T, forms
+// w(s) = v hf <Lam, y_s> from the stored tiles, draws, and keeps the drawn
+// spin's product lane by lane.  No tile crosses a wave.
+//
+// The team walks the rows and columns in lock step and fetches the tiles of a
+// column once, straight into a ring of LDS stages (global_load_lds, TL columns
+// ahead; each wave fetches an equal share), from which every wave reads its
+// operands one column ahead.  One barrier per column keeps the ring
+// consistent: at column t a wave reads stage t, refills the stage of column
+// t - 1 with column t + TL - 1, waits for its own fetch of column t + 1 and
+// meets the others at the barrier.  The per-row factor tables are built once
+// per team.  Sharing the fetch divides the operand traffic by TW and keeps the
+// waves of a team on the same tiles, so they stay in L2 even when other work
+// runs between launches.
+#ifndef TN_TEAM_STAGES
+#define TN_TEAM_STAGES 4
+#endif
+constexpr int TW = 4;                 // waves per team
+constexpr int TL = TN_TEAM_STAGES;    // LDS stages (columns in flight)
+
+template <int NT, bool BF16>
+struct TeamCfg {
+    static constexpr uint32_t STAGE = (uint32_t)ATiles<NT, BF16>::SITE_BYTES;   // both spins
+    static constexpr uint32_t LANE = STAGE / (TW * 64) >= 16 ? 16 : 4;   // dwordx4 or dword fetches
+    static constexpr int LOADS = (int)(STAGE / (TW * 64 * LANE));            // per wave per column
+    static_assert(LOADS * TW * 64 * LANE == STAGE, "stage must split evenly");
+};
+
+struct TeamSmem {
+    int ring, rows, uni, mixP, vS, epart, total;
+    __host__ __device__ TeamSmem(int Lx, uint32_t stage) {
+        ring = 0;                                        // [TL][stage bytes]
+        rows = ring + TL * (int)stage;                   // int8 [2 parity][Lx][TW*16]
+        uni = rows + ((2 * Lx * TW * 16 + 15) & ~15);    // uint32 [Lx][TW*16]
+        mixP = uni + Lx * TW * 16 * 4;                   // float [Lx][s_up][s'][s]
+        vS = mixP + Lx * 8 * 4;                          // double [Lx][s_up][s_prev][s]
+        epart = vS + Lx * 8 * 8;                         // double [TW][4][16]
+        total = epart + TW * 4 * 16 * 8;
+    }
+};
+
+template <uint32_t LANE>
+__device__ __forceinline__ void lds_fetch(const char *g, __attribute__((address_space(3))) void *l) {
+    static_assert(LANE == 16 || LANE == 4, "fetch width");
+    if constexpr (LANE == 16) __builtin_amdgcn_global_load_lds((const void *)g, l, 16, 0, 0);
+    else __builtin_amdgcn_global_load_lds((const void *)g, l, 4, 0, 0);
+}
+
+// wait until at most N vector-memory operations of this wave are in flight
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int NT, bool BF16>
+__device__ __forceinline__ void lds_tiles(ATiles<NT, BF16> &a, const unsigned char *st, int lane) {
+    if constexpr (BF16) {
+#pragma unroll
+        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt)
+                a.a[mo][mt] = *(const shortx4 *)(st + ((mo * NT + mt) * 64 + lane) * 8);
+    } else {
+#pragma unroll
+        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) {
+                const floatx4 v = *(const floatx4 *)(st + ((mo * NT + mt) * 64 + lane) * 16);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a.a[mo][4 * mt + i] = v[i];
+            }
+    }
+}
+
+template <int NT, bool BF16>
+__device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0, const int eval,
+                                          const uint32_t k0, const uint32_t k1, const uint64_t step0) {
+    using AT = ATiles<NT, BF16>;
+    using CF = TeamCfg<NT, BF16>;
+    const int B = A.B, Lx = A.Lx, Ly = A.Ly, per_step = A.per_step;
+    const double *__restrict__ Jh = A.Jh;
+    const double *__restrict__ Jv = A.Jv;
+    const double *__restrict__ h = A.h;
+    const double *__restrict__ fac = A.fac;
+    int8_t *__restrict__ S = A.S;
+    const uint32_t inst = A.inst;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n = lane & 15, grp = lane >> 4;
+    const int pn = w * 16 + n;                 // proposal slot in the team
+    const int blk = unit0 + w;                 // this wave's 16-proposal unit
+    const int b = blk * 16 + n;
+    const bool valid = b < B;
+    constexpr int PT = TW * 16;                // proposals per team
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TeamSmem L(Lx, CF::STAGE);
+    unsigned char *ring = smem + L.ring;
+    uint32_t(*uni)[PT] = (uint32_t(*)[PT])(smem + L.uni);
+    float(*mixP)[2][2][2] = (float(*)[2][2][2])(smem + L.mixP);
+    double(*vS)[2][2][2] = (double(*)[2][2][2])(smem + L.vS);
+    double(*epart)[4][16] = (double(*)[4][16])(smem + L.epart);
+    auto rowbuf = [&](int par) { return (int8_t(*)[PT])(smem + L.rows + par * Lx * PT); };
+
+    const uint32_t gstride = 2u * NT * 64 * 16;   // bytes of stored y tiles per column
+    const char *gwg = uniform_ptr(A.gscr + (size_t)blk * Lx * (gstride / 4));
+    const __amdgpu_buffer_rsrc_t grs = make_rsrc(gwg, uniform_u32((uint32_t)Lx * gstride));
+    // this wave's share of a stage: LOADS chunks of 64 lanes x LANE bytes
+    const uint32_t share = (uint32_t)w * CF::LOADS * 64 * CF::LANE;
+
+    double num = 1.0, den = 1.0, E = 0.0;   // ln q = ln(num / den) + nexp ln 2
+    int nexp = 0;
+    uint32_t n_clamp = 0, n_both = 0, n_near = 0;
+
+    for (int r = 0; r < Ly; ++r) {
+        const bool drawR = (r & 1) == 0;
+        __syncthreads();   // the previous row's readers are done with the tables
+        for (int t = threadIdx.x; t < Lx * 8; t += TW * 64) {
+            const int c = t >> 3, su = (t >> 2) & 1, x = (t >> 1) & 1, sg = t & 1;
+            const double *f = fac + ((size_t)r * Lx + c) * 6;
+            const double v = f[sg] * f[2 + (su ^ sg)];
+            const int cw = drawR ? c : c + 1;
+            double Wv = 1.0;
+            if (cw >= 1 && cw <= Lx - 1) Wv = fac[((size_t)r * Lx + cw) * 6 + ((x == sg) ? 4 : 5)];
+            mixP[c][su][x][sg] = (float)(Wv * v);
+            double hf = 1.0;
+            if (cw >= 1 && cw <= Lx - 1) hf = fac[((size_t)r * Lx + cw) * 6 + ((x == sg) ? 4 : 5)];
+            vS[c][su][x][sg] = v * hf;
+        }
+        int8_t(*crow)[PT] = rowbuf(r & 1);
+        const int8_t(*prow)[PT] = rowbuf((r + 1) & 1);
+        if (!eval) {
+            for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
+                const int c = t / PT, nn = t % PT;
+                const int i = r * Lx + c;
+                const uint32_t j = (uint32_t)unit0 * 16 + nn;
+                const uint64_t id = A.first_id + j % (uint32_t)per_step;
+                const uint32_t st = (uint32_t)(step0 + j / (uint32_t)per_step);
+                const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2), (uint32_t)id, st,
+                                                     (inst << 2) | 0u), k0, k1);
+                uni[c][nn] = tn_word(x, i & 3);
+            }
+        } else {
+            for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
+                const int nn = t / Lx, c = t % Lx;
+                const int bb = unit0 * 16 + nn;
+                crow[c][nn] = bb < B ? S[((size_t)bb * Ly + r) * Lx + c] : (int8_t)1;
+            }
+        }
+        const size_t rowb = (size_t)r * Lx;
+        for (int role = 0; role < 2; ++role) {
+            const bool sweep = role == 0;
+            const bool rightward = sweep ? !drawR : drawR;
+            const char *Gb = uniform_ptr((const char *)(rightward ? A.GL : A.GR) + rowb * AT::SITE_BYTES);
+            auto colof = [&](int t) { return rightward ? t : Lx - 1 - t; };
+            auto issue = [&](int t) {   // stage t % TL <- column colof(min(t, Lx - 1))
+                const char *src = Gb + (size_t)colof(min(t, Lx - 1)) * AT::SITE_BYTES + share + lane * CF::LANE;
+                unsigned char *dst = ring + (t % TL) * CF::STAGE + share;
+#pragma unroll
+                for (int j = 0; j < CF::LOADS; ++j)
+                    lds_fetch<CF::LANE>(src + j * 64 * CF::LANE,
+                                        (__attribute__((address_space(3))) void *)(dst + j * 64 * CF::LANE));
+            };
+            __syncthreads();   // tables and spins of the row; the ring is free
+#pragma unroll
+            for (int t = 0; t < TL - 1; ++t) issue(t);
+            wait_vm<(TL - 2) * CF::LOADS>();   // own share of column 0 has landed
+            __syncthreads();
+            AT a[2][2];   // [parity][spin]
+            lds_tiles<NT, BF16>(a[0][0], ring, lane);
+            lds_tiles<NT, BF16>(a[0][1], ring + CF::STAGE / 2, lane);
+            if (sweep) {
+                floatx4 v0[NT], v1[NT];
+#pragma unroll
+                for (int mt = 0; mt < NT; ++mt) v0[mt] = v1[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (grp == 0) v0[0][0] = v1[0][0] = 1.0f;
+                int e = 0;
+                auto stepP = [&](int k, int t) {
+                    const int c = colof(t);
+                    floatx4 acc[2][NT];
+                    mul_both<NT, BF16>(a[k], v0, v1, acc);
+                    issue(t + TL - 1);
+                    const bool up_minus = r > 0 && prow[c][pn] < 0;
+                    const floatx4 m = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
+                    if (t % RS == 0 && t > 0) {
+#pragma unroll
+                        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                            for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) acc[sp][mo][i] = ldexpf(acc[sp][mo][i], -e);
+                    }
+#pragma unroll
+                    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                        for (int mo = 0; mo < NT; ++mo)
+                            __builtin_amdgcn_raw_buffer_store_b128(
+                                __builtin_bit_cast(uintx4, acc[sp][mo]), grs,
+                                (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            v0[mo][i] = m[0] * acc[0][mo][i] + m[1] * acc[1][mo][i];
+                            v1[mo][i] = m[2] * acc[0][mo][i] + m[3] * acc[1][mo][i];
+                        }
+                    if (t % RS == RS - 1) {
+                        float mx = 0.0f;
+#pragma unroll
+                        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                            for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(acc[sp][mo][i]));
+                        e = pow2_exponent_f(rows4_max(mx));
+                    }
+#ifdef TN_TEAM_FENCE
+                    __builtin_amdgcn_sched_barrier(0);
+#endif
+                    // own fetch of column t + 1 has landed: at most the ops
+                    // issued after it are in flight (fewer in the first steps,
+                    // which follow the prologue's fetches)
+                    if (t >= TL - 2) wait_vm<2 * NT + (TL - 2) * (CF::LOADS + 2 * NT)>();
+                    else wait_vm<(TL - 2) * CF::LOADS + 2 * NT>();
+                    __syncthreads();
+                    const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
+                    lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
+                    lds_tiles<NT, BF16>(a[k ^ 1][1], st + CF::STAGE / 2, lane);
+                };
+                int t = 0;
+                for (; t + 2 <= Lx; t += 2) {
+                    stepP(0, t);
+                    stepP(1, t + 1);
+                }
+                if (t < Lx) stepP(0, t);
+            } else {
+                auto gload = [&](floatx4 (&gk)[2][NT], int c) {
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                        for (int mo = 0; mo < NT; ++mo)
+                            gk[s2][mo] = __builtin_bit_cast(
+                                floatx4, __builtin_amdgcn_raw_buffer_load_b128(
+                                             grs, (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
+                                             uniform_u32((uint32_t)c * gstride), 0));
+                };
+                floatx4 g[2][2][NT];
+                gload(g[0], colof(0));
+                gload(g[1], colof(min(1, Lx - 1)));
+                floatx4 lam[NT];
+#pragma unroll
+                for (int mt = 0; mt < NT; ++mt) lam[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (grp == 0) lam[0][0] = 1.0f;
+                int sprev = 0;
+                auto stepS = [&](int k, int t) {
+                    const int c = colof(t);
+                    const int8_t up = prow[c][pn];
+                    const uint32_t word = uni[c][pn];
+                    const int8_t given = crow[c][pn];
+                    const bool up_minus = r > 0 && up < 0;
+                    const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
+                    floatx4 acc[2][NT];
+                    mul_both<NT, BF16>(a[k], lam, lam, acc);
+                    float d0 = 0.0f, d1 = 0.0f;
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            d0 = fmaf(lam[mo][i], g[k][0][mo][i], d0);
+                            d1 = fmaf(lam[mo][i], g[k][1][mo][i], d1);
+                        }
+                    gload(g[k], colof(min(t + 2, Lx - 1)));
+                    issue(t + TL - 1);
+                    rows4_sum2(d0, d1);
+                    double w0 = vv.x * (double)d0;
+                    double w1 = vv.y * (double)d1;
+                    n_clamp += (w0 < 0.0) + (w1 < 0.0);
+                    w0 = fmax(w0, 0.0);
+                    w1 = fmax(w1, 0.0);
+                    const double tot = w0 + w1;
+                    const bool bad = !(tot > 0.0 && tot <= 1.79e308);
+                    n_both += bad;
+                    const double u = tn_u01(word);
+                    const double ut = bad ? u : u * tot, wt = bad ? 0.5 : w0, sc = bad ? 1.0 : tot;
+                    const int sd = eval ? (int)given : ((ut < wt) ? 1 : -1);
+                    n_near += !eval && fabs(ut - wt) < 1e-6 * sc;
+                    crow[c][pn] = (int8_t)sd;
+                    num *= bad ? 0.5 : (sd > 0 ? w0 : w1);
+                    den *= sc;
+                    sprev = sd > 0 ? 0 : 1;
+                    if (t % RS == RS - 1) {
+                        float mx = 0.0f;
+#pragma unroll
+                        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(lam[mo][i]));
+                        const int ee = pow2_exponent_f(rows4_max(mx));
+#pragma unroll
+                        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                            for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) acc[sp][mo][i] = ldexpf(acc[sp][mo][i], -ee);
+                        int e1, e2;
+                        num = frexp(num, &e1);
+                        den = frexp(den, &e2);
+                        nexp += e1 - e2;
+                    }
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo) lam[mo] = sd > 0 ? acc[0][mo] : acc[1][mo];
+#ifdef TN_TEAM_FENCE
+                    __builtin_amdgcn_sched_barrier(0);
+#endif
+                    // own fetch of column t + 1 has landed (ops issued after it:
+                    // TL - 2 steps of y loads and fetches; more in the first steps)
+                    wait_vm<(TL - 2) * (CF::LOADS + 2 * NT)>();
+                    __syncthreads();
+                    const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
+                    lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
+                    lds_tiles<NT, BF16>(a[k ^ 1][1], st + CF::STAGE / 2, lane);
+                };
+                int t = 0;
+                for (; t + 2 <= Lx; t += 2) {
+                    stepS(0, t);
+                    stepS(1, t + 1);
+                }
+                if (t < Lx) stepS(0, t);
+            }
+        }
+        __syncthreads();   // the drawn row is complete in LDS
+        {
+            double eg = 0.0;
+            for (int c = grp; c < Lx; c += 4) {
+                const double sc = crow[c][pn];
+                const double hv = h ? h[rowb + c] : 0.0;
+                const double jl = c > 0 ? Jh[(size_t)r * (Lx - 1) + c - 1] * (double)crow[c - 1][pn] : 0.0;
+                const double ja = r > 0 ? Jv[(size_t)(r - 1) * Lx + c] * (double)prow[c][pn] : 0.0;
+                eg -= sc * (hv + jl + ja);
+            }
+            epart[w][grp][n] = eg;
+        }
+        if (!eval) {
+            for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
+                const int nn = t / Lx, c = t % Lx;
+                const int bb = unit0 * 16 + nn;
+                if (bb < B) S[((size_t)bb * Ly + r) * Lx + c] = crow[c][nn];
+            }
+        }
+        __syncthreads();
+        if (grp == 0) E += ((epart[w][0][n] + epart[w][1][n]) + epart[w][2][n]) + epart[w][3][n];
+    }
+    if (grp == 0 && valid) {
+        A.logq[b] = (log(num) - log(den)) + (double)nexp * 0.69314718055994530942;
+        A.energy[b] = E;
+        if (n_clamp) atomicAdd(&A.counters[CNT_CLAMPS], (unsigned long long)n_clamp);
+        if (n_both) atomicAdd(&A.counters[CNT_BOTH], (unsigned long long)n_both);
+        if (n_near && !eval) atomicAdd(&A.counters[CNT_NEAR], (unsigned long long)n_near);
+    }
+}
+
+template <int NT, bool BF16>
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_sampler_team(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step0,
+               const uint64_t *__restrict__ step_base) {
+    team_body<NT, BF16>(A, blockIdx.x * TW, eval, k0, k1, step0 + *step_base);
+}
+
+template <int NT, bool BF16>
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0, uint32_t k1,
+                     uint64_t step0, const uint64_t *__restrict__ step_base) {
+    const int u0 = (int)blockIdx.x * TW;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {   // last instance whose first unit is <= u0
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].blk0 <= u0) lo = mid;
+        else hi = mid - 1;
+    }
+    const tn_samp_desc A = descs[lo];
+    team_body<NT, BF16>(A, u0 - A.blk0, 0, k0, k1, step0 + *step_base);
+}
+
 // One instance: the arguments by value; the MH step is step0 + *step_base.
 template <int NT, bool BF16>
 __global__ void __launch_bounds__(256)
@@ -557,6 +1007,18 @@ template <int NT, bool BF16>
 int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     const int blocks = (B + 15) / 16;
+    if constexpr (team_kernel_fits<NT, BF16>()) {
+        const TeamSmem T(ctx->Lx, TeamCfg<NT, BF16>::STAGE);
+        auto kern = k_sampler_team<NT, BF16>;
+        if (T.total > 65536)
+            TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, T.total));
+        const tn_samp_desc A = tn_samp_desc_of(ctx, B, S, logq, energy, g, per_step, first_id);
+        hipLaunchKernelGGL(kern, dim3((B + TW * 16 - 1) / (TW * 16)), dim3(TW * 64), T.total, ctx->stream,
+                           A, eval ? 1 : 0, (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
+        TN_HIP(ctx, hipGetLastError());
+        return TN_OK;
+    }
     const SmemLayout<NT> L(ctx->Lx);
     auto kern = k_sampler_mfma<NT, BF16>;
     if (L.total > 65536)
@@ -572,6 +1034,18 @@ int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 template <int NT, bool BF16>
 int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks, int maxLx,
                       uint64_t seed, uint64_t step0) {
+    if constexpr (team_kernel_fits<NT, BF16>()) {
+        // blocks counts 16-proposal units, TW-aligned per instance
+        const TeamSmem T(maxLx, TeamCfg<NT, BF16>::STAGE);
+        auto kern = k_sampler_team_multi<NT, BF16>;
+        if (T.total > 65536)
+            TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, T.total));
+        hipLaunchKernelGGL(kern, dim3((blocks + TW - 1) / TW), dim3(TW * 64), T.total, ctx->stream, descs, n,
+                           (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
+        TN_HIP(ctx, hipGetLastError());
+        return TN_OK;
+    }
     const SmemLayout<NT> L(maxLx);
     auto kern = k_sampler_mfma_multi<NT, BF16>;
     if (L.total > 65536)
@@ -602,10 +1076,8 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
     if (batch == 0) return TN_OK;
     if (ctx->Lx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
-    const int blocks = (batch + 15) / 16;
-    const size_t need = (size_t)blocks * 2 * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
     int rc;
-    if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, need))) return rc;
+    if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, tn_mfma_scratch_bytes(ctx, batch)))) return rc;
     float *g = (float *)ctx->gscr;
     if (ctx->prec == TN_BF16)
         return dispatch_nt<true>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
