@@ -651,6 +651,17 @@ __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
+// Barrier of the team's column steps.  __syncthreads() would also wait for
+// every memory operation in flight (the LDS fetches count as such), which
+// would drain the ring at every column; here each wave has already waited for
+// its own fetch of the stage read next, so a bare s_barrier suffices.  The
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void team_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <int NT, bool BF16>
 __device__ __forceinline__ void lds_tiles(ATiles<NT, BF16> &a, const unsigned char *st, int lane) {
     if constexpr (BF16) {
@@ -821,7 +832,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     // which follow the prologue's fetches)
                     if (t >= TL - 2) wait_vm<2 * NT + (TL - 2) * (CF::LOADS + 2 * NT)>();
                     else wait_vm<(TL - 2) * CF::LOADS + 2 * NT>();
-                    __syncthreads();
+                    team_barrier();
                     const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
                     lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
                     lds_tiles<NT, BF16>(a[k ^ 1][1], st + CF::STAGE / 2, lane);
@@ -913,7 +924,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     // own fetch of column t + 1 has landed (ops issued after it:
                     // TL - 2 steps of y loads and fetches; more in the first steps)
                     wait_vm<(TL - 2) * (CF::LOADS + 2 * NT)>();
-                    __syncthreads();
+                    team_barrier();
                     const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
                     lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
                     lds_tiles<NT, BF16>(a[k ^ 1][1], st + CF::STAGE / 2, lane);
