@@ -42,10 +42,15 @@ __device__ __forceinline__ int pow2_exponent_f(float m) {
     return e;
 }
 
-__device__ __forceinline__ short bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int uintx2 __attribute__((ext_vector_type(2)));
+
+// Four floats to bf16 with round-to-nearest-even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ shortx4 bf16x4_rne(const floatx4 v) {
+    const floatx2 lo = {v[0], v[1]}, hi = {v[2], v[3]};
+    const bf16x2 a = __builtin_convertvector(lo, bf16x2), b = __builtin_convertvector(hi, bf16x2);
+    return __builtin_bit_cast(shortx4, uintx2{__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)});
 }
 
 // Buffer resource over [base, base + bytes): loads and stores take a 32-bit
@@ -122,9 +127,7 @@ struct ATiles<NT, true> {
         for (int mo = 0; mo < NT; ++mo) acc[mo] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) {
-            shortx4 bv;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) bv[i] = bf16_rne(x[mt][i]);
+            const shortx4 bv = bf16x4_rne(x[mt]);
 #pragma unroll
             for (int mo = 0; mo < NT; ++mo)
                 acc[mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mo][mt], bv, acc[mo], 0, 0, 0);
@@ -548,10 +551,11 @@ __device__ __forceinline__ void sampler_body(const tn_samp_desc &A, const int bl
 }
 
 // ---------------------------------------------------------------------------
-// Used where both spins' operands and vectors fit one wave's registers without
-// spilling at two waves per SIMD (D <= 32).
+// Used where both spins' operands and vectors fit one wave's registers: FP32
+// with D <= 32 (two waves per SIMD) and BF16 with D <= 64 (one wave per SIMD
+// from D = 33).
 template <int NT, bool BF16>
-constexpr bool team_kernel_fits() { return NT <= 2; }
+constexpr bool team_kernel_fits() { return BF16 ? NT <= 4 : NT <= 2; }
 
 // Products of both spins' tiles, the four (2 NT) accumulation chains
 // interleaved: acc[s] = A[s] x[s].
@@ -565,12 +569,10 @@ __device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const f
     if constexpr (BF16) {
         shortx4 b0[NT], b1[NT];
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                b0[mt][i] = bf16_rne(x0[mt][i]);
-                b1[mt][i] = bf16_rne(x1[mt][i]);
-            }
+        for (int mt = 0; mt < NT; ++mt) {
+            b0[mt] = bf16x4_rne(x0[mt]);
+            b1[mt] = bf16x4_rne(x1[mt]);
+        }
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
@@ -610,27 +612,29 @@ __device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const f
 // per team.  Sharing the fetch divides the operand traffic by TW and keeps the
 // waves of a team on the same tiles, so they stay in L2 even when other work
 // runs between launches.
-#ifndef TN_TEAM_STAGES
-#define TN_TEAM_STAGES 4
-#endif
-constexpr int TW = 4;                 // waves per team
-constexpr int TL = TN_TEAM_STAGES;    // LDS stages (columns in flight)
+constexpr int TW = 4;   // waves per team
 
+// Per bond class: TL LDS stages (columns in flight); UNI: the row's random
+// words precomputed in LDS (else drawn by each wave as it goes); WPE: waves per
+// SIMD the registers allow.
 template <int NT, bool BF16>
 struct TeamCfg {
     static constexpr uint32_t STAGE = (uint32_t)ATiles<NT, BF16>::SITE_BYTES;   // both spins
-    static constexpr uint32_t LANE = STAGE / (TW * 64) >= 16 ? 16 : 4;   // dwordx4 or dword fetches
+    static constexpr uint32_t LANE = STAGE % (TW * 64 * 16) == 0 ? 16 : 4;     // dwordx4 or dword fetches
     static constexpr int LOADS = (int)(STAGE / (TW * 64 * LANE));            // per wave per column
     static_assert(LOADS * TW * 64 * LANE == STAGE, "stage must split evenly");
+    static constexpr int TL = NT <= 2 ? 4 : 2;
+    static constexpr bool UNI = NT <= 2;
+    static constexpr int WPE = NT <= 2 ? 2 : 1;
 };
 
 struct TeamSmem {
     int ring, rows, uni, mixP, vS, epart, total;
-    __host__ __device__ TeamSmem(int Lx, uint32_t stage) {
+    __host__ __device__ TeamSmem(int Lx, uint32_t stage, int tl, bool with_uni) {
         ring = 0;                                        // [TL][stage bytes]
-        rows = ring + TL * (int)stage;                   // int8 [2 parity][Lx][TW*16]
-        uni = rows + ((2 * Lx * TW * 16 + 15) & ~15);    // uint32 [Lx][TW*16]
-        mixP = uni + Lx * TW * 16 * 4;                   // float [Lx][s_up][s'][s]
+        rows = ring + tl * (int)stage;                   // int8 [2 parity][Lx][TW*16]
+        uni = rows + ((2 * Lx * TW * 16 + 15) & ~15);    // uint32 [Lx][TW*16] (if with_uni)
+        mixP = uni + (with_uni ? Lx * TW * 16 * 4 : 0);  // float [Lx][s_up][s'][s]
         vS = mixP + Lx * 8 * 4;                          // double [Lx][s_up][s_prev][s]
         epart = vS + Lx * 8 * 8;                         // double [TW][4][16]
         total = epart + TW * 4 * 16 * 8;
@@ -687,6 +691,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                                           const uint32_t k0, const uint32_t k1, const uint64_t step0) {
     using AT = ATiles<NT, BF16>;
     using CF = TeamCfg<NT, BF16>;
+    constexpr int TL = CF::TL;
     const int B = A.B, Lx = A.Lx, Ly = A.Ly, per_step = A.per_step;
     const double *__restrict__ Jh = A.Jh;
     const double *__restrict__ Jv = A.Jv;
@@ -704,7 +709,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
     constexpr int PT = TW * 16;                // proposals per team
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const TeamSmem L(Lx, CF::STAGE);
+    const TeamSmem L(Lx, CF::STAGE, TL, CF::UNI);
     unsigned char *ring = smem + L.ring;
     uint32_t(*uni)[PT] = (uint32_t(*)[PT])(smem + L.uni);
     float(*mixP)[2][2][2] = (float(*)[2][2][2])(smem + L.mixP);
@@ -739,7 +744,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
         }
         int8_t(*crow)[PT] = rowbuf(r & 1);
         const int8_t(*prow)[PT] = rowbuf((r + 1) & 1);
-        if (!eval) {
+        if (!eval && CF::UNI) {
             for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
                 const int c = t / PT, nn = t % PT;
                 const int i = r * Lx + c;
@@ -750,7 +755,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                                                      (inst << 2) | 0u), k0, k1);
                 uni[c][nn] = tn_word(x, i & 3);
             }
-        } else {
+        } else if (eval) {
             for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
                 const int nn = t / Lx, c = t % Lx;
                 const int bb = unit0 * 16 + nn;
@@ -862,10 +867,27 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                 for (int mt = 0; mt < NT; ++mt) lam[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
                 if (grp == 0) lam[0][0] = 1.0f;
                 int sprev = 0;
+                // random words drawn as the row goes (when not in LDS): one
+                // Philox block per four sites, kept for the next sites
+                uint4 words = make_uint4(0u, 0u, 0u, 0u);
+                int wblk = -1;
+                const uint32_t jj = (uint32_t)unit0 * 16 + pn;
+                const uint64_t wid = A.first_id + jj % (uint32_t)per_step;
+                const uint32_t wst = (uint32_t)(step0 + jj / (uint32_t)per_step);
                 auto stepS = [&](int k, int t) {
                     const int c = colof(t);
                     const int8_t up = prow[c][pn];
-                    const uint32_t word = uni[c][pn];
+                    uint32_t word;
+                    if constexpr (CF::UNI) {
+                        word = uni[c][pn];
+                    } else {
+                        const int i = r * Lx + c;
+                        if (!eval && (i >> 2) != wblk) {
+                            wblk = i >> 2;
+                            words = tn_philox(make_uint4((uint32_t)wblk, (uint32_t)wid, wst, (inst << 2) | 0u), k0, k1);
+                        }
+                        word = tn_word(words, i & 3);
+                    }
                     const int8_t given = crow[c][pn];
                     const bool up_minus = r > 0 && up < 0;
                     const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
@@ -879,8 +901,8 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                             d0 = fmaf(lam[mo][i], g[k][0][mo][i], d0);
                             d1 = fmaf(lam[mo][i], g[k][1][mo][i], d1);
                         }
-                    gload(g[k], colof(min(t + 2, Lx - 1)));
                     issue(t + TL - 1);
+                    gload(g[k], colof(min(t + 2, Lx - 1)));
                     rows4_sum2(d0, d1);
                     double w0 = vv.x * (double)d0;
                     double w1 = vv.y * (double)d1;
@@ -922,8 +944,9 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     __builtin_amdgcn_sched_barrier(0);
 #endif
                     // own fetch of column t + 1 has landed (ops issued after it:
-                    // TL - 2 steps of y loads and fetches; more in the first steps)
-                    wait_vm<(TL - 2) * (CF::LOADS + 2 * NT)>();
+                    // the y loads of its step and TL - 2 steps of fetches and y
+                    // loads; more in the first steps)
+                    wait_vm<2 * NT + (TL - 2) * (CF::LOADS + 2 * NT)>();
                     team_barrier();
                     const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
                     lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
@@ -969,14 +992,14 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
 }
 
 template <int NT, bool BF16>
-__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16>::WPE, 8)))
 k_sampler_team(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step0,
                const uint64_t *__restrict__ step_base) {
     team_body<NT, BF16>(A, blockIdx.x * TW, eval, k0, k1, step0 + *step_base);
 }
 
 template <int NT, bool BF16>
-__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16>::WPE, 8)))
 k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0, uint32_t k1,
                      uint64_t step0, const uint64_t *__restrict__ step_base) {
     const int u0 = (int)blockIdx.x * TW;
@@ -1019,7 +1042,7 @@ int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     const int blocks = (B + 15) / 16;
     if constexpr (team_kernel_fits<NT, BF16>()) {
-        const TeamSmem T(ctx->Lx, TeamCfg<NT, BF16>::STAGE);
+        const TeamSmem T(ctx->Lx, TeamCfg<NT, BF16>::STAGE, TeamCfg<NT, BF16>::TL, TeamCfg<NT, BF16>::UNI);
         auto kern = k_sampler_team<NT, BF16>;
         if (T.total > 65536)
             TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,
@@ -1047,7 +1070,7 @@ int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks,
                       uint64_t seed, uint64_t step0) {
     if constexpr (team_kernel_fits<NT, BF16>()) {
         // blocks counts 16-proposal units, TW-aligned per instance
-        const TeamSmem T(maxLx, TeamCfg<NT, BF16>::STAGE);
+        const TeamSmem T(maxLx, TeamCfg<NT, BF16>::STAGE, TeamCfg<NT, BF16>::TL, TeamCfg<NT, BF16>::UNI);
         auto kern = k_sampler_team_multi<NT, BF16>;
         if (T.total > 65536)
             TN_HIP(ctx, hipFuncSetAttribute((const void *)kern,

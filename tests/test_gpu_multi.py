@@ -42,7 +42,7 @@ def clone(st):
     return {k: v.clone() for k, v in st.items()}
 
 
-@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("prec", [FP32, FP64, BF16], ids=["fp32", "fp64", "bf16"])
 def test_multi_env_matches_oracle_and_steps_match_single(prec):
     from paper_2104_13264_amd import Sampler
     items = mixed_instances()
