@@ -626,6 +626,7 @@ struct TeamCfg {
     static constexpr int TL = NT <= 2 ? 4 : 2;
     static constexpr bool UNI = NT <= 2;
     static constexpr int WPE = NT <= 2 ? 2 : 1;
+    static constexpr int ABUF = 2;   // operand register sets (read one column ahead)
 };
 
 struct TeamSmem {
@@ -781,7 +782,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             for (int t = 0; t < TL - 1; ++t) issue(t);
             wait_vm<(TL - 2) * CF::LOADS>();   // own share of column 0 has landed
             __syncthreads();
-            AT a[2][2];   // [parity][spin]
+            AT a[CF::ABUF][2];   // [set][spin]
             lds_tiles<NT, BF16>(a[0][0], ring, lane);
             lds_tiles<NT, BF16>(a[0][1], ring + CF::STAGE / 2, lane);
             if (sweep) {
@@ -793,7 +794,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                 auto stepP = [&](int k, int t) {
                     const int c = colof(t);
                     floatx4 acc[2][NT];
-                    mul_both<NT, BF16>(a[k], v0, v1, acc);
+                    mul_both<NT, BF16>(a[k % CF::ABUF], v0, v1, acc);
                     issue(t + TL - 1);
                     const bool up_minus = r > 0 && prow[c][pn] < 0;
                     const floatx4 m = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
@@ -839,8 +840,8 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     else wait_vm<(TL - 2) * CF::LOADS + 2 * NT>();
                     team_barrier();
                     const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
-                    lds_tiles<NT, BF16>(a[k ^ 1][1], st + CF::STAGE / 2, lane);
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], st, lane);
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], st + CF::STAGE / 2, lane);
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
@@ -892,7 +893,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     const bool up_minus = r > 0 && up < 0;
                     const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
                     floatx4 acc[2][NT];
-                    mul_both<NT, BF16>(a[k], lam, lam, acc);
+                    mul_both<NT, BF16>(a[k % CF::ABUF], lam, lam, acc);
                     float d0 = 0.0f, d1 = 0.0f;
 #pragma unroll
                     for (int mo = 0; mo < NT; ++mo)
@@ -949,8 +950,8 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     wait_vm<2 * NT + (TL - 2) * (CF::LOADS + 2 * NT)>();
                     team_barrier();
                     const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, BF16>(a[k ^ 1][0], st, lane);
-                    lds_tiles<NT, BF16>(a[k ^ 1][1], st + CF::STAGE / 2, lane);
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], st, lane);
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], st + CF::STAGE / 2, lane);
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {

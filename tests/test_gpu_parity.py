@@ -366,3 +366,26 @@ def test_bf16_sampler_against_oracle(name, mk, D, B):
     log(f"  max |ln q_bf16 - ln q_fp64| {dev.max():.3e} (mean {dev.mean():.3e}, bound {bound:.3e})")
     assert np.all(np.isfinite(lq)) and dev.max() <= bound
     s.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, BF16], ids=["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("D", [8, 24, 40, 64])
+def test_beta0_spins_follow_the_philox_stream(prec, D):
+    # at beta = 0 both spins of every site weigh exactly the same in any
+    # precision, so p+ = 1/2 exactly and every spin is fixed by its random word
+    # alone: the batched kernels of every bond class (the row's words drawn in
+    # LDS or as the row goes) must reproduce the oracle's spins bit for bit,
+    # with ln q = N ln(1/2)
+    inst = random_instance(9, 11, 0.0, D, seed=61)
+    log(f"[beta0] 9x11 D={D} prec {prec}")
+    s, envs = gpu_sampler_with_oracle_env(inst, D, prec)
+    B, seed, step, first = 70, 31, 5, 3
+    sp, lq, _ = s.sample(B, seed, step=step, first_id=first)
+    ref = sampler.sample(model_of(inst), envs, B, seed, step=step, first_id=first)
+    assert np.array_equal(sp.cpu().numpy(), ref['spins'])
+    np.testing.assert_allclose(lq.cpu().numpy(), 99 * np.log(0.5), rtol=1e-12)
+    steps = s.sample_steps(B, 3, seed, step0=step, first_id=first)
+    for t in range(3):
+        r = sampler.sample(model_of(inst), envs, B, seed, step=step + t, first_id=first)
+        assert np.array_equal(steps[0][t].cpu().numpy(), r['spins'])
+    s.close()
