@@ -69,6 +69,9 @@ SAMPLER_CASES = [
     ("column 7x1", lambda: random_instance(7, 1, 0.8, 4, seed=15), 4, 17),
     ("ea 12 D64", lambda: ea_pm(12, 1.0, 64, seed=16), 64, 19),
     ("frustrated 6x128 beta3 D4", lambda: fully_frustrated(6, 3.0, 4, Lx=128), 4, 9),
+    # the widest lattice (largest LDS tables of the batched kernels)
+    ("wide 3x256 D32", lambda: random_instance(3, 256, 0.6, 32, seed=17, field_scale=0.1), 32, 40),
+    ("wide 2x256 D64", lambda: random_instance(2, 256, 0.6, 64, seed=18), 64, 20),
 ]
 
 
@@ -339,6 +342,8 @@ BF16_CASES = [
     ("ea 12 D20", lambda: ea_pm(12, 1.0, 20, seed=13), 20, 33),
     ("frustrated 10 D33", lambda: fully_frustrated(10, 1.0, 33), 33, 21),
     ("ea 12 D64", lambda: ea_pm(12, 1.0, 64, seed=16), 64, 19),
+    ("wide 3x256 D32", lambda: random_instance(3, 256, 0.6, 32, seed=17, field_scale=0.1), 32, 40),
+    ("wide 2x256 D64", lambda: random_instance(2, 256, 0.6, 64, seed=18), 64, 20),
 ]
 
 
