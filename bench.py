@@ -58,13 +58,13 @@ def tau_int(E, burn=0.1, c=6.0):
 
 
 def ahead_steps(chains):
-    """MH steps whose proposals share one sampler launch: enough 16-proposal
-    wavefronts for two per SIMD (two four-wave teams per compute unit;
-    proposals do not depend on the chains' state, Sec. 2, so drawing them
-    ahead leaves the chains unchanged)."""
+    """MH steps whose proposals share one sampler launch: enough for two
+    four-wave teams of 128 proposals per compute unit (proposals do not depend
+    on the chains' state, Sec. 2, so drawing them ahead leaves the chains
+    unchanged)."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    return max(1, -(-8 * 16 * cus // chains))
+    return max(1, -(-16 * 16 * cus // chains))
 
 
 def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):

@@ -400,11 +400,11 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
     if (chains == 0 || nsteps == 0) return TN_OK;
     if (!state_spins || !state_logq || !state_energy || !accepted)
         return tn_fail(ctx, TN_EINVAL, "NULL state buffer");
-    // steps per sampler launch: two 16-proposal wavefronts for every SIMD
+    // steps per sampler launch: two teams of 128 proposals for every compute unit
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
         cus = 256;
-    const long target = 8L * 16 * cus;
+    const long target = 16L * 16 * cus;
     int m = (int)((target + chains - 1) / chains);
     m = m < 1 ? 1 : (m > nsteps ? nsteps : m);
     if ((size_t)chains * m > (size_t)INT32_MAX / 2) m = 1;
@@ -572,8 +572,8 @@ int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *s
                     continue;
                 tn_samp_desc A = tn_samp_desc_of(k, C, k->pspins, k->plogq, k->pE,
                                                  (float *)k->gscr, C, 0);
-                A.blk0 = g.blocks;   // in 16-proposal units, whole teams of four per instance
-                g.blocks += ((C + 63) / 64) * 4;
+                A.blk0 = g.blocks;   // in 16-proposal units, whole teams (up to eight units) per instance
+                g.blocks += ((C + 127) / 128) * 8;
                 g.maxLx = k->Lx > g.maxLx ? k->Lx : g.maxLx;
                 sd.push_back(A);
                 ++g.count;

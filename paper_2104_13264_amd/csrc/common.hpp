@@ -202,7 +202,7 @@ inline tn_samp_desc tn_samp_desc_of(tn_ctx *ctx, int B, int8_t *S, double *logq,
 }
 // Scratch bytes of the batched sampler for `batch` proposals.
 inline size_t tn_mfma_scratch_bytes(const tn_ctx *ctx, int batch) {
-    const int units = ((batch + 63) / 64) * 4;   // 16-proposal units, whole teams of four
+    const int units = ((batch + 127) / 128) * 8;   // 16-proposal units, whole teams (up to eight)
     return (size_t)units * 2 * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
 }
 int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, const tn_samp_desc *descs, int n, int blocks,

@@ -152,15 +152,18 @@ __device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const f
 }
 
 // ---------------------------------------------------------------------------
-// Teams of TW wavefronts, 16 proposals each, sharing the environment tiles.
+// Teams of TW wavefronts sharing the environment tiles.
 //
-// Each wave keeps both spins' operands and vectors in registers and runs the
-// environment sweep of a row and then its drawing, row after row, for its own
-// 16 proposals: per column the sweep chains 2 NT independent MFMA
-// accumulations (both spins), stores y_s and mixes r_s' = sum_s W(s', s)
-// v_c(s) y_s in place; the drawing multiplies Lam by both G_c(s)^T, forms
-// w(s) = v hf <Lam, y_s> from the stored tiles, draws, and keeps the drawn
-// spin's product lane by lane.  No tile crosses a wave.
+// Each wave owns SETS sets of 16 proposals (two for D <= 32, one above).  It
+// keeps both spins' operands and all its sets' vectors in registers and runs
+// the environment sweep of a row and then its drawing, row after row: per
+// column the sweep chains 2 NT independent MFMA accumulations per set (both
+// spins), stores y_s and mixes r_s' = sum_s W(s', s) v_c(s) y_s in place; the
+// drawing multiplies Lam by both G_c(s)^T, forms w(s) = v hf <Lam, y_s> from
+// the stored tiles, draws, and keeps the drawn spin's product lane by lane.
+// No tile crosses a wave.  With two sets the fp64 draw serves both at once:
+// lanes 0-31 decide set 0, lanes 32-63 set 1, and a permlane32 swap hands
+// every lane both sets' spins.
 //
 // The team walks the rows and columns in lock step and fetches the tiles of a
 // column once, straight into a ring of LDS stages (global_load_lds, TL columns
@@ -174,9 +177,9 @@ __device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const f
 // runs between launches.
 constexpr int TW = 4;   // waves per team
 
-// Per bond class: TL LDS stages (columns in flight); UNI: the row's random
-// words precomputed in LDS (else drawn by each wave as it goes); WPE: waves per
-// SIMD the registers allow.
+// Per bond class: TL LDS stages (columns in flight); SETS: 16-proposal sets
+// per wave; WPE: waves per SIMD the registers allow; ABUF: operand register
+// sets (two: read one column ahead; one: read just in time).
 template <int NT, bool BF16>
 struct TeamCfg {
     static constexpr uint32_t STAGE = (uint32_t)ATiles<NT, BF16>::SITE_BYTES;   // both spins
@@ -184,18 +187,18 @@ struct TeamCfg {
     static constexpr int LOADS = (int)(STAGE / (TW * 64 * LANE));            // per wave per column
     static_assert(LOADS * TW * 64 * LANE == STAGE, "stage must split evenly");
     static constexpr int TL = NT <= 2 ? 4 : 2;
-    static constexpr bool UNI = NT <= 2;
+    static constexpr int SETS = NT <= 2 ? 2 : 1;
     static constexpr int WPE = NT <= 2 ? 2 : 1;
-    static constexpr int ABUF = (BF16 || NT <= 2) ? 2 : 1;   // operand register sets
+    static constexpr int ABUF = (BF16 || NT <= 2) ? 2 : 1;
+    static constexpr int PT = TW * 16 * SETS;   // proposals per team
 };
 
 struct TeamSmem {
-    int ring, rows, uni, mixP, vS, epart, total;
-    __host__ __device__ TeamSmem(int Lx, uint32_t stage, int tl, bool with_uni) {
+    int ring, rows, mixP, vS, epart, total;
+    __host__ __device__ TeamSmem(int Lx, uint32_t stage, int tl, int pt) {
         ring = 0;                                        // [TL][stage bytes]
-        rows = ring + tl * (int)stage;                   // int8 [2 parity][Lx][TW*16]
-        uni = rows + ((2 * Lx * TW * 16 + 15) & ~15);    // uint32 [Lx][TW*16] (if with_uni)
-        mixP = uni + (with_uni ? Lx * TW * 16 * 4 : 0);  // float [Lx][s_up][s'][s]
+        rows = ring + tl * (int)stage;                   // int8 [2 parity][Lx][pt]
+        mixP = rows + ((2 * Lx * pt + 15) & ~15);        // float [Lx][s_up][s'][s]
         vS = mixP + Lx * 8 * 4;                          // double [Lx][s_up][s_prev][s]
         epart = vS + Lx * 8 * 8;                         // double [TW][4][16]
         total = epart + TW * 4 * 16 * 8;
@@ -252,7 +255,8 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                                           const uint32_t k0, const uint32_t k1, const uint64_t step0) {
     using AT = ATiles<NT, BF16>;
     using CF = TeamCfg<NT, BF16>;
-    constexpr int TL = CF::TL;
+    constexpr int TL = CF::TL, SE = CF::SETS, PT = CF::PT;
+    constexpr int CG = 4 / SE;                 // column groups of a set's energy
     const int B = A.B, Lx = A.Lx, Ly = A.Ly, per_step = A.per_step;
     const double *__restrict__ Jh = A.Jh;
     const double *__restrict__ Jv = A.Jv;
@@ -263,26 +267,37 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = lane & 15, grp = lane >> 4;
-    const int pn = w * 16 + n;                 // proposal slot in the team
-    const int blk = unit0 + w;                 // this wave's 16-proposal unit
-    const int b = blk * 16 + n;
-    const bool valid = b < B;
-    constexpr int PT = TW * 16;                // proposals per team
+    // Every lane holds tiles of all SE sets (proposal n of each); the scalar
+    // work of the draw is split: with two sets, lanes 0-31 take set 0 and
+    // lanes 32-63 set 1 (the lane's draw set ds).
+    const int ds = SE == 2 ? (lane >> 5) : 0;
+    const int cg = grp % CG;
+    auto slot = [&](int st) { return (w * SE + st) * 16 + n; };   // slot in the team
+    const int pd = slot(ds);
+    const int bd = (unit0 + w * SE + ds) * 16 + n;   // the draw set's proposal
+    const bool valid = bd < B;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const TeamSmem L(Lx, CF::STAGE, TL, CF::UNI);
+    const TeamSmem L(Lx, CF::STAGE, TL, PT);
     unsigned char *ring = smem + L.ring;
-    uint32_t(*uni)[PT] = (uint32_t(*)[PT])(smem + L.uni);
     float(*mixP)[2][2][2] = (float(*)[2][2][2])(smem + L.mixP);
     double(*vS)[2][2][2] = (double(*)[2][2][2])(smem + L.vS);
-    double(*epart)[4][16] = (double(*)[4][16])(smem + L.epart);
+    double(*epart)[SE][CG][16] = (double(*)[SE][CG][16])(smem + L.epart);
     auto rowbuf = [&](int par) { return (int8_t(*)[PT])(smem + L.rows + par * Lx * PT); };
 
     const uint32_t gstride = 2u * NT * 64 * 16;   // bytes of stored y tiles per column
-    const char *gwg = uniform_ptr(A.gscr + (size_t)blk * Lx * (gstride / 4));
-    const __amdgpu_buffer_rsrc_t grs = make_rsrc(gwg, uniform_u32((uint32_t)Lx * gstride));
+    __amdgpu_buffer_rsrc_t grs[SE];
+#pragma unroll
+    for (int st = 0; st < SE; ++st)
+        grs[st] = make_rsrc(uniform_ptr(A.gscr + (size_t)(unit0 + w * SE + st) * Lx * (gstride / 4)),
+                            uniform_u32((uint32_t)Lx * gstride));
     // this wave's share of a stage: LOADS chunks of 64 lanes x LANE bytes
     const uint32_t share = (uint32_t)w * CF::LOADS * 64 * CF::LANE;
+    // random words of the draw set's proposal, drawn as the row goes: one
+    // Philox block per four sites, kept for the next sites
+    const uint32_t jj = (uint32_t)(bd);
+    const uint64_t wid = A.first_id + jj % (uint32_t)per_step;
+    const uint32_t wst = (uint32_t)(step0 + jj / (uint32_t)per_step);
 
     double num = 1.0, den = 1.0, E = 0.0;   // ln q = ln(num / den) + nexp ln 2
     int nexp = 0;
@@ -299,24 +314,11 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             double Wv = 1.0;
             if (cw >= 1 && cw <= Lx - 1) Wv = fac[((size_t)r * Lx + cw) * 6 + ((x == sg) ? 4 : 5)];
             mixP[c][su][x][sg] = (float)(Wv * v);
-            double hf = 1.0;
-            if (cw >= 1 && cw <= Lx - 1) hf = fac[((size_t)r * Lx + cw) * 6 + ((x == sg) ? 4 : 5)];
-            vS[c][su][x][sg] = v * hf;
+            vS[c][su][x][sg] = v * Wv;   // the same bond, towards the previous drawn column
         }
         int8_t(*crow)[PT] = rowbuf(r & 1);
         const int8_t(*prow)[PT] = rowbuf((r + 1) & 1);
-        if (!eval && CF::UNI) {
-            for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
-                const int c = t / PT, nn = t % PT;
-                const int i = r * Lx + c;
-                const uint32_t j = (uint32_t)unit0 * 16 + nn;
-                const uint64_t id = A.first_id + j % (uint32_t)per_step;
-                const uint32_t st = (uint32_t)(step0 + j / (uint32_t)per_step);
-                const uint4 x = tn_philox(make_uint4((uint32_t)(i >> 2), (uint32_t)id, st,
-                                                     (inst << 2) | 0u), k0, k1);
-                uni[c][nn] = tn_word(x, i & 3);
-            }
-        } else if (eval) {
+        if (eval) {
             for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
                 const int nn = t / Lx, c = t % Lx;
                 const int bb = unit0 * 16 + nn;
@@ -342,66 +344,74 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             for (int t = 0; t < TL - 1; ++t) issue(t);
             wait_vm<(TL - 2) * CF::LOADS>();   // own share of column 0 has landed
             __syncthreads();
-            AT a[CF::ABUF][2];   // [set][spin]
+            AT a[CF::ABUF][2];   // [set of registers][spin]
             lds_tiles<NT, BF16>(a[0][0], ring, lane);
             lds_tiles<NT, BF16>(a[0][1], ring + CF::STAGE / 2, lane);
             if (sweep) {
-                floatx4 v0[NT], v1[NT];
+                floatx4 v0[SE][NT], v1[SE][NT];   // r_+ and r_- of every set
 #pragma unroll
-                for (int mt = 0; mt < NT; ++mt) v0[mt] = v1[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                if (grp == 0) v0[0][0] = v1[0][0] = 1.0f;
-                int e = 0;
+                for (int st = 0; st < SE; ++st)
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt) v0[st][mt] = v1[st][mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (grp == 0)
+#pragma unroll
+                    for (int st = 0; st < SE; ++st) v0[st][0][0] = v1[st][0][0] = 1.0f;
+                int e[SE];
+#pragma unroll
+                for (int st = 0; st < SE; ++st) e[st] = 0;
                 auto stepP = [&](int k, int t) {
                     const int c = colof(t);
-                    floatx4 acc[2][NT];
-                    mul_both<NT, BF16>(a[k % CF::ABUF], v0, v1, acc);
+                    floatx4 acc[SE][2][NT];
+#pragma unroll
+                    for (int st = 0; st < SE; ++st) mul_both<NT, BF16>(a[k % CF::ABUF], v0[st], v1[st], acc[st]);
                     issue(t + TL - 1);
-                    const bool up_minus = r > 0 && prow[c][pn] < 0;
-                    const floatx4 m = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
-                    if (t % RS == 0 && t > 0) {
+#pragma unroll
+                    for (int st = 0; st < SE; ++st) {
+                        const bool up_minus = r > 0 && prow[c][slot(st)] < 0;
+                        const floatx4 m = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
+                        if (t % RS == 0 && t > 0) {
+#pragma unroll
+                            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                                for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                    for (int i = 0; i < 4; ++i) acc[st][sp][mo][i] = ldexpf(acc[st][sp][mo][i], -e[st]);
+                        }
 #pragma unroll
                         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
                             for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                                for (int i = 0; i < 4; ++i) acc[sp][mo][i] = ldexpf(acc[sp][mo][i], -e);
-                    }
-#pragma unroll
-                    for (int sp = 0; sp < 2; ++sp)
+                                __builtin_amdgcn_raw_buffer_store_b128(
+                                    __builtin_bit_cast(uintx4, acc[st][sp][mo]), grs[st],
+                                    (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
 #pragma unroll
                         for (int mo = 0; mo < NT; ++mo)
-                            __builtin_amdgcn_raw_buffer_store_b128(
-                                __builtin_bit_cast(uintx4, acc[sp][mo]), grs,
-                                (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
 #pragma unroll
-                    for (int mo = 0; mo < NT; ++mo)
+                            for (int i = 0; i < 4; ++i) {
+                                v0[st][mo][i] = m[0] * acc[st][0][mo][i] + m[1] * acc[st][1][mo][i];
+                                v1[st][mo][i] = m[2] * acc[st][0][mo][i] + m[3] * acc[st][1][mo][i];
+                            }
+                        if (t % RS == RS - 1) {
+                            float mx = 0.0f;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            v0[mo][i] = m[0] * acc[0][mo][i] + m[1] * acc[1][mo][i];
-                            v1[mo][i] = m[2] * acc[0][mo][i] + m[3] * acc[1][mo][i];
+                            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                                for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(acc[st][sp][mo][i]));
+                            e[st] = pow2_exponent_f(rows4_max(mx));
                         }
-                    if (t % RS == RS - 1) {
-                        float mx = 0.0f;
-#pragma unroll
-                        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-                            for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                                for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(acc[sp][mo][i]));
-                        e = pow2_exponent_f(rows4_max(mx));
                     }
-#ifdef TN_TEAM_FENCE
-                    __builtin_amdgcn_sched_barrier(0);
-#endif
                     // own fetch of column t + 1 has landed: at most the ops
                     // issued after it are in flight (fewer in the first steps,
                     // which follow the prologue's fetches)
-                    if (t >= TL - 2) wait_vm<2 * NT + (TL - 2) * (CF::LOADS + 2 * NT)>();
-                    else wait_vm<(TL - 2) * CF::LOADS + 2 * NT>();
+                    constexpr int ST = SE * 2 * NT;   // stores per step
+                    if (t >= TL - 2) wait_vm<ST + (TL - 2) * (CF::LOADS + ST)>();
+                    else wait_vm<(TL - 2) * CF::LOADS + ST>();
                     team_barrier();
-                    const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], st, lane);
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], st + CF::STAGE / 2, lane);
+                    const unsigned char *stg = ring + ((t + 1) % TL) * CF::STAGE;
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
@@ -410,108 +420,128 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                 }
                 if (t < Lx) stepP(0, t);
             } else {
-                auto gload = [&](floatx4 (&gk)[2][NT], int c) {
+                auto gload = [&](floatx4 (&gk)[SE][2][NT], int c) {
 #pragma unroll
-                    for (int s2 = 0; s2 < 2; ++s2)
+                    for (int st = 0; st < SE; ++st)
 #pragma unroll
-                        for (int mo = 0; mo < NT; ++mo)
-                            gk[s2][mo] = __builtin_bit_cast(
-                                floatx4, __builtin_amdgcn_raw_buffer_load_b128(
-                                             grs, (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
-                                             uniform_u32((uint32_t)c * gstride), 0));
+                        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                            for (int mo = 0; mo < NT; ++mo)
+                                gk[st][s2][mo] = __builtin_bit_cast(
+                                    floatx4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 grs[st], (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
+                                                 uniform_u32((uint32_t)c * gstride), 0));
                 };
-                floatx4 g[2][2][NT];
+                floatx4 g[2][SE][2][NT];
                 gload(g[0], colof(0));
                 gload(g[1], colof(min(1, Lx - 1)));
-                floatx4 lam[NT];
+                floatx4 lam[SE][NT];
 #pragma unroll
-                for (int mt = 0; mt < NT; ++mt) lam[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-                if (grp == 0) lam[0][0] = 1.0f;
+                for (int st = 0; st < SE; ++st)
+#pragma unroll
+                    for (int mt = 0; mt < NT; ++mt) lam[st][mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (grp == 0)
+#pragma unroll
+                    for (int st = 0; st < SE; ++st) lam[st][0][0] = 1.0f;
                 int sprev = 0;
-                // random words drawn as the row goes (when not in LDS): one
-                // Philox block per four sites, kept for the next sites
                 uint4 words = make_uint4(0u, 0u, 0u, 0u);
                 int wblk = -1;
-                const uint32_t jj = (uint32_t)unit0 * 16 + pn;
-                const uint64_t wid = A.first_id + jj % (uint32_t)per_step;
-                const uint32_t wst = (uint32_t)(step0 + jj / (uint32_t)per_step);
                 auto stepS = [&](int k, int t) {
                     const int c = colof(t);
-                    const int8_t up = prow[c][pn];
-                    uint32_t word;
-                    if constexpr (CF::UNI) {
-                        word = uni[c][pn];
-                    } else {
-                        const int i = r * Lx + c;
-                        if (!eval && (i >> 2) != wblk) {
-                            wblk = i >> 2;
-                            words = tn_philox(make_uint4((uint32_t)wblk, (uint32_t)wid, wst, (inst << 2) | 0u), k0, k1);
-                        }
-                        word = tn_word(words, i & 3);
+                    const int8_t up = prow[c][pd];
+                    const int8_t given = crow[c][pd];
+                    const int i = r * Lx + c;
+                    if (!eval && (i >> 2) != wblk) {   // uniform: every lane's sites move together
+                        wblk = i >> 2;
+                        words = tn_philox(make_uint4((uint32_t)wblk, (uint32_t)wid, wst, (inst << 2) | 0u), k0, k1);
                     }
-                    const int8_t given = crow[c][pn];
+                    const uint32_t word = tn_word(words, i & 3);
                     const bool up_minus = r > 0 && up < 0;
                     const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
-                    floatx4 acc[2][NT];
-                    mul_both<NT, BF16>(a[k % CF::ABUF], lam, lam, acc);
-                    float d0 = 0.0f, d1 = 0.0f;
+                    floatx4 acc[SE][2][NT];
 #pragma unroll
-                    for (int mo = 0; mo < NT; ++mo)
+                    for (int st = 0; st < SE; ++st) mul_both<NT, BF16>(a[k % CF::ABUF], lam[st], lam[st], acc[st]);
+                    float d0[SE], d1[SE];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            d0 = fmaf(lam[mo][i], g[k][0][mo][i], d0);
-                            d1 = fmaf(lam[mo][i], g[k][1][mo][i], d1);
-                        }
+                    for (int st = 0; st < SE; ++st) {
+                        d0[st] = 0.0f;
+                        d1[st] = 0.0f;
+#pragma unroll
+                        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                            for (int ii = 0; ii < 4; ++ii) {
+                                d0[st] = fmaf(lam[st][mo][ii], g[k][st][0][mo][ii], d0[st]);
+                                d1[st] = fmaf(lam[st][mo][ii], g[k][st][1][mo][ii], d1[st]);
+                            }
+                    }
                     issue(t + TL - 1);
                     gload(g[k], colof(min(t + 2, Lx - 1)));
-                    rows4_sum2(d0, d1);
-                    double w0 = vv.x * (double)d0;
-                    double w1 = vv.y * (double)d1;
+#pragma unroll
+                    for (int st = 0; st < SE; ++st) rows4_sum2(d0[st], d1[st]);
+                    const float dd0 = (SE == 2 && ds) ? d0[SE - 1] : d0[0];
+                    const float dd1 = (SE == 2 && ds) ? d1[SE - 1] : d1[0];
+                    double w0 = vv.x * (double)dd0;
+                    double w1 = vv.y * (double)dd1;
                     n_clamp += (w0 < 0.0) + (w1 < 0.0);
                     w0 = fmax(w0, 0.0);
                     w1 = fmax(w1, 0.0);
                     const double tot = w0 + w1;
                     const bool bad = !(tot > 0.0 && tot <= 1.79e308);
                     n_both += bad;
+                    // s = +1 iff u < w0 / tot, decided as u tot < w0 (p+ = 1/2 if degenerate)
                     const double u = tn_u01(word);
                     const double ut = bad ? u : u * tot, wt = bad ? 0.5 : w0, sc = bad ? 1.0 : tot;
                     const int sd = eval ? (int)given : ((ut < wt) ? 1 : -1);
                     n_near += !eval && fabs(ut - wt) < 1e-6 * sc;
-                    crow[c][pn] = (int8_t)sd;
+                    crow[c][pd] = (int8_t)sd;   // the lanes of a proposal write the same value
                     num *= bad ? 0.5 : (sd > 0 ? w0 : w1);
                     den *= sc;
                     sprev = sd > 0 ? 0 : 1;
+                    // every set's decisions in every lane
+                    int sdset[SE];
+                    if constexpr (SE == 2) {
+                        const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)sd, (uint32_t)sd, false, false);
+                        sdset[0] = (int)sw[0];
+                        sdset[SE - 1] = (int)sw[1];
+                    } else {
+                        sdset[0] = sd;
+                    }
                     if (t % RS == RS - 1) {
-                        float mx = 0.0f;
+                        // power-of-two rescale of the output (from the input's largest
+                        // entry) and renormalisation of the ln q products
 #pragma unroll
-                        for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(lam[mo][i]));
-                        const int ee = pow2_exponent_f(rows4_max(mx));
-#pragma unroll
-                        for (int sp = 0; sp < 2; ++sp)
+                        for (int st = 0; st < SE; ++st) {
+                            float mx = 0.0f;
 #pragma unroll
                             for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                                for (int i = 0; i < 4; ++i) acc[sp][mo][i] = ldexpf(acc[sp][mo][i], -ee);
+                                for (int ii = 0; ii < 4; ++ii) mx = fmaxf(mx, fabsf(lam[st][mo][ii]));
+                            const int ee = pow2_exponent_f(rows4_max(mx));
+#pragma unroll
+                            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                                for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                    for (int ii = 0; ii < 4; ++ii) acc[st][sp][mo][ii] = ldexpf(acc[st][sp][mo][ii], -ee);
+                        }
                         int e1, e2;
                         num = frexp(num, &e1);
                         den = frexp(den, &e2);
                         nexp += e1 - e2;
                     }
 #pragma unroll
-                    for (int mo = 0; mo < NT; ++mo) lam[mo] = sd > 0 ? acc[0][mo] : acc[1][mo];
-#ifdef TN_TEAM_FENCE
-                    __builtin_amdgcn_sched_barrier(0);
-#endif
+                    for (int st = 0; st < SE; ++st)
+#pragma unroll
+                        for (int mo = 0; mo < NT; ++mo) lam[st][mo] = sdset[st] > 0 ? acc[st][0][mo] : acc[st][1][mo];
                     // own fetch of column t + 1 has landed (ops issued after it:
                     // the y loads of its step and TL - 2 steps of fetches and y
                     // loads; more in the first steps)
-                    wait_vm<2 * NT + (TL - 2) * (CF::LOADS + 2 * NT)>();
+                    constexpr int GL = SE * 2 * NT;   // y loads per step
+                    wait_vm<GL + (TL - 2) * (CF::LOADS + GL)>();
                     team_barrier();
-                    const unsigned char *st = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], st, lane);
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], st + CF::STAGE / 2, lane);
+                    const unsigned char *stg = ring + ((t + 1) % TL) * CF::STAGE;
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
+                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
@@ -522,16 +552,18 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             }
         }
         __syncthreads();   // the drawn row is complete in LDS
+        // energy of row r (Eq. ising: field, bonds in the row, bonds to the row
+        // above): CG column groups per proposal, summed in a fixed order
         {
             double eg = 0.0;
-            for (int c = grp; c < Lx; c += 4) {
-                const double sc = crow[c][pn];
+            for (int c = cg; c < Lx; c += CG) {
+                const double sc = crow[c][pd];
                 const double hv = h ? h[rowb + c] : 0.0;
-                const double jl = c > 0 ? Jh[(size_t)r * (Lx - 1) + c - 1] * (double)crow[c - 1][pn] : 0.0;
-                const double ja = r > 0 ? Jv[(size_t)(r - 1) * Lx + c] * (double)prow[c][pn] : 0.0;
+                const double jl = c > 0 ? Jh[(size_t)r * (Lx - 1) + c - 1] * (double)crow[c - 1][pd] : 0.0;
+                const double ja = r > 0 ? Jv[(size_t)(r - 1) * Lx + c] * (double)prow[c][pd] : 0.0;
                 eg -= sc * (hv + jl + ja);
             }
-            epart[w][grp][n] = eg;
+            epart[w][ds][cg][n] = eg;
         }
         if (!eval) {
             for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
@@ -541,11 +573,16 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             }
         }
         __syncthreads();
-        if (grp == 0) E += ((epart[w][0][n] + epart[w][1][n]) + epart[w][2][n]) + epart[w][3][n];
+        if (cg == 0) {
+            double es = 0.0;
+#pragma unroll
+            for (int q = 0; q < CG; ++q) es += epart[w][ds][q][n];
+            E += es;
+        }
     }
-    if (grp == 0 && valid) {
-        A.logq[b] = (log(num) - log(den)) + (double)nexp * 0.69314718055994530942;
-        A.energy[b] = E;
+    if (cg == 0 && valid) {
+        A.logq[bd] = (log(num) - log(den)) + (double)nexp * 0.69314718055994530942;
+        A.energy[bd] = E;
         if (n_clamp) atomicAdd(&A.counters[CNT_CLAMPS], (unsigned long long)n_clamp);
         if (n_both) atomicAdd(&A.counters[CNT_BOTH], (unsigned long long)n_both);
         if (n_near && !eval) atomicAdd(&A.counters[CNT_NEAR], (unsigned long long)n_near);
@@ -556,14 +593,14 @@ template <int NT, bool BF16>
 __global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16>::WPE, 8)))
 k_sampler_team(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step0,
                const uint64_t *__restrict__ step_base) {
-    team_body<NT, BF16>(A, blockIdx.x * TW, eval, k0, k1, step0 + *step_base);
+    team_body<NT, BF16>(A, blockIdx.x * TW * TeamCfg<NT, BF16>::SETS, eval, k0, k1, step0 + *step_base);
 }
 
 template <int NT, bool BF16>
 __global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16>::WPE, 8)))
 k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0, uint32_t k1,
                      uint64_t step0, const uint64_t *__restrict__ step_base) {
-    const int u0 = (int)blockIdx.x * TW;
+    const int u0 = (int)blockIdx.x * TW * TeamCfg<NT, BF16>::SETS;
     int lo = 0, hi = n - 1;
     while (lo < hi) {   // last instance whose first unit is <= u0
         const int mid = (lo + hi + 1) >> 1;
@@ -578,13 +615,13 @@ template <int NT, bool BF16>
 int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     using CF = TeamCfg<NT, BF16>;
-    const TeamSmem T(ctx->Lx, CF::STAGE, CF::TL, CF::UNI);
+    const TeamSmem T(ctx->Lx, CF::STAGE, CF::TL, CF::PT);
     auto kern = k_sampler_team<NT, BF16>;
     if (T.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
     const tn_samp_desc A = tn_samp_desc_of(ctx, B, S, logq, energy, g, per_step, first_id);
-    hipLaunchKernelGGL(kern, dim3((B + TW * 16 - 1) / (TW * 16)), dim3(TW * 64), T.total, ctx->stream, A,
+    hipLaunchKernelGGL(kern, dim3((B + CF::PT - 1) / CF::PT), dim3(TW * 64), T.total, ctx->stream, A,
                        eval ? 1 : 0, (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
@@ -595,12 +632,13 @@ template <int NT, bool BF16>
 int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks, int maxLx,
                       uint64_t seed, uint64_t step0) {
     using CF = TeamCfg<NT, BF16>;
-    const TeamSmem T(maxLx, CF::STAGE, CF::TL, CF::UNI);
+    const TeamSmem T(maxLx, CF::STAGE, CF::TL, CF::PT);
     auto kern = k_sampler_team_multi<NT, BF16>;
     if (T.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
-    hipLaunchKernelGGL(kern, dim3((blocks + TW - 1) / TW), dim3(TW * 64), T.total, ctx->stream, descs, n,
+    hipLaunchKernelGGL(kern, dim3((blocks + TW * CF::SETS - 1) / (TW * CF::SETS)), dim3(TW * 64), T.total,
+                       ctx->stream, descs, n,
                        (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
