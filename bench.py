@@ -4,10 +4,11 @@ chain on a 64x64 open ferromagnet at beta = 0.4407 with D = 32 environments,
 
 One step = one proposal per chain drawn by the batched fp32 MFMA sampler plus
 the acceptance kernel.  The proposals do not depend on the chains' state, so
-the sampler draws those of a few consecutive steps per launch (enough to give
-every compute unit two workgroups); the chains are bitwise those of one launch
-per step.  The environment build (fp64 QR/SVD) is done once before the timed
-region and reported separately.  The plain fp64 GPU path (per-row
+the sampler draws those of a few consecutive steps per launch; the chains are
+bitwise those of one launch per step.  Before the timed region the library's
+autotuner picks the sampler's launch variant and that step count by timing
+them (all variants draw the same proposals).  The environment build (fp64
+QR/SVD) is done once before the timed region and reported separately.  The plain fp64 GPU path (per-row
 launches) runs the same chains from the same seeds for the comparison, and
 the FP64 CPU oracle is timed on a bounded sample of the same workload.
 
@@ -67,7 +68,11 @@ def ahead_steps(chains):
     return max(1, -(-16 * 16 * cus // chains))
 
 
-def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):
+def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1, tune_steps=0, tune_cache=None):
+    """tune_steps > 0: pick the sampler's launch variant and the MH steps per
+    launch (up to tune_steps) with the library's autotuner before warm-up
+    (tune_cache: its JSON file of earlier choices, or None); else variant 0
+    and `ahead` steps per launch."""
     import numpy as np
     import torch
     from paper_2104_13264_amd import Sampler
@@ -84,6 +89,10 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):
         s.set_env(inst.Jh, inst.Jv, inst.h, inst.beta, inst.D, env, dims, ell, logZ, prec)
         build_s = None
     C = inst.chains
+    variant = 0
+    if tune_steps > 0:
+        variant, ahead = s.autotune(C, max_steps=tune_steps, cache=tune_cache)
+        log(f"[bench] tuned: variant {variant}, {ahead} MH steps per sampler launch")
     state = s.init_state(C)
     m = max(1, ahead)
     prop = (torch.empty((m, C, inst.Ly, inst.Lx), dtype=torch.int8, device=s.device),
@@ -135,7 +144,7 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1):
     E = E_series.cpu().numpy()
     s.close()
     return dict(wall=wall, accepted=st["accepted"], proposed=st["proposed"],
-                sampler_ms=float(np.mean(full if full else kern_ms)), steps_per_launch=m,
+                sampler_ms=float(np.mean(full if full else kern_ms)), steps_per_launch=m, variant=variant,
                 build_s=build_s, logZ=logZ, E=E, near=st["near_threshold"],
                 clamps=st["clamps"]), env_state
 
@@ -186,6 +195,8 @@ def run_ea_mix(steps, warmup):
     with torch.cuda.stream(stream):
         states = [sub.init_state(i.chains) for sub, i in zip(subs, insts)]
     stream.synchronize()
+    variants = s.autotune_multi()   # launch variant of each bond class's sampler launch
+    log(f"[bench] ea_mix: tuned variants {variants}")
     for t in range(warmup):
         s.mh_step_multi(states, SEED, t)
     stream.synchronize()
@@ -213,7 +224,9 @@ def run_ea_mix(steps, warmup):
             "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
             "config": {"workload": "ea_mix: 64 Edwards-Anderson +-J instances, L in {16,24,32,48} "
                                    "(16 each), beta [1,2,3][i mod 3], D 16/32/32/64, 1024 chains "
-                                   "each, one captured graph per MH step"},
+                                   "each, one captured graph per MH step",
+                       "sampler_variants": {f"{'bf16' if b else 'fp32'} D<={16 * nt}": v
+                                            for (b, nt), v in sorted(variants.items())}},
             "acceptance": acc / max(prop, 1),
             "acceptance_by_L": {str(L): a[0] / max(a[1], 1) for L, a in sorted(by_L.items())},
             "achieved_tflops_algorithmic": flops_step * steps / wall / 1e12,
@@ -364,9 +377,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(proposals_per_launch):
+def measured_traffic(proposals_per_launch, variant):
     """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source and launch size."""
+    they were taken on the current kernel source, launch variant and size."""
     p = os.path.join(ROOT, "profiles", "sampler_team_ferro64_traffic.json")
     try:
         with open(p) as fh:
@@ -375,7 +388,7 @@ def measured_traffic(proposals_per_launch):
         return None
     if d.get("source_hash") != kernel_source_hash():
         return None
-    if d.get("proposals_per_launch") != proposals_per_launch:
+    if d.get("proposals_per_launch") != proposals_per_launch or d.get("variant", 0) != variant:
         return None
     return d.get("bytes_per_launch")
 
@@ -387,6 +400,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
+    ap.add_argument("--tune-steps", type=int, default=32,
+                    help="largest MH-step count per sampler launch the autotuner tries "
+                         "(0: no tuning, variant 0 and the built-in count)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="the autotuner's JSON file of earlier choices (default: time afresh)")
     ap.add_argument("--ahead", type=int, default=None,
                     help="MH steps per sampler launch (default: enough for two four-wave teams per CU)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -424,7 +442,10 @@ def main():
     log(f"[bench] ferro 64x64 D={D} chains={C} steps={args.steps} warmup={args.warmup}")
 
     m = ahead_steps(C) if args.ahead is None else args.ahead
-    res32, env_state = run_gpu(1, inst, args.steps, args.warmup, ahead=m)
+    res32, env_state = run_gpu(1, inst, args.steps, args.warmup, ahead=m,
+                               tune_steps=0 if args.ahead is not None else args.tune_steps,
+                               tune_cache=args.tune_cache)
+    m = res32["steps_per_launch"]
     log(f"[bench] fp32 batched: {res32['wall']*1e3/args.steps:.3f} ms/step, "
         f"sampler {res32['sampler_ms']:.3f} ms per launch of {m} steps, "
         f"acc {res32['accepted']}/{res32['proposed']}, env build {res32['build_s']:.2f} s")
@@ -442,7 +463,7 @@ def main():
     # launch draws the proposals of `steps_per_launch` MH steps.
     flops_launch = 6.0 * D * D * L * L * C * res32["steps_per_launch"]
     achieved = flops_launch / (res32["sampler_ms"] * 1e-3)
-    traffic = measured_traffic(C * res32["steps_per_launch"])
+    traffic = measured_traffic(C * res32["steps_per_launch"], res32["variant"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -460,11 +481,12 @@ def main():
                                "beta=0.4407, D=32 fp64 environments, 4096 chains from all-up, "
                                "one proposal per chain per step",
                    "chains": C, "L": L, "D": D, "beta": inst.beta, "seed": inst.seed,
-                   "mh_steps_per_sampler_launch": res32["steps_per_launch"]},
+                   "mh_steps_per_sampler_launch": res32["steps_per_launch"],
+                   "sampler_variant": res32["variant"]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic,
-                     "kernel": "k_sampler_team<2,false>",
+                     "kernel": f"k_sampler_team<2,false,{res32['variant']}>",
                      "flops_per_launch": flops_launch,
                      "proposals_per_launch": C * res32["steps_per_launch"],
                      "kernel_ms": res32["sampler_ms"]},

@@ -255,6 +255,44 @@ int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
  *   while capturing; TN_EINVAL for beta*J = 0.  Synchronises the stream. */
 int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
 
+/* ---- Launch-shape autotuning --------------------------------------------
+ * The batched sampler has launch variants that draw bitwise the same
+ * proposals and differ only in how they are packed onto the GPU (for D <= 32:
+ * two or one sets of 16 proposals per wavefront, two or three wavefronts per
+ * SIMD).  These calls time the candidates on the context's own instance with
+ * HIP events and keep the fastest time per proposal (a candidate must beat an
+ * earlier one by 1% to replace it).  Timing launches use internal buffers and
+ * leave the caller's buffers, the counters of tn_stats and the random streams
+ * as they were.
+ * cache_path (host string, may be NULL): JSON file of earlier choices, one
+ * member per line keyed by device architecture and problem; a key found there
+ * is used without timing, a new choice is added and the file rewritten
+ * through a temporary file renamed over it.  Both calls synchronise the
+ * stream and are refused while capturing (TN_ESTATE). */
+
+/* Tune this context's instance for tn_mh_run with `chains` chains: every
+ * variant and every count of MH steps per sampler launch among 1, 2, 4, ...,
+ * max_steps (capped at 64 and by a quarter of the free device memory).  The
+ * choice applies to tn_sample, tn_sample_steps, tn_eval_logq, tn_mh_step and
+ * tn_mh_run while the lattice size, the bond dimension rounded up to 16 and
+ * the precision stay those tuned (a new build with other couplings keeps it);
+ * tn_mh_run then draws about the tuned number of proposals per launch.
+ *   variant_out, steps_out (host, may be NULL): the chosen variant and steps
+ *   per launch.  Errors: TN_ESTATE without an environment, TN_EINVAL for
+ *   chains < 1 or max_steps < 1, TN_ENOMEM, TN_EHIP; the cache file cannot be
+ *   written: TN_EINVAL.  An FP64 context tunes the steps per launch only. */
+int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, int *variant_out,
+                int *steps_out);
+
+/* Tune the sampler launch of every group of tn_mh_step_multi (instances of
+ * one bond class and precision share a launch) for the instances and chain
+ * counts of the last tn_build_env_multi; later tn_mh_step_multi calls use the
+ * choices.  variants_out (host, int [8], may be NULL): entry
+ * 4 * bf16 + NT - 1 gets the variant of group (bf16, NT = D rounded up to 16,
+ * divided by 16), -1 where there is no such group.  TN_ESTATE before
+ * tn_build_env_multi. */
+int tn_autotune_multi(tn_ctx *ctx, const char *cache_path, int *variants_out);
+
 typedef struct {
     uint64_t clamps;        /* conditional weights clamped to 0 */
     uint64_t both_nonpos;   /* sites drawn with p+ = 1/2 */

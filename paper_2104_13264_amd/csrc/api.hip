@@ -31,6 +31,52 @@ int tn_ensure(tn_ctx *ctx, void **ptr, size_t *cap, size_t bytes) {
     return TN_OK;
 }
 
+int tn_multi_prepare(tn_ctx *ctx) {
+    int rc;
+    for (size_t i = 0; i < ctx->kids.size(); ++i) {
+        tn_ctx *k = ctx->kids[i];
+        const int C = ctx->kid_chains[i];
+        const size_t nsite = (size_t)k->Lx * k->Ly;
+        const size_t spin_bytes = (((size_t)C * nsite + 255) / 256) * 256;
+        const size_t need = spin_bytes + 2 * (size_t)C * sizeof(double);
+        const size_t gneed = k->prec == TN_FP64 ? (size_t)C * k->Lx * 2 * k->D * sizeof(double)
+                                                : tn_mfma_scratch_bytes(k, C);
+        if ((need > k->pcap || gneed > k->gscr_cap) && ctx->capturing)
+            return tn_fail(ctx, TN_ESTATE, "buffers not allocated: run the step once before capture");
+        if (need > k->pcap) {
+            void *p = k->pspins;
+            if ((rc = tn_ensure(k, &p, &k->pcap, need))) return tn_fail(ctx, rc, k->err);
+            k->pspins = (int8_t *)p;
+        }
+        if (gneed > k->gscr_cap && (rc = tn_ensure(k, &k->gscr, &k->gscr_cap, gneed)))
+            return tn_fail(ctx, rc, k->err);
+        k->plogq = (double *)(k->pspins + spin_bytes);
+        k->pE = k->plogq + C;
+    }
+    return TN_OK;
+}
+
+void tn_multi_groups(tn_ctx *ctx, std::vector<tn_samp_desc> &sd, std::vector<tn_multi_group> &groups) {
+    for (int bf = 0; bf < 2; ++bf)
+        for (int NT = 1; NT <= 4; ++NT) {
+            tn_multi_group g{NT, bf == 1, (int)sd.size(), 0, 0, 1};
+            for (size_t i = 0; i < ctx->kids.size(); ++i) {
+                tn_ctx *k = ctx->kids[i];
+                const int C = ctx->kid_chains[i];
+                if (k->prec == TN_FP64 || C == 0 || k->Dp / 16 != NT || (k->prec == TN_BF16) != (bf == 1))
+                    continue;
+                tn_samp_desc A = tn_samp_desc_of(k, C, k->pspins, k->plogq, k->pE,
+                                                 (float *)k->gscr, C, 0);
+                A.blk0 = g.blocks;   // in 16-proposal units, whole teams (up to eight units) per instance
+                g.blocks += ((C + 127) / 128) * 8;
+                g.maxLx = k->Lx > g.maxLx ? k->Lx : g.maxLx;
+                sd.push_back(A);
+                ++g.count;
+            }
+            if (g.count) groups.push_back(g);
+        }
+}
+
 namespace {
 
 void free_all(tn_ctx *ctx) {
@@ -400,11 +446,12 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
     if (chains == 0 || nsteps == 0) return TN_OK;
     if (!state_spins || !state_logq || !state_energy || !accepted)
         return tn_fail(ctx, TN_EINVAL, "NULL state buffer");
-    // steps per sampler launch: two teams of 128 proposals for every compute unit
+    // steps per sampler launch: the autotuned proposals per launch, else two
+    // teams of 128 proposals for every compute unit
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
         cus = 256;
-    const long target = 16L * 16 * cus;
+    const long target = tn_tuned_here(ctx) ? ctx->tuned.proposals : 16L * 16 * cus;
     int m = (int)((target + chains - 1) / chains);
     m = m < 1 ? 1 : (m > nsteps ? nsteps : m);
     if ((size_t)chains * m > (size_t)INT32_MAX / 2) m = 1;
@@ -530,56 +577,13 @@ int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *s
         return tn_fail(ctx, TN_EINVAL, "NULL state array");
     const int n = (int)ctx->kids.size();
     int rc;
-    // proposal buffers and sampler scratch per instance (allocated on first use)
-    for (int i = 0; i < n; ++i) {
-        tn_ctx *k = ctx->kids[i];
-        const int C = ctx->kid_chains[i];
-        if (C > 0 && (!state_spins[i] || !state_logq[i] || !state_energy[i] || !accepted[i]))
+    for (int i = 0; i < n; ++i)
+        if (ctx->kid_chains[i] > 0 && (!state_spins[i] || !state_logq[i] || !state_energy[i] || !accepted[i]))
             return tn_fail(ctx, TN_EINVAL, "NULL state buffer of instance " + std::to_string(i));
-        const size_t nsite = (size_t)k->Lx * k->Ly;
-        const size_t spin_bytes = (((size_t)C * nsite + 255) / 256) * 256;
-        const size_t need = spin_bytes + 2 * (size_t)C * sizeof(double);
-        const size_t gneed = k->prec == TN_FP64 ? (size_t)C * k->Lx * 2 * k->D * sizeof(double)
-                                                : tn_mfma_scratch_bytes(k, C);
-        if ((need > k->pcap || gneed > k->gscr_cap) && ctx->capturing)
-            return tn_fail(ctx, TN_ESTATE, "buffers not allocated: run the step once before capture");
-        if (need > k->pcap) {
-            void *p = k->pspins;
-            if ((rc = tn_ensure(k, &p, &k->pcap, need))) return tn_fail(ctx, rc, k->err);
-            k->pspins = (int8_t *)p;
-        }
-        if (gneed > k->gscr_cap && (rc = tn_ensure(k, &k->gscr, &k->gscr_cap, gneed)))
-            return tn_fail(ctx, rc, k->err);
-        k->plogq = (double *)(k->pspins + spin_bytes);
-        k->pE = k->plogq + C;
-    }
-    // descriptor tables: sampler descriptors grouped by (bond class, bf16), then
-    // the acceptance descriptors of all instances
-    struct Group {
-        int NT;
-        bool bf16;
-        int first, count, blocks, maxLx;
-    };
+    if ((rc = tn_multi_prepare(ctx))) return rc;
     std::vector<tn_samp_desc> sd;
-    std::vector<Group> groups;
-    for (int bf = 0; bf < 2; ++bf)
-        for (int NT = 1; NT <= 4; ++NT) {
-            Group g{NT, bf == 1, (int)sd.size(), 0, 0, 1};
-            for (int i = 0; i < n; ++i) {
-                tn_ctx *k = ctx->kids[i];
-                const int C = ctx->kid_chains[i];
-                if (k->prec == TN_FP64 || C == 0 || k->Dp / 16 != NT || (k->prec == TN_BF16) != (bf == 1))
-                    continue;
-                tn_samp_desc A = tn_samp_desc_of(k, C, k->pspins, k->plogq, k->pE,
-                                                 (float *)k->gscr, C, 0);
-                A.blk0 = g.blocks;   // in 16-proposal units, whole teams (up to eight units) per instance
-                g.blocks += ((C + 127) / 128) * 8;
-                g.maxLx = k->Lx > g.maxLx ? k->Lx : g.maxLx;
-                sd.push_back(A);
-                ++g.count;
-            }
-            if (g.count) groups.push_back(g);
-        }
+    std::vector<tn_multi_group> groups;
+    tn_multi_groups(ctx, sd, groups);
     std::vector<tn_acc_desc> ad;
     int total = 0;
     for (int i = 0; i < n; ++i) {
@@ -630,10 +634,12 @@ int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *s
     }
     const tn_samp_desc *sdev = (const tn_samp_desc *)ctx->mdesc[slot];
     const tn_acc_desc *adev = (const tn_acc_desc *)((unsigned char *)ctx->mdesc[slot] + sbytes);
-    for (const Group &g : groups)
-        if ((rc = tn_run_mfma_multi(ctx, g.NT, g.bf16, sdev + g.first, g.count, g.blocks, g.maxLx,
-                                    seed, step)))
+    for (const tn_multi_group &g : groups) {
+        const int v = ctx->multi_variant[g.bf16 ? 1 : 0][g.NT];
+        if ((rc = tn_run_mfma_multi(ctx, g.NT, g.bf16, v < 0 ? 0 : v, sdev + g.first, g.count, g.blocks,
+                                    g.maxLx, seed, step)))
             return rc;
+    }
     for (int i = 0; i < n; ++i) {   // plain fp64 instances: one sampler launch each
         tn_ctx *k = ctx->kids[i];
         const int C = ctx->kid_chains[i];

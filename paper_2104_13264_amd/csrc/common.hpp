@@ -24,6 +24,16 @@ enum {
     CNT_N = 8
 };
 
+// Launch shape chosen by tn_autotune for one instance (lattice, padded bond
+// dimension and precision): the batched sampler's variant and the proposals
+// per sampler launch in tn_mh_run.
+struct tn_tuned {
+    bool valid = false;
+    int Lx = 0, Ly = 0, Dp = 0, prec = -1;
+    int variant = 0;
+    long proposals = 0;
+};
+
 struct tn_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -109,6 +119,11 @@ struct tn_ctx {
     // adjoint scratch
     void *gradscr = nullptr;
     size_t gradscr_cap = 0;
+
+    // autotuned launch shapes: this instance's, and per (bf16, bond class)
+    // group of tn_mh_step_multi (-1: not tuned, variant 0)
+    tn_tuned tuned;
+    int multi_variant[2][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
 };
 
 int tn_fail(tn_ctx *ctx, int code, const std::string &msg);
@@ -200,22 +215,46 @@ inline tn_samp_desc tn_samp_desc_of(tn_ctx *ctx, int B, int8_t *S, double *logq,
     A.counters = ctx->counters;
     return A;
 }
-// Scratch bytes of the batched sampler for `batch` proposals.
+// Scratch bytes of the batched sampler for `batch` proposals: both spins' y
+// tiles (fp32, 16 proposals x Dp) of every column, per 16-proposal unit, for
+// whole teams (up to eight units).
 inline size_t tn_mfma_scratch_bytes(const tn_ctx *ctx, int batch) {
-    const int units = ((batch + 127) / 128) * 8;   // 16-proposal units, whole teams (up to eight)
-    return (size_t)units * 2 * ctx->Lx * 2 * (ctx->Dp / 16) * 64 * 4 * sizeof(float);
+    const int units = ((batch + 127) / 128) * 8;
+    return (size_t)units * ctx->Lx * 2 * (size_t)ctx->Dp * 16 * sizeof(float);
 }
-int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, const tn_samp_desc *descs, int n, int blocks,
-                      int maxLx, uint64_t seed, uint64_t step0);
+// Launch variants of the batched sampler for bond class NT = Dp / 16 (same
+// arithmetic, different launch shape; sampler_mfma.hip).
+constexpr int tn_team_variants(int NT) { return NT <= 2 ? 3 : 1; }
+// Whether tn_autotune's choice applies to the context's current instance
+// (same lattice, padded bond dimension and precision), and its variant (0 if
+// there is none).
+inline bool tn_tuned_here(const tn_ctx *ctx) {
+    const tn_tuned &t = ctx->tuned;
+    return t.valid && t.Lx == ctx->Lx && t.Ly == ctx->Ly && t.Dp == ctx->Dp && t.prec == ctx->prec;
+}
+inline int tn_ctx_variant(const tn_ctx *ctx) { return tn_tuned_here(ctx) ? ctx->tuned.variant : 0; }
+int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp_desc *descs, int n,
+                      int blocks, int maxLx, uint64_t seed, uint64_t step0);
+// tn_mh_step_multi's proposal draws: every instance's proposal buffers and
+// scratch (allocated on first use; refused while capturing), and the sampler
+// descriptors grouped by (bf16, bond class), each group one launch.
+struct tn_multi_group {
+    int NT;
+    bool bf16;
+    int first, count, blocks, maxLx;
+};
+int tn_multi_prepare(tn_ctx *ctx);
+void tn_multi_groups(tn_ctx *ctx, std::vector<tn_samp_desc> &sd, std::vector<tn_multi_group> &groups);
 
 // Samplers: proposal j of a launch has id first_id + j % per_step and MH step
 // step0 + j / per_step.
 int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
                 double *energy);
+// variant: launch variant of the batched sampler, -1 for the context's
 int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
-                double *energy);
+                double *energy, int variant = -1);
 
 // MH accept kernel launcher (mh.hip)
 // One instance's MH acceptance launch as the kernel sees it.

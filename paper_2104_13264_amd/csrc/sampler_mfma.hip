@@ -29,6 +29,12 @@
 // proposal distribution does not depend on the chains' state).
 #include "common.hpp"
 
+// No implicit fusion of products into sums: the launch variants of the team
+// kernel must round alike, and the compiler's choice of which product of an
+// expression to fuse may differ between instantiations.  Fused operations are
+// written out (fmaf).
+#pragma clang fp contract(off)
+
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -177,18 +183,24 @@ __device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const f
 // runs between launches.
 constexpr int TW = 4;   // waves per team
 
-// Per bond class: TL LDS stages (columns in flight); SETS: 16-proposal sets
-// per wave; WPE: waves per SIMD the registers allow; ABUF: operand register
-// sets (two: read one column ahead; one: read just in time).
-template <int NT, bool BF16>
+// Per bond class and launch variant V: TL LDS stages (columns in flight);
+// SETS: 16-proposal sets per wave; WPE: waves per SIMD the registers allow;
+// ABUF: operand register sets (two: read one column ahead; one: read just in
+// time).  The variants differ in launch shape only, never in the arithmetic
+// of a proposal; for D <= 32 an autotuner picks one (tn_autotune):
+//   V = 0  two sets per wave, two waves per SIMD (D 33-64: one set, one wave)
+//   V = 1  one set per wave, two waves per SIMD (half the LDS per team)
+//   V = 2  one set per wave, three waves per SIMD
+template <int NT, bool BF16, int V>
 struct TeamCfg {
+    static_assert(V >= 0 && V < tn_team_variants(NT), "no such variant for this bond class");
     static constexpr uint32_t STAGE = (uint32_t)ATiles<NT, BF16>::SITE_BYTES;   // both spins
     static constexpr uint32_t LANE = STAGE % (TW * 64 * 16) == 0 ? 16 : 4;     // dwordx4 or dword fetches
     static constexpr int LOADS = (int)(STAGE / (TW * 64 * LANE));            // per wave per column
     static_assert(LOADS * TW * 64 * LANE == STAGE, "stage must split evenly");
     static constexpr int TL = NT <= 2 ? 4 : 2;
-    static constexpr int SETS = NT <= 2 ? 2 : 1;
-    static constexpr int WPE = NT <= 2 ? 2 : 1;
+    static constexpr int SETS = (NT <= 2 && V == 0) ? 2 : 1;
+    static constexpr int WPE = NT <= 2 ? (V == 2 ? 3 : 2) : 1;
     static constexpr int ABUF = (BF16 || NT <= 2) ? 2 : 1;
     static constexpr int PT = TW * 16 * SETS;   // proposals per team
 };
@@ -200,8 +212,8 @@ struct TeamSmem {
         rows = ring + tl * (int)stage;                   // int8 [2 parity][Lx][pt]
         mixP = rows + ((2 * Lx * pt + 15) & ~15);        // float [Lx][s_up][s'][s]
         vS = mixP + Lx * 8 * 4;                          // double [Lx][s_up][s_prev][s]
-        epart = vS + Lx * 8 * 8;                         // double [TW][4][16]
-        total = epart + TW * 4 * 16 * 8;
+        epart = vS + Lx * 8 * 8;                         // double [TW][sets][4][16]
+        total = epart + pt * 4 * 8;
     }
 };
 
@@ -250,11 +262,11 @@ __device__ __forceinline__ void lds_tiles(ATiles<NT, BF16> &a, const unsigned ch
     }
 }
 
-template <int NT, bool BF16>
+template <int NT, bool BF16, int V>
 __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0, const int eval,
                                           const uint32_t k0, const uint32_t k1, const uint64_t step0) {
     using AT = ATiles<NT, BF16>;
-    using CF = TeamCfg<NT, BF16>;
+    using CF = TeamCfg<NT, BF16, V>;
     constexpr int TL = CF::TL, SE = CF::SETS, PT = CF::PT;
     constexpr int CG = 4 / SE;                 // column groups of a set's energy
     const int B = A.B, Lx = A.Lx, Ly = A.Ly, per_step = A.per_step;
@@ -282,7 +294,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
     unsigned char *ring = smem + L.ring;
     float(*mixP)[2][2][2] = (float(*)[2][2][2])(smem + L.mixP);
     double(*vS)[2][2][2] = (double(*)[2][2][2])(smem + L.vS);
-    double(*epart)[SE][CG][16] = (double(*)[SE][CG][16])(smem + L.epart);
+    double(*epart)[SE][4][16] = (double(*)[SE][4][16])(smem + L.epart);
     auto rowbuf = [&](int par) { return (int8_t(*)[PT])(smem + L.rows + par * Lx * PT); };
 
     const uint32_t gstride = 2u * NT * 64 * 16;   // bytes of stored y tiles per column
@@ -388,8 +400,8 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                         for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
-                                v0[st][mo][i] = m[0] * acc[st][0][mo][i] + m[1] * acc[st][1][mo][i];
-                                v1[st][mo][i] = m[2] * acc[st][0][mo][i] + m[3] * acc[st][1][mo][i];
+                                v0[st][mo][i] = fmaf(m[1], acc[st][1][mo][i], m[0] * acc[st][0][mo][i]);
+                                v1[st][mo][i] = fmaf(m[3], acc[st][1][mo][i], m[2] * acc[st][0][mo][i]);
                             }
                         if (t % RS == RS - 1) {
                             float mx = 0.0f;
@@ -553,17 +565,19 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
         }
         __syncthreads();   // the drawn row is complete in LDS
         // energy of row r (Eq. ising: field, bonds in the row, bonds to the row
-        // above): CG column groups per proposal, summed in a fixed order
-        {
+        // above): four column groups per proposal (c = q mod 4), each summed in
+        // column order by one lane, then added in a fixed order, whatever the
+        // number of lanes per proposal
+        for (int q = cg; q < 4; q += CG) {
             double eg = 0.0;
-            for (int c = cg; c < Lx; c += CG) {
+            for (int c = q; c < Lx; c += 4) {
                 const double sc = crow[c][pd];
                 const double hv = h ? h[rowb + c] : 0.0;
                 const double jl = c > 0 ? Jh[(size_t)r * (Lx - 1) + c - 1] * (double)crow[c - 1][pd] : 0.0;
                 const double ja = r > 0 ? Jv[(size_t)(r - 1) * Lx + c] * (double)prow[c][pd] : 0.0;
                 eg -= sc * (hv + jl + ja);
             }
-            epart[w][ds][cg][n] = eg;
+            epart[w][ds][q][n] = eg;
         }
         if (!eval) {
             for (int t = threadIdx.x; t < PT * Lx; t += TW * 64) {
@@ -573,12 +587,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             }
         }
         __syncthreads();
-        if (cg == 0) {
-            double es = 0.0;
-#pragma unroll
-            for (int q = 0; q < CG; ++q) es += epart[w][ds][q][n];
-            E += es;
-        }
+        if (cg == 0) E += ((epart[w][ds][0][n] + epart[w][ds][1][n]) + epart[w][ds][2][n]) + epart[w][ds][3][n];
     }
     if (cg == 0 && valid) {
         A.logq[bd] = (log(num) - log(den)) + (double)nexp * 0.69314718055994530942;
@@ -589,18 +598,18 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
     }
 }
 
-template <int NT, bool BF16>
-__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16>::WPE, 8)))
+template <int NT, bool BF16, int V>
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16, V>::WPE, 8)))
 k_sampler_team(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step0,
                const uint64_t *__restrict__ step_base) {
-    team_body<NT, BF16>(A, blockIdx.x * TW * TeamCfg<NT, BF16>::SETS, eval, k0, k1, step0 + *step_base);
+    team_body<NT, BF16, V>(A, blockIdx.x * TW * TeamCfg<NT, BF16, V>::SETS, eval, k0, k1, step0 + *step_base);
 }
 
-template <int NT, bool BF16>
-__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16>::WPE, 8)))
+template <int NT, bool BF16, int V>
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16, V>::WPE, 8)))
 k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0, uint32_t k1,
                      uint64_t step0, const uint64_t *__restrict__ step_base) {
-    const int u0 = (int)blockIdx.x * TW * TeamCfg<NT, BF16>::SETS;
+    const int u0 = (int)blockIdx.x * TW * TeamCfg<NT, BF16, V>::SETS;
     int lo = 0, hi = n - 1;
     while (lo < hi) {   // last instance whose first unit is <= u0
         const int mid = (lo + hi + 1) >> 1;
@@ -608,15 +617,15 @@ k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0,
         else hi = mid - 1;
     }
     const tn_samp_desc A = descs[lo];
-    team_body<NT, BF16>(A, u0 - A.blk0, 0, k0, k1, step0 + *step_base);
+    team_body<NT, BF16, V>(A, u0 - A.blk0, 0, k0, k1, step0 + *step_base);
 }
 
-template <int NT, bool BF16>
+template <int NT, bool BF16, int V>
 int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
-    using CF = TeamCfg<NT, BF16>;
+    using CF = TeamCfg<NT, BF16, V>;
     const TeamSmem T(ctx->Lx, CF::STAGE, CF::TL, CF::PT);
-    auto kern = k_sampler_team<NT, BF16>;
+    auto kern = k_sampler_team<NT, BF16, V>;
     if (T.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
@@ -628,12 +637,13 @@ int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 }
 
 // blocks counts 16-proposal units, a whole number of teams per instance
-template <int NT, bool BF16>
+template <int NT, bool BF16, int V>
 int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks, int maxLx,
                       uint64_t seed, uint64_t step0) {
-    using CF = TeamCfg<NT, BF16>;
+    using CF = TeamCfg<NT, BF16, V>;
+    static_assert(8 % (TW * CF::SETS) == 0, "an instance's eight-unit blocks must split into teams");
     const TeamSmem T(maxLx, CF::STAGE, CF::TL, CF::PT);
-    auto kern = k_sampler_team_multi<NT, BF16>;
+    auto kern = k_sampler_team_multi<NT, BF16, V>;
     if (T.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
@@ -644,14 +654,35 @@ int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks,
     return TN_OK;
 }
 
+// D <= 32 classes: the three launch variants; D 33-64: variant 0 only
+template <int NT, bool BF16>
+int launch_variant(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq, double *energy,
+                   float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
+    if constexpr (NT <= 2) {
+        if (V == 1) return launch_mfma<NT, BF16, 1>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+        if (V == 2) return launch_mfma<NT, BF16, 2>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    }
+    return launch_mfma<NT, BF16, 0>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+}
+
+template <int NT, bool BF16>
+int launch_variant_multi(tn_ctx *ctx, int V, const tn_samp_desc *descs, int n, int blocks, int maxLx,
+                         uint64_t seed, uint64_t step0) {
+    if constexpr (NT <= 2) {
+        if (V == 1) return launch_mfma_multi<NT, BF16, 1>(ctx, descs, n, blocks, maxLx, seed, step0);
+        if (V == 2) return launch_mfma_multi<NT, BF16, 2>(ctx, descs, n, blocks, maxLx, seed, step0);
+    }
+    return launch_mfma_multi<NT, BF16, 0>(ctx, descs, n, blocks, maxLx, seed, step0);
+}
+
 template <bool BF16>
-int dispatch_nt(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
+int dispatch_nt(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     switch (ctx->Dp / 16) {
-    case 1: return launch_mfma<1, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    case 2: return launch_mfma<2, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    case 3: return launch_mfma<3, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    case 4: return launch_mfma<4, BF16>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 1: return launch_variant<1, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 2: return launch_variant<2, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 3: return launch_variant<3, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 4: return launch_variant<4, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
     default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
     }
 }
@@ -659,31 +690,34 @@ int dispatch_nt(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 }  // namespace
 
 int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
-                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy) {
+                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy, int variant) {
     if (batch == 0) return TN_OK;
     if (ctx->Lx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
+    if (variant < 0) variant = tn_ctx_variant(ctx);
+    if (variant >= tn_team_variants(ctx->Dp / 16)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     int rc;
     if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, tn_mfma_scratch_bytes(ctx, batch)))) return rc;
     float *g = (float *)ctx->gscr;
     if (ctx->prec == TN_BF16)
-        return dispatch_nt<true>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
-    return dispatch_nt<false>(ctx, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+        return dispatch_nt<true>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    return dispatch_nt<false>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
 }
 
-int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, const tn_samp_desc *descs, int n, int blocks,
-                      int maxLx, uint64_t seed, uint64_t step0) {
+int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp_desc *descs, int n,
+                      int blocks, int maxLx, uint64_t seed, uint64_t step0) {
     if (blocks == 0) return TN_OK;
     if (maxLx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
+    if (NT < 1 || NT > 4) return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
+    if (variant < 0 || variant >= tn_team_variants(NT)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     switch (NT * 2 + (bf16 ? 1 : 0)) {
-    case 2: return launch_mfma_multi<1, false>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 3: return launch_mfma_multi<1, true>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 4: return launch_mfma_multi<2, false>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 5: return launch_mfma_multi<2, true>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 6: return launch_mfma_multi<3, false>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 7: return launch_mfma_multi<3, true>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 8: return launch_mfma_multi<4, false>(ctx, descs, n, blocks, maxLx, seed, step0);
-    case 9: return launch_mfma_multi<4, true>(ctx, descs, n, blocks, maxLx, seed, step0);
-    default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
+    case 2: return launch_variant_multi<1, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 3: return launch_variant_multi<1, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 4: return launch_variant_multi<2, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 5: return launch_variant_multi<2, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 6: return launch_variant_multi<3, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 7: return launch_variant_multi<3, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 8: return launch_variant_multi<4, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    default: return launch_variant_multi<4, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
     }
 }

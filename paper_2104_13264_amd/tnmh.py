@@ -76,6 +76,8 @@ def lib():
         "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_grad_two_sided": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
+        "tn_autotune": (i, [vp, i, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "tn_autotune_multi": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -91,7 +93,8 @@ def exported_symbols():
             "tn_build_env_rows", "tn_build_env_end", "tn_sample",
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
-            "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats"]
+            "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
+            "tn_autotune", "tn_autotune_multi"]
 
 
 def _ptr(t):
@@ -317,6 +320,23 @@ class Sampler:
         fn = lib().tn_grad_two_sided if two_sided else lib().tn_grad
         self._check(fn(self._ctx, _ptr(dJh), _ptr(dJv), ctypes.byref(db)))
         return dJh, dJv, db.value
+
+    def autotune(self, chains, max_steps=16, cache=None):
+        """Pick the batched sampler's launch variant and the MH steps per
+        sampler launch of mh_run by timing them (tn_autotune).  cache: path of
+        the JSON file of earlier choices, or None.  Returns (variant, steps)."""
+        v, m = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().tn_autotune(self._ctx, int(chains), int(max_steps),
+                                      os.fsencode(cache) if cache else None,
+                                      ctypes.byref(v), ctypes.byref(m)))
+        return v.value, m.value
+
+    def autotune_multi(self, cache=None):
+        """Pick the launch variant of every sampler group of mh_step_multi by
+        timing (tn_autotune_multi).  Returns {(bf16, NT): variant}."""
+        out = (ctypes.c_int * 8)()
+        self._check(lib().tn_autotune_multi(self._ctx, os.fsencode(cache) if cache else None, out))
+        return {(k // 4 == 1, k % 4 + 1): out[k] for k in range(8) if out[k] >= 0}
 
     def stats(self, reset=False):
         st = _Stats()

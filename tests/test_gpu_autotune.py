@@ -1,0 +1,181 @@
+"""Launch-shape autotuning of the batched sampler (tn_autotune,
+tn_autotune_multi).
+
+The launch variants share the arithmetic of a proposal, so every variant must
+draw bitwise the same spins, ln q and energies, and evaluate ln q of given
+spins bitwise alike; a variant is forced by seeding the tuning cache with it
+(which also checks that a cached choice is used as found).  A timed choice
+must be a valid one, land in the cache file as JSON, leave the counters
+alone and leave mh_run's chains bitwise unchanged.
+"""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import random_instance, ea_pm, ferro
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32, BF16 = 0, 1, 2
+PNAME = {FP64: "fp64", FP32: "fp32", BF16: "bf16"}
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def arch():
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def write_cache(path, entries):
+    """entries: {key: (variant, proposals)}, written one member per line."""
+    lines = [f'  "{k}": ' + json.dumps({"variant": v, "proposals": p, "ns_per_proposal": 1.0})
+             for k, (v, p) in entries.items()]
+    path.write_text("{\n" + ",\n".join(lines) + "\n}\n")
+
+
+def single_key(inst, D, prec, chains, steps):
+    return f"{arch()}|{inst.Lx}x{inst.Ly}|D{D}|{PNAME[prec]}|chains{chains}|steps{steps}"
+
+
+CASES = [  # (instance, D, precision, batch): both bond classes with variants, ragged batches
+    (random_instance(10, 13, 0.6, 8, seed=81, field_scale=0.3), 8, FP32, 200),
+    (random_instance(12, 20, 0.8, 32, seed=82), 32, FP32, 300),
+    (ea_pm(16, 1.0, 24, seed=83), 24, BF16, 129),
+    (ferro(9, 0.4407, 16, Lx=14), 16, BF16, 77),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_variants_draw_bitwise_the_same(case, tmp_path):
+    from paper_2104_13264_amd import Sampler
+    inst, D, prec, B = CASES[case]
+    log(f"[tune] variants {inst.name} D={D} prec={prec} batch={B}")
+    s = Sampler()
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, D, prec)
+    ref = None
+    for v in (0, 1, 2):
+        path = tmp_path / f"v{v}.json"
+        write_cache(path, {single_key(inst, D, prec, B, 1): (v, B)})
+        assert s.autotune(B, max_steps=1, cache=str(path)) == (v, 1)
+        s.stats(reset=True)
+        sp, lq, E = s.sample(B, seed=11, step=3, first_id=5)
+        lq2, E2 = s.eval_logq(sp)
+        st = s.stats()
+        got = (sp.cpu().numpy(), lq.cpu().numpy(), E.cpu().numpy(), lq2.cpu().numpy(), E2.cpu().numpy(),
+               st["clamps"], st["near_threshold"], st["both_nonpos"])
+        if ref is None:
+            ref = got
+            continue
+        np.testing.assert_array_equal(got[0], ref[0])
+        for a, b in zip(got[1:5], ref[1:5]):
+            np.testing.assert_array_equal(a, b)
+        assert got[5:] == ref[5:]
+    s.close()
+
+
+def test_timed_choice_is_cached_and_leaves_chains_and_counters(tmp_path):
+    from paper_2104_13264_amd import Sampler
+    inst = ferro(16, 0.4407, 16)
+    C, nsteps = 96, 6
+    log(f"[tune] timed choice ferro16 D=16 chains={C}")
+    cache = tmp_path / "tune.json"
+    a = Sampler()
+    a.build_env(inst.Jh, inst.Jv, None, inst.beta, 16, FP32)
+    sa = a.init_state(C)
+    a.mh_run(sa, 5, 0, 2)
+    before = a.stats()
+    v, m = a.autotune(C, max_steps=4, cache=str(cache))
+    assert a.stats() == before
+    assert v in (0, 1, 2) and m in (1, 2, 4)
+    data = json.loads(cache.read_text())
+    k = single_key(inst, 16, FP32, C, 4)
+    assert data[k]["variant"] == v and data[k]["proposals"] == m * C and data[k]["ns_per_proposal"] > 0
+    # a second context finds the choice in the file
+    b = Sampler()
+    b.build_env(inst.Jh, inst.Jv, None, inst.beta, 16, FP32)
+    assert b.autotune(C, max_steps=4, cache=str(cache)) == (v, m)
+    # chains after the tuned mh_run are bitwise those of an untuned context
+    c = Sampler()
+    c.build_env(inst.Jh, inst.Jv, None, inst.beta, 16, FP32)
+    sb = b.init_state(C)
+    sc = c.init_state(C)
+    accb, esb = b.mh_run(sb, 9, 0, nsteps)
+    accc, esc = c.mh_run(sc, 9, 0, nsteps)
+    for key in ("spins", "logq", "energy"):
+        assert torch.equal(sb[key], sc[key]), key
+    assert torch.equal(accb, accc) and torch.equal(esb, esc)
+    for x in (a, b, c):
+        x.close()
+
+
+def test_autotune_errors(tmp_path):
+    from paper_2104_13264_amd import Sampler, TNError
+    s = Sampler()
+    with pytest.raises(TNError):
+        s.autotune(16)   # no environment yet
+    inst = ferro(6, 0.4, 8)
+    s.build_env(inst.Jh, inst.Jv, None, inst.beta, 8, FP32)
+    with pytest.raises(TNError):
+        s.autotune(0)
+    with pytest.raises(TNError):
+        s.autotune(16, max_steps=0)
+    with pytest.raises(TNError):
+        s.autotune(16, max_steps=1, cache=str(tmp_path / "no_such_dir" / "t.json"))
+    s.close()
+
+
+def multi_items():
+    return [
+        (random_instance(6, 9, 0.7, 8, seed=91, field_scale=0.2), 8, 37),
+        (ea_pm(10, 1.0, 12, seed=92), 12, 150),
+        (random_instance(9, 7, 0.5, 24, seed=93), 24, 16),
+        (ea_pm(12, 2.0, 32, seed=94), 32, 70),
+        (ferro(8, 0.4407, 40), 40, 9),
+    ]
+
+
+def multi_keys(items, prec):
+    groups = {}
+    for inst, D, C in items:
+        nt = -(-D // 16)
+        shape = f"{inst.Lx}x{inst.Ly}:D{D}:c{C}"
+        groups.setdefault(nt, {}).setdefault(shape, 0)
+        groups[nt][shape] += 1
+    return {nt: f"{arch()}|multi|{PNAME[prec]}|NT{nt}|" +
+            ",".join(f"{k}*{n}" for k, n in sorted(g.items())) for nt, g in groups.items()}
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16], ids=["fp32", "bf16"])
+def test_multi_variants_step_bitwise_alike(prec, tmp_path):
+    from paper_2104_13264_amd import Sampler
+    items = multi_items()
+    dicts = [dict(Jh=i.Jh, Jv=i.Jv, h=i.h, beta=i.beta, D=D, chains=C) for i, D, C in items]
+    keys = multi_keys(items, prec)
+    runs = []
+    for v in (None, 1, 2, "timed"):
+        log(f"[tune] multi prec={prec} variant={v}")
+        s = Sampler()
+        s.build_env_multi(dicts, prec)
+        if v == "timed":
+            got = s.autotune_multi()
+            assert set(got) == {(prec == BF16, nt) for nt in keys}
+            assert all(0 <= x < (3 if nt <= 2 else 1) for (_, nt), x in got.items())
+        elif v is not None:
+            path = tmp_path / f"m{v}.json"
+            write_cache(path, {k: (v if nt <= 2 else 0, 1) for nt, k in keys.items()})
+            got = s.autotune_multi(cache=str(path))
+            assert got == {(prec == BF16, nt): (v if nt <= 2 else 0) for nt in keys}
+        subs = [s.instance(i) for i in range(len(items))]
+        st = [sub.init_state(C) for sub, (_, _, C) in zip(subs, items)]
+        for t in range(3):
+            s.mh_step_multi(st, 4, t)
+        runs.append([{k: x[k].cpu().numpy() for k in ("spins", "logq", "energy", "accepted")} for x in st])
+        s.close()
+    for r in runs[1:]:
+        for a, b in zip(r, runs[0]):
+            for k in a:
+                np.testing.assert_array_equal(a[k], b[k], err_msg=k)
