@@ -502,6 +502,7 @@ def main():
         out["plain_fp64"] = {"value": v64, "unit": UNIT,
                              "ms_per_step": res64["wall"] * 1e3 / args.steps,
                              "acceptance": res64["accepted"] / max(res64["proposed"], 1),
+                             "tau_int_mean_energy": tau_int(res64["E"]),
                              "sampler_ms": res64["sampler_ms"]}
         out["speedup_vs_plain_fp64"] = value / v64 if v64 > 0 else None
     if not args.no_cpu:
