@@ -162,8 +162,10 @@ int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::strin
 // The same in three parts (row steps s0..s1-1 per call, synchronised), for a
 // build reported row chunk by row chunk.
 struct tn_build_plan {
-    int n = 0, maxLy = 0, nthr = 0;
-    size_t lds_bytes = 0;
+    int n = 0, maxLy = 0;
+    // the two kernel classes: D <= 32 (512 threads, matrices in LDS) and
+    // D 33-64 (1024 threads); LDS bytes 0 where no instance is of the class
+    size_t lds_small = 0, lds_big = 0;
     tn_env_desc *dd = nullptr;
     double ms = 0.0;
 };

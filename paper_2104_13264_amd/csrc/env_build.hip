@@ -82,40 +82,164 @@ __device__ void mpo_apply_row(const tn_env_desc &dsc, int k) {
 #define TN_QL (threadIdx.x & 15)          // lane within the row
 #define TN_NQW ((int)(blockDim.x >> 4))
 
-// Householder QR of A (m x n, column-major, A[j*lda + i] = A(i, j)): R in
-// the upper triangle, reflector j = (1, A(j+1:, j)) with coefficient tau[j].
-// Column-major storage keeps the 16 lanes of a row on consecutive words.
+// Column storage of the QR work matrices: LDS (D <= 32), or global memory
+// read through a buffer resource, so that a lane's element addresses are
+// 32-bit offsets from one scalar base (64-bit addresses per element would
+// not fit the registers of the 1024-thread kernel).
+template <bool GLB>
+struct ColMem;
+template <>
+struct ColMem<false> {
+    double *p;
+    __device__ ColMem(double *base, uint32_t) : p(base) {}
+    __device__ double ld(uint32_t idx) const { return p[idx]; }
+    __device__ void st(uint32_t idx, double v) const { p[idx] = v; }
+};
+template <>
+struct ColMem<true> {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ ColMem(double *base, uint32_t bytes) {
+        const uint64_t a = (uint64_t)base;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+        rs = __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), 0,
+                                               (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+    }
+    __device__ double ld(uint32_t idx) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, idx * 8u, 0, 0));
+    }
+    __device__ void st(uint32_t idx, double v) const {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, idx * 8u, 0, 0);
+    }
+};
+
+// Elements i = j + lane + 16 e (e0 <= e < e0 + N) of the column starting at
+// element c0 (m entries), one register each; entries at or beyond m read as
+// zero.  The index is clamped into the column so that all N loads issue
+// together (a loop bounded by m would wait for each load in turn).
+template <int N, bool GLB>
+__device__ __forceinline__ void col_load(const ColMem<GLB> &M, uint32_t c0, int j, int m, int e0, double (&x)[N]) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const int i = j + TN_QL + 16 * (e0 + e);
+        const double t = M.ld(c0 + (uint32_t)min(i, m - 1));
+        x[e] = i < m ? t : 0.0;
+    }
+}
+
+// col <- col - t (v . col) v over rows j .. m-1 of the column starting at
+// element c, with v the reflector stored in the column starting at vc below
+// row j and an implicit 1 at row j.  Columns of up to 128 rows (MPL <= 8)
+// keep v in registers across the columns a lane row updates (vreg, loaded
+// by the caller); longer ones read v and the column in chunks of eight,
+// twice (for the product and for the update), to bound the registers.
+template <int MPL, bool GLB>
+__device__ __forceinline__ void reflect_col(const ColMem<GLB> &M, uint32_t c, uint32_t vc,
+                                            const double (&vreg)[MPL < 8 ? MPL : 8], int j, int m, double t) {
+    constexpr int CH = MPL < 8 ? MPL : 8;
+    static_assert(MPL % CH == 0, "whole chunks");
+    double dot = 0.0;
+    if constexpr (MPL == CH) {
+        double y[CH];
+        col_load<CH, GLB>(M, c, j, m, 0, y);
+#pragma unroll
+        for (int e = 0; e < CH; ++e) dot += vreg[e] * y[e];
+        dot = tn_row16_sum(dot) * t;
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int i = j + TN_QL + 16 * e;
+            if (i < m) M.st(c + i, y[e] - dot * vreg[e]);
+        }
+    } else {
+        auto vchunk = [&](int e0, double (&v)[CH]) {
+            col_load<CH, GLB>(M, vc, j, m, e0, v);
+            if (e0 == 0 && TN_QL == 0) v[0] = 1.0;
+        };
+#pragma unroll
+        for (int e0 = 0; e0 < MPL; e0 += CH) {
+            double v[CH], y[CH];
+            vchunk(e0, v);
+            col_load<CH, GLB>(M, c, j, m, e0, y);
+#pragma unroll
+            for (int e = 0; e < CH; ++e) dot += v[e] * y[e];
+        }
+        dot = tn_row16_sum(dot) * t;
+#pragma unroll
+        for (int e0 = 0; e0 < MPL; e0 += CH) {
+            double v[CH], y[CH];
+            vchunk(e0, v);
+            col_load<CH, GLB>(M, c, j, m, e0, y);
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const int i = j + TN_QL + 16 * (e0 + e);
+                if (i < m) M.st(c + i, y[e] - dot * v[e]);
+            }
+        }
+    }
+}
+
+// The reflector's elements per lane, its leading 1 included, for reflect_col
+// (columns of up to 128 rows only).
+template <int MPL, bool GLB>
+__device__ __forceinline__ void reflector_regs(const ColMem<GLB> &M, uint32_t vc, int j, int m,
+                                               double (&v)[MPL < 8 ? MPL : 8]) {
+    if constexpr (MPL <= 8) {
+        col_load<MPL, GLB>(M, vc, j, m, 0, v);
+        if (TN_QL == 0) v[0] = 1.0;
+    }
+}
+
+// Householder QR of A (m x n, column-major, A[j*lda + i] = A(i, j); m <= 16
+// MPL): R in the upper triangle, reflector j = (1, A(j+1:, j)) with
+// coefficient tau[j].  Column-major storage keeps the 16 lanes of a row on
+// consecutive words.
+template <int MPL, bool GLB>
 __device__ void qw_householder(double *A, int m, int n, int lda, double *tau) {
+    const ColMem<GLB> M(A, (uint32_t)((size_t)lda * n * sizeof(double)));
+    constexpr int CH = MPL < 8 ? MPL : 8;
     const int kk = min(m, n);
     for (int j = 0; j < kk; ++j) {
-        double *Aj = A + (size_t)j * lda;
+        const uint32_t cj = (uint32_t)j * lda;
         if (TN_QW == 0) {
             double s2 = 0.0;
-            for (int i = j + 1 + TN_QL; i < m; i += 16) s2 += Aj[i] * Aj[i];
+#pragma unroll
+            for (int e0 = 0; e0 < MPL; e0 += CH) {
+                double x[CH];
+                col_load<CH, GLB>(M, cj, j + 1, m, e0, x);
+#pragma unroll
+                for (int e = 0; e < CH; ++e) s2 += x[e] * x[e];
+            }
             s2 = tn_row16_sum(s2);
-            const double alpha = Aj[j];
+            const double alpha = M.ld(cj + j);
             double t = 0.0, scl = 0.0, beta = alpha;
             if (s2 > 0.0) {
                 beta = -copysign(sqrt(alpha * alpha + s2), alpha);
                 t = (beta - alpha) / beta;
                 scl = 1.0 / (alpha - beta);
             }
-            for (int i = j + 1 + TN_QL; i < m; i += 16) Aj[i] *= scl;
+#pragma unroll
+            for (int e0 = 0; e0 < MPL; e0 += CH) {
+                double x[CH];
+                col_load<CH, GLB>(M, cj, j + 1, m, e0, x);
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const int i = j + 1 + TN_QL + 16 * (e0 + e);
+                    if (i < m) M.st(cj + i, x[e] * scl);
+                }
+            }
             if (TN_QL == 0) {
-                Aj[j] = beta;
+                M.st(cj + j, beta);
                 tau[j] = t;
             }
         }
         __syncthreads();
         const double t = tau[j];
         if (t != 0.0) {
-            for (int l = j + 1 + TN_QW; l < n; l += TN_NQW) {
-                double *Al = A + (size_t)l * lda;
-                double dot = 0.0;
-                for (int i = j + TN_QL; i < m; i += 16) dot += (i == j ? 1.0 : Aj[i]) * Al[i];
-                dot = tn_row16_sum(dot) * t;
-                for (int i = j + TN_QL; i < m; i += 16) Al[i] -= dot * (i == j ? 1.0 : Aj[i]);
-            }
+            double v[CH];
+            reflector_regs<MPL, GLB>(M, cj, j, m, v);
+            for (int l = j + 1 + TN_QW; l < n; l += TN_NQW)
+                reflect_col<MPL, GLB>(M, (uint32_t)l * lda, cj, v, j, m, t);
         }
         __syncthreads();
     }
@@ -123,9 +247,12 @@ __device__ void qw_householder(double *A, int m, int n, int lda, double *tau) {
 
 // Q (m x kk, column-major, ld ldq) = H_0 ... H_{kk-1} [I; 0] from the
 // reflectors in A (as left by qw_householder).
-__device__ void qw_form_q(const double *A, int m, int n, int lda, const double *tau, double *Q,
-                          int ldq) {
+template <int MPL, bool GLB>
+__device__ void qw_form_q(double *A, int m, int n, int lda, const double *tau, double *Q, int ldq) {
     const int kk = min(m, n);
+    const ColMem<GLB> MA(A, (uint32_t)((size_t)lda * n * sizeof(double)));
+    const ColMem<GLB> MQ(Q, (uint32_t)((size_t)ldq * kk * sizeof(double)));
+    constexpr int CH = MPL < 8 ? MPL : 8;
     for (int t = threadIdx.x; t < m * kk; t += blockDim.x) {
         const int l = t / m, i = t % m;
         Q[(size_t)l * ldq + i] = (i == l) ? 1.0 : 0.0;
@@ -133,41 +260,70 @@ __device__ void qw_form_q(const double *A, int m, int n, int lda, const double *
     __syncthreads();
     for (int j = kk - 1; j >= 0; --j) {
         const double tj = tau[j];
-        const double *Aj = A + (size_t)j * lda;
+        const uint32_t cj = (uint32_t)j * lda;
         if (tj != 0.0) {
+            double v[CH];
+            reflector_regs<MPL, GLB>(MA, cj, j, m, v);
             for (int l = j + TN_QW; l < kk; l += TN_NQW) {
-                double *Ql = Q + (size_t)l * ldq;
-                double dot = 0.0;
-                for (int i = j + TN_QL; i < m; i += 16) dot += (i == j ? 1.0 : Aj[i]) * Ql[i];
-                dot = tn_row16_sum(dot) * tj;
-                for (int i = j + TN_QL; i < m; i += 16) Ql[i] -= dot * (i == j ? 1.0 : Aj[i]);
+                if constexpr (MPL <= 8) {
+                    reflect_col<MPL, GLB>(MQ, (uint32_t)l * ldq, 0, v, j, m, tj);
+                } else {
+                    // the reflector lives in A, the column in Q: read both by chunks
+                    double dot = 0.0;
+#pragma unroll
+                    for (int e0 = 0; e0 < MPL; e0 += CH) {
+                        double w[CH], y[CH];
+                        col_load<CH, GLB>(MA, cj, j, m, e0, w);
+                        if (e0 == 0 && TN_QL == 0) w[0] = 1.0;
+                        col_load<CH, GLB>(MQ, (uint32_t)l * ldq, j, m, e0, y);
+#pragma unroll
+                        for (int e = 0; e < CH; ++e) dot += w[e] * y[e];
+                    }
+                    dot = tn_row16_sum(dot) * tj;
+#pragma unroll
+                    for (int e0 = 0; e0 < MPL; e0 += CH) {
+                        double w[CH], y[CH];
+                        col_load<CH, GLB>(MA, cj, j, m, e0, w);
+                        if (e0 == 0 && TN_QL == 0) w[0] = 1.0;
+                        col_load<CH, GLB>(MQ, (uint32_t)l * ldq, j, m, e0, y);
+#pragma unroll
+                        for (int e = 0; e < CH; ++e) {
+                            const int i = j + TN_QL + 16 * (e0 + e);
+                            if (i < m) MQ.st((uint32_t)l * ldq + i, y[e] - dot * w[e]);
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
     }
 }
 
-// One-sided (Hestenes) Jacobi on the rows of W [n][len] (ld ldw, len <= 128):
-// plane rotations of row pairs in the parallel round-robin order, until every
-// pair is orthogonal to relative tolerance 4*len*eps.  Rows whose squared norm
-// is below small2 = (len*eps)^2 ||W||_F^2 are numerically zero and not rotated.
-// The squared row norms are recomputed at the start of every sweep and
-// updated exactly by each rotation (a - t g, b + t g), so a pair needs only its
-// inner product.  Returns the number of sweeps, or -1 without convergence.
-__device__ int qw_jacobi(double *W, int n, int len, int ldw, double small2, double *nrm,
-                         int *flag) {
+// One-sided (Hestenes) Jacobi on the rows of W [n][len] (ld ldw, len <= 128,
+// rows zero padded to 16 NQ entries): plane rotations of row pairs in the
+// parallel round-robin order, until every pair is orthogonal to relative
+// tolerance 4*len*eps.  Rows whose squared norm is below small2 =
+// (len*eps)^2 ||W||_F^2 are numerically zero and not rotated.  The squared
+// row norms are recomputed at the start of every sweep and updated exactly by
+// each rotation (a - t g, b + t g), so a pair needs only its inner product.
+// NQ, the 16-wide slices of a row, is fixed at compile time so that a lane's
+// entries load together.  Returns the number of sweeps, or -1 without
+// convergence.
+template <int NQ>
+__device__ int qw_jacobi_nq(double *W, int n, int len, int ldw, double small2, double *nrm,
+                            int *flag) {
     if (n <= 1) return 0;
     const int npad = n + (n & 1), nr = npad - 1;
-    const int nq = (len + 15) >> 4;   // 16-wide slices per row (rows are zero padded)
     const double tol = 4.0 * len * 2.220446049250313e-16;
     const double tol2 = tol * tol;
     for (int sweep = 0; sweep < 60; ++sweep) {
         for (int i = TN_QW; i < n; i += TN_NQW) {
+            double v[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[q] = W[i * ldw + TN_QL + 16 * q];
             double s2 = 0.0;
-            for (int q = 0; q < nq; ++q) {
-                const double v = W[i * ldw + TN_QL + 16 * q];
-                s2 += v * v;
-            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) s2 += v[q] * v[q];
             s2 = tn_row16_sum(s2);
             if (TN_QL == 0) nrm[i] = s2;
         }
@@ -186,29 +342,38 @@ __device__ int qw_jacobi(double *W, int n, int len, int ldw, double small2, doub
                     if (j < 0) j += nr;
                 }
                 if (i >= n || j >= n) continue;
-                double x[8], y[8];
+                const double a = nrm[i], b = nrm[j];   // read with the rows, ahead of the reduction
+                double x[NQ], y[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    x[q] = W[i * ldw + TN_QL + 16 * q];
+                    y[q] = W[j * ldw + TN_QL + 16 * q];
+                }
                 double g = 0.0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (q < nq) {   // uniform
-                        x[q] = W[i * ldw + TN_QL + 16 * q];
-                        y[q] = W[j * ldw + TN_QL + 16 * q];
-                        g += x[q] * y[q];
-                    }
-                }
+                for (int q = 0; q < NQ; ++q) g += x[q] * y[q];
                 g = tn_row16_sum(g);
-                const double a = nrm[i], b = nrm[j];
                 if (a > small2 && b > small2 && g * g > tol2 * a * b) {
-                    // t = tan of the angle that makes the pair orthogonal
+                    // t = tan of the angle that makes the pair orthogonal.  Only
+                    // the rotation's orthogonality must be exact (cs = (1 +
+                    // t^2)^-1/2 to rounding, sn = cs t); an angle a few ulps
+                    // off leaves a residual inner product of that relative
+                    // size, which later rotations remove.  So the square root
+                    // and the reciprocal in t use the hardware estimates with
+                    // one Newton step each.
                     const double d = b - a;
-                    const double tt = copysign(1.0, d) * (2.0 * g) / (fabs(d) + sqrt(d * d + 4.0 * g * g));
+                    const double qq = d * d + 4.0 * g * g;   // > 0: g != 0 here
+                    double rq = __builtin_amdgcn_rsq(qq);
+                    rq = rq * fma(-0.5 * qq * rq, rq, 1.5);
+                    const double den = fabs(d) + qq * rq;
+                    double rd = __builtin_amdgcn_rcp(den);
+                    rd = rd * fma(-den, rd, 2.0);
+                    const double tt = (d < 0.0 ? -2.0 * g : 2.0 * g) * rd;
                     const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        if (q < nq) {
-                            W[i * ldw + TN_QL + 16 * q] = cs * x[q] - sn * y[q];
-                            W[j * ldw + TN_QL + 16 * q] = sn * x[q] + cs * y[q];
-                        }
+                    for (int q = 0; q < NQ; ++q) {
+                        W[i * ldw + TN_QL + 16 * q] = cs * x[q] - sn * y[q];
+                        W[j * ldw + TN_QL + 16 * q] = sn * x[q] + cs * y[q];
                     }
                     if (TN_QL == 0) {
                         nrm[i] = fmax(a - tt * g, 0.0);
@@ -222,6 +387,26 @@ __device__ int qw_jacobi(double *W, int n, int len, int ldw, double small2, doub
         const int any = *flag;
         __syncthreads();
         if (!any) return sweep;
+    }
+    return -1;
+}
+
+// len <= 16 SL (SL: the largest count of 16-wide slices of a row)
+template <int SL>
+__device__ int qw_jacobi(double *W, int n, int len, int ldw, double small2, double *nrm, int *flag) {
+    switch (min((len + 15) >> 4, SL)) {   // 16-wide slices per row (rows are zero padded to them)
+    case 1: return qw_jacobi_nq<1>(W, n, len, ldw, small2, nrm, flag);
+    case 2: return qw_jacobi_nq<2>(W, n, len, ldw, small2, nrm, flag);
+    case 3: return qw_jacobi_nq<3>(W, n, len, ldw, small2, nrm, flag);
+    case 4: return qw_jacobi_nq<4>(W, n, len, ldw, small2, nrm, flag);
+    }
+    if constexpr (SL > 4) {
+        switch ((len + 15) >> 4) {
+        case 5: return qw_jacobi_nq<5>(W, n, len, ldw, small2, nrm, flag);
+        case 6: return qw_jacobi_nq<6>(W, n, len, ldw, small2, nrm, flag);
+        case 7: return qw_jacobi_nq<7>(W, n, len, ldw, small2, nrm, flag);
+        default: return qw_jacobi_nq<8>(W, n, len, ldw, small2, nrm, flag);
+        }
     }
     return -1;
 }
@@ -294,9 +479,9 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
         const double xn = sqrt(x2);
         const double xinv = xn > 0.0 ? 1.0 / xn : 1.0;
         if (xn > 0.0) lognorm += log(xn);
-        qw_householder(QA, m, n, lda, tau);
+        qw_householder<QLDS ? 8 : 16, !QLDS>(QA, m, n, lda, tau);   // m <= 4 D
         const int kk = min(m, n);
-        qw_form_q(QA, m, n, lda, tau, QB, lda);
+        qw_form_q<QLDS ? 8 : 16, !QLDS>(QA, m, n, lda, tau, QB, lda);
         for (int t = threadIdx.x; t < m * kk; t += blockDim.x) {
             const int r = t / kk, l = t % kk;
             X[r * ld + l] = QB[(size_t)l * lda + r];
@@ -359,7 +544,7 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
         }
         f2 = tn_block_sum(f2, red);
         const double zero2 = f2 * (len * eps) * (len * eps);
-        const int sweeps = qw_jacobi(W, rows, len, ldw, zero2, nrm, &flag);
+        const int sweeps = qw_jacobi<QLDS ? 4 : 8>(W, rows, len, ldw, zero2, nrm, &flag);   // len <= 2 D
         if (sweeps < 0 && threadIdx.x == 0) atomicAdd(&counters[CNT_NOCONV], 1ull);
         for (int i = TN_QW; i < rows; i += TN_NQW) {
             double s2 = 0.0;
@@ -457,18 +642,19 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
 // Row step `step` of every instance (row k = Ly - 1 - step; the instances
 // that have no such row return at once): the MPO application and the
 // compression of row k.
-__global__ void __launch_bounds__(1024) k_env_row(const tn_env_desc *__restrict__ descs, int step) {
+// One kernel per class of bond cap (the instances of the other class return
+// at once): D <= 32 with 512 threads and the work matrices in LDS, D 33-64
+// with 1024 threads (one 16-lane row per row pair of the 2 D-row SVD matrix).
+template <bool BIG>
+__global__ void __launch_bounds__(BIG ? 1024 : 512) k_env_row(const tn_env_desc *__restrict__ descs, int step) {
     extern __shared__ double lds[];
     const tn_env_desc dsc = descs[blockIdx.x];
     const int k = dsc.Ly - 1 - step;
-    if (k < 1) return;
+    if (k < 1 || (dsc.D > 32) != BIG) return;
     if (step == 0)   // trivial env below the last row: bond 1 everywhere
         for (int c = threadIdx.x; c <= dsc.Lx; c += blockDim.x) dsc.dims[(size_t)dsc.Ly * (dsc.Lx + 1) + c] = 1;
     mpo_apply_row(dsc, k);
-    if (dsc.D <= 32)
-        truncate_row<true>(dsc, k, lds);
-    else
-        truncate_row<false>(dsc, k, lds);
+    truncate_row<!BIG>(dsc, k, lds);
 }
 
 // ln <top|env_1>: row 0 (no up legs) contracted with env 1 left to right,
@@ -562,7 +748,7 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
     };
     std::vector<tn_env_desc> ds(n);
     int maxLy = 1, maxD = 1;
-    size_t lds_dbl = 0;
+    size_t lds_small = 0, lds_big = 0;   // doubles
     for (int i = 0; i < n; ++i) {
         tn_ctx *ctx = ctxs[i];
         const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
@@ -597,8 +783,9 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
         d.counters = ctx->counters;
         maxLy = Ly > maxLy ? Ly : maxLy;
         maxD = D > maxD ? D : maxD;
+        size_t &lds_cls = D <= 32 ? lds_small : lds_big;
         const size_t need = D <= 32 ? 2 * tn_qr_area(D) : tn_svd_area(D);
-        lds_dbl = need > lds_dbl ? need : lds_dbl;
+        lds_cls = need > lds_cls ? need : lds_cls;
     }
     int rc;
     if ((rc = tn_ensure(c0, (void **)&c0->descs, &c0->descs_cap, n * sizeof(tn_env_desc))))
@@ -611,16 +798,18 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
         if (hipMemsetAsync(ctxs[i]->counters + CNT_NOCONV, 0, sizeof(unsigned long long), stream) !=
             hipSuccess)
             return fail(TN_EHIP, "counter reset failed");
-    const size_t lds_bytes = lds_dbl * sizeof(double);
-    if (hipFuncSetAttribute((const void *)k_env_row, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes) != hipSuccess)
+    if (lds_small && hipFuncSetAttribute((const void *)k_env_row<false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(lds_small * sizeof(double))) != hipSuccess)
         return fail(TN_EHIP, "LDS size not accepted");
-    // one 16-lane row per row pair of the largest SVD matrix (2 D rows)
-    const int nthr = maxD <= 32 ? 512 : 1024;
+    if (lds_big && hipFuncSetAttribute((const void *)k_env_row<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(lds_big * sizeof(double))) != hipSuccess)
+        return fail(TN_EHIP, "LDS size not accepted");
     plan->n = n;
     plan->maxLy = maxLy;
-    plan->nthr = nthr;
-    plan->lds_bytes = lds_bytes;
+    plan->lds_small = lds_small * sizeof(double);
+    plan->lds_big = lds_big * sizeof(double);
     plan->dd = dd;
     plan->ms = 0.0;
     return TN_OK;
@@ -629,8 +818,12 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
 int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err) {
     auto t0 = std::chrono::steady_clock::now();
     for (int step = s0; step < s1 && step + 1 < plan->maxLy; ++step) {
-        hipLaunchKernelGGL(k_env_row, dim3(plan->n), dim3(plan->nthr), plan->lds_bytes, stream,
-                           plan->dd, step);
+        if (plan->lds_small)
+            hipLaunchKernelGGL(k_env_row<false>, dim3(plan->n), dim3(512), plan->lds_small, stream,
+                               plan->dd, step);
+        if (plan->lds_big)
+            hipLaunchKernelGGL(k_env_row<true>, dim3(plan->n), dim3(1024), plan->lds_big, stream,
+                               plan->dd, step);
         if (hipGetLastError() != hipSuccess) {
             if (err) *err = "row kernel launch failed";
             return TN_EHIP;
