@@ -305,6 +305,71 @@ def run_antiferro256(steps, warmup, n_eval=2048):
             "env_build_s": build_s, "logZ": lz}
 
 
+def run_hybrid(steps=200, chains=1024, sweeps=1):
+    """+-J spin glass 32x32 at beta = 3 (the hardest of the uneven-instance
+    workload's regimes), D = 32, FP32: TNMH steps alone and with one
+    single-spin-flip Metropolis sweep after each step (the interleaving the
+    paper reports for stuck chains), from all-up, same seeds.  Reports the
+    acceptance, the energy reached and the cost of a sweep call (sweep kernel
+    plus the re-evaluation of ln q)."""
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler, FP32
+    from workloads import ea_pm, SEED
+    inst = ea_pm(32, 3.0, 32, SEED + 7, chains=chains)
+    s = Sampler()
+    t0 = time.perf_counter()
+    s.build_env(inst.Jh, inst.Jv, None, inst.beta, inst.D, FP32)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    out = {"workload": "hybrid_ea32_beta3_D32", "chains": chains, "steps": steps, "env_build_s": build_s,
+           "logZ": s.stats()["logZ"]}
+    stream = torch.cuda.current_stream()
+    for mode in ("tnmh", "tnmh+metropolis"):
+        state = s.init_state(chains)
+        s.stats(reset=True)
+        E = np.zeros(steps)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(steps):
+            s.mh_step(state, SEED, t)
+            if mode != "tnmh":
+                ev[2 * t].record(stream)
+                s.metropolis_sweeps(state, sweeps, SEED, t)
+                ev[2 * t + 1].record(stream)
+            E[t] = float(state["energy"].mean())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = s.stats()
+        r = {"acceptance": st["accepted"] / max(st["proposed"], 1), "ms_per_step": wall * 1e3 / steps,
+             "mean_energy_per_site_last_quarter": float(E[3 * steps // 4:].mean()) / (inst.Lx * inst.Ly),
+             "energy_per_site_at": {str(t): E[t] / (inst.Lx * inst.Ly) for t in (0, 9, 49, steps - 1)}}
+        if mode != "tnmh":
+            call_ms = [ev[2 * t].elapsed_time(ev[2 * t + 1]) for t in range(steps)]
+            r["sweep_call_ms"] = float(np.median(call_ms))
+            r["flips_per_site_update"] = st["metropolis_flips"] / (steps * sweeps * chains * inst.Lx * inst.Ly)
+        out[mode] = r
+        log(f"[bench] hybrid {mode}: acceptance {r['acceptance']:.4f}, E/site last quarter "
+            f"{r['mean_energy_per_site_last_quarter']:.5f}, {r['ms_per_step']:.2f} ms/step")
+    # the sweep call is the sweep kernel plus ln q of the new states; time the
+    # latter alone to split them
+    state = s.init_state(chains)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        s.eval_logq(state["spins"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eval_ms = e0.elapsed_time(e1) / 5
+    kern_ms = out["tnmh+metropolis"]["sweep_call_ms"] - eval_ms
+    out["eval_logq_ms"] = eval_ms
+    out["sweep_kernel_ms_est"] = kern_ms
+    out["site_updates_per_s_est"] = sweeps * chains * inst.Lx * inst.Ly / (kern_ms * 1e-3) if kern_ms > 0 else None
+    s.close()
+    return out
+
+
 def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8, fd_bonds=2):
     """128x128 fully frustrated lattice, beta = 1, D = 32: d ln Z~ / dJ and
     d ln Z~ / d beta (tn_grad), timed, beside the chain's own estimates of
@@ -410,7 +475,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="ferro64",
-                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128"],
+                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -422,6 +487,8 @@ def main():
             out = run_ea_mix(args.steps, args.warmup)
         elif args.workload == "antiferro256":
             out = run_antiferro256(min(args.steps, 20), min(args.warmup, 2))
+        elif args.workload == "hybrid":
+            out = run_hybrid()
         else:
             out = run_frustrated128()
         print(json.dumps(out), flush=True)

@@ -182,6 +182,25 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
               int8_t *state_spins, double *state_logq, double *state_energy,
               uint8_t *accepted, double *energy_series);
 
+/* Single-spin-flip Metropolis sweeps of every chain's state, to interleave
+ * with TNMH steps (Sec. 3 reports that spin-flip sweeps between TNMH moves
+ * help chains the approximate prior alone leaves stuck).  A sweep updates all
+ * sites with r + c even, then all with r + c odd (sites of one colour share no
+ * bond); at site i with spin s and local field F = h_i + sum of J s over the
+ * neighbours (left, right, up, down, in this order), the flip changes the
+ * energy of Eq. (ising) by dE = 2 s F and is accepted iff u < exp(-beta dE).
+ * u: word i % 4 of Philox4x32-10 at counter (sweep * 2^14 + i / 4, chain,
+ * step, instance << 2 | 2) on key `seed`, mapped to (x + 1/2) 2^-32.
+ * Afterwards ln q and E of the new states are evaluated by the arithmetic of
+ * the proposals (as tn_eval_logq), so the next tn_mh_step weighs them alike.
+ *   state_spins (dev, int8 [chains][Ly][Lx], updated in place), state_logq,
+ *   state_energy (dev, fp64 [chains], overwritten).
+ * Errors: TN_ESTATE without an environment; TN_EINVAL for chains or nsweeps
+ * < 0, nsweeps >= 2^18, more than 65536 sites, NULL buffers.  Accepted flips
+ * are counted in tn_stats. */
+int tn_metropolis_sweeps(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step,
+                         int8_t *state_spins, double *state_logq, double *state_energy);
+
 /* ---- Batched uneven instances -------------------------------------------
  * Many independent instances (lattice, couplings, beta, bond cap) sampled
  * together: their environment builds run side by side (one workgroup per
@@ -302,6 +321,7 @@ typedef struct {
     uint64_t degenerate_cuts;/* truncations with s_chi-1 - s_chi < 1e-12 s_0 */
     double   logZ;          /* ln Z~ of the current environment */
     double   env_build_ms;  /* wall time of the last tn_build_env */
+    uint64_t metropolis_flips; /* spins flipped by tn_metropolis_sweeps */
 } tn_stats_t;
 
 /* Read (and, if reset != 0, clear) the counters.  Synchronises the stream. */

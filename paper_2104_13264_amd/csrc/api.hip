@@ -485,6 +485,24 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
     return TN_OK;
 }
 
+int tn_metropolis_sweeps(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step,
+                         int8_t *state_spins, double *state_logq, double *state_energy) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (chains < 0 || nsweeps < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsweeps < 0");
+    if (nsweeps >= (1 << 18)) return tn_fail(ctx, TN_EINVAL, "nsweeps must be below 2^18");
+    if ((long)ctx->Lx * ctx->Ly > 65536) return tn_fail(ctx, TN_EINVAL, "more than 65536 sites");
+    if (chains == 0 || nsweeps == 0) return TN_OK;
+    if (!state_spins || !state_logq || !state_energy) return tn_fail(ctx, TN_EINVAL, "NULL state buffer");
+    if ((rc = tn_launch_metropolis(ctx, chains, nsweeps, seed, step, state_spins))) return rc;
+    // ln q and E of the new states, by the arithmetic that draws the proposals
+    if (ctx->prec == TN_FP64)
+        return tn_run_fp64(ctx, chains, 0, 0, chains, 0, state_spins, true, state_logq, state_energy);
+    return tn_run_mfma(ctx, chains, 0, 0, chains, 0, state_spins, true, state_logq, state_energy);
+}
+
 int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                  const int8_t *prop_spins, const double *prop_logq, const double *prop_energy,
                  int8_t *state_spins, double *state_logq, double *state_energy,
@@ -793,6 +811,7 @@ int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset) {
     out->accepted = c[CNT_ACCEPTED];
     out->proposed = c[CNT_PROPOSED];
     out->degenerate_cuts = c[CNT_DEGEN];
+    out->metropolis_flips = c[CNT_FLIPS];
     out->logZ = ctx->logZ;
     out->env_build_ms = ctx->env_build_ms;
     if (reset) TN_HIP(ctx, hipMemset(ctx->counters, 0, sizeof(c)));

@@ -21,6 +21,7 @@ enum {
     CNT_PROPOSED = 4,
     CNT_DEGEN = 5,
     CNT_NOCONV = 6,
+    CNT_FLIPS = 7,   // accepted single-spin flips of the Metropolis sweeps
     CNT_N = 8
 };
 
@@ -257,6 +258,9 @@ int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
 int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
                 double *energy, int variant = -1);
+
+// Metropolis sweeps of `chains` states in place (metropolis.hip)
+int tn_launch_metropolis(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step, int8_t *spins);
 
 // MH accept kernel launcher (mh.hip)
 // One instance's MH acceptance launch as the kernel sees it.

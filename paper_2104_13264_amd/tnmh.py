@@ -37,7 +37,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("clamps", ctypes.c_uint64), ("both_nonpos", ctypes.c_uint64),
                 ("near_threshold", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
                 ("proposed", ctypes.c_uint64), ("degenerate_cuts", ctypes.c_uint64),
-                ("logZ", ctypes.c_double), ("env_build_ms", ctypes.c_double)]
+                ("logZ", ctypes.c_double), ("env_build_ms", ctypes.c_double),
+                ("metropolis_flips", ctypes.c_uint64)]
 
 
 def lib():
@@ -78,6 +79,7 @@ def lib():
         "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
         "tn_autotune": (i, [vp, i, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "tn_autotune_multi": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i)]),
+        "tn_metropolis_sweeps": (i, [vp, i, i, u64, u64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -94,7 +96,7 @@ def exported_symbols():
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
-            "tn_autotune", "tn_autotune_multi"]
+            "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps"]
 
 
 def _ptr(t):
@@ -300,6 +302,15 @@ class Sampler:
                                     _ptr(state["energy"]), _ptr(acc),
                                     _ptr(es) if es is not None else None))
         return acc, es
+
+    def metropolis_sweeps(self, state, nsweeps, seed, step):
+        """nsweeps single-spin-flip Metropolis sweeps of every chain in place
+        (tn_metropolis_sweeps); ln q and the energy are re-evaluated."""
+        C = state["spins"].shape[0]
+        self._check(lib().tn_metropolis_sweeps(self._ctx, C, int(nsweeps), int(seed), int(step),
+                                               _ptr(state["spins"]), _ptr(state["logq"]),
+                                               _ptr(state["energy"])))
+        return state
 
     def mh_accept(self, proposal, state, seed, step):
         """Acceptance half of an MH step for proposals drawn with sample()."""
