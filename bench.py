@@ -306,23 +306,23 @@ def run_antiferro256(steps, warmup, n_eval=2048):
 
 
 def run_hybrid(steps=200, chains=1024, sweeps=1):
-    """+-J spin glass 32x32 at beta = 3 (the hardest of the uneven-instance
-    workload's regimes), D = 32, FP32: TNMH steps alone and with one
-    single-spin-flip Metropolis sweep after each step (the interleaving the
-    paper reports for stuck chains), from all-up, same seeds.  Reports the
-    acceptance, the energy reached and the cost of a sweep call (sweep kernel
-    plus the re-evaluation of ln q)."""
+    """+-J spin glass 32x32 at T = 0.212 (beta = 4.717) with D = 16, the
+    temperature, size and bond dimension of the paper's interleaving
+    experiment (Fig. hb b), FP32: TNMH steps alone and with one
+    single-spin-flip Metropolis sweep after each step, from all-up, same
+    seeds.  Reports the acceptance, the energy reached and the cost of a sweep
+    call (sweep kernel plus the re-evaluation of ln q)."""
     import numpy as np
     import torch
     from paper_2104_13264_amd import Sampler, FP32
     from workloads import ea_pm, SEED
-    inst = ea_pm(32, 3.0, 32, SEED + 7, chains=chains)
+    inst = ea_pm(32, 1.0 / 0.212, 16, SEED + 7, chains=chains)
     s = Sampler()
     t0 = time.perf_counter()
     s.build_env(inst.Jh, inst.Jv, None, inst.beta, inst.D, FP32)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    out = {"workload": "hybrid_ea32_beta3_D32", "chains": chains, "steps": steps, "env_build_s": build_s,
+    out = {"workload": "hybrid_ea32_T0.212_D16", "chains": chains, "steps": steps, "env_build_s": build_s,
            "logZ": s.stats()["logZ"]}
     stream = torch.cuda.current_stream()
     for mode in ("tnmh", "tnmh+metropolis"):
