@@ -131,7 +131,7 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1, tune_steps=0, tu
         launch_sizes.append(mm)
         for j in range(mm):
             accept(warmup + k, j)
-            E_series[k + j].copy_(state["energy"])
+            torch.mul(state["energy"], 1.0, out=E_series[k + j])   # an elementwise kernel, not a blit
         k += mm
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -444,7 +444,8 @@ def kernel_source_hash():
 
 def measured_traffic(proposals_per_launch, variant):
     """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source, launch variant and size."""
+    they were taken on the current kernel source in this launch shape (the
+    file holds one entry per measured shape)."""
     p = os.path.join(ROOT, "profiles", "sampler_team_ferro64_traffic.json")
     try:
         with open(p) as fh:
@@ -453,9 +454,10 @@ def measured_traffic(proposals_per_launch, variant):
         return None
     if d.get("source_hash") != kernel_source_hash():
         return None
-    if d.get("proposals_per_launch") != proposals_per_launch or d.get("variant", 0) != variant:
-        return None
-    return d.get("bytes_per_launch")
+    for e in d.get("entries", []):
+        if e.get("proposals_per_launch") == proposals_per_launch and e.get("variant", 0) == variant:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def main():

@@ -474,12 +474,10 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
             const size_t o = (size_t)j * chains;
             if ((rc = tn_launch_accept(ctx, chains, seed, step0 + t0 + j, ctx->pspins + o * nsite,
                                        ctx->plogq + o, ctx->pE + o, state_spins, state_logq,
-                                       state_energy, accepted + (size_t)(t0 + j) * chains)))
+                                       state_energy, accepted + (size_t)(t0 + j) * chains,
+                                       energy_series ? energy_series + (size_t)(t0 + j) * chains
+                                                     : nullptr)))
                 return rc;
-            if (energy_series)
-                TN_HIP(ctx, hipMemcpyAsync(energy_series + (size_t)(t0 + j) * chains, state_energy,
-                                           (size_t)chains * sizeof(double),
-                                           hipMemcpyDeviceToDevice, ctx->stream));
         }
     }
     return TN_OK;
@@ -622,6 +620,7 @@ int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *s
         A.sE = state_energy[i];
         A.accepted = accepted[i];
         A.counters = k->counters;
+        A.eser = nullptr;
         ad.push_back(A);
         total += C;
     }

@@ -275,13 +275,15 @@ struct tn_acc_desc {
     double *slogq, *sE;
     uint8_t *accepted;
     unsigned long long *counters;
+    double *eser;   // state energy after the step, [chains], or NULL
 };
 int tn_launch_accept_multi(tn_ctx *ctx, const tn_acc_desc *descs, int n, int total_chains,
                            uint64_t seed, uint64_t step);
 int tn_launch_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                      const int8_t *prop_spins, const double *prop_logq,
                      const double *prop_energy, int8_t *state_spins, double *state_logq,
-                     double *state_energy, uint8_t *accepted);
+                     double *state_energy, uint8_t *accepted,
+                     double *energy_series = nullptr);
 
 // adjoint (grad.hip)
 // upper == nullptr: the frozen-truncation derivative of ln Z~; otherwise the
