@@ -298,7 +298,7 @@ def run_antiferro256(steps, warmup, n_eval=2048):
             "roofline": {"bound": "mfma", "achieved": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 1e12,
                          "peak": 2500.0, "unit": "TFLOP/s",
                          "frac": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
-                         "traffic": None, "kernel": "k_sampler_team<4,true>",
+                         "traffic": None, "kernel": "k_sampler_team<4,true,0>",
                          "kernel_ms": out["bf16"]["sampler_ms"]},
             "fp32": {k: v for k, v in out["fp32"].items() if k not in ("spins", "logq")},
             "abs_logq_minus_fp64": dev, "n_eval": n_eval,
