@@ -325,7 +325,7 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     out = {"workload": "hybrid_ea32_T0.212_D16", "chains": chains, "steps": steps, "env_build_s": build_s,
            "logZ": s.stats()["logZ"]}
     stream = torch.cuda.current_stream()
-    for mode in ("tnmh", "tnmh+metropolis"):
+    for mode, nsw in modes:
         state = s.init_state(chains)
         s.stats(reset=True)
         E = np.zeros(steps)
@@ -366,6 +366,68 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     out["eval_logq_ms"] = eval_ms
     out["sweep_kernel_ms_est"] = kern_ms
     out["site_updates_per_s_est"] = sweeps * chains * inst.Lx * inst.Ly / (kern_ms * 1e-3) if kern_ms > 0 else None
+    s.close()
+    return out
+
+
+def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("tnmh+metropolis", 1))):
+    """Equilibration test of Sec. 3, Eq. (Delta), on Gaussian spin glasses in
+    the setting of the paper's Fig. hb b: n_inst 32x32 open instances at
+    T = 0.212, D = 16, 30 chains each (15 replica pairs), from uniform random
+    configurations; MH steps of all instances together (`modes`: name and
+    Metropolis sweeps after each step).  Delta(t) is the disorder average
+    over the instances of <H>/|V| + beta (|E| - link overlap)/|V| with the
+    thermal averages over each instance's chains and replica pairs."""
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler, FP32
+    from workloads import ea_gauss_set, random_spins, SEED
+    prec = FP32 if prec is None else prec
+    insts = ea_gauss_set(n=n_inst, chains=chains)
+    L = insts[0].Lx
+    nV, nE = L * L, 2 * L * (L - 1)
+    beta = insts[0].beta
+    s = Sampler()
+    t0 = time.perf_counter()
+    s.build_env_multi([dict(Jh=i.Jh, Jv=i.Jv, h=None, beta=i.beta, D=i.D, chains=i.chains) for i in insts], prec)
+    build_s = time.perf_counter() - t0
+    log(f"[bench] delta: {n_inst} Gaussian instances built in {build_s:.2f} s")
+    subs = [s.instance(k) for k in range(n_inst)]
+    out = {"workload": "delta_ea_gauss32_T0.212_D16", "instances": n_inst, "chains": chains,
+           "steps": steps, "env_build_s": build_s}
+    thresholds = (0.25, 0.15, 0.05, 0.025)
+    for mode, nsw in modes:
+        states = [sub.init_state(chains, torch.as_tensor(random_spins(chains, L, L, SEED + 77 + k)))
+                  for k, sub in enumerate(subs)]
+        for sub in subs:
+            sub.stats(reset=True)
+
+        def delta_now():
+            d = []
+            for sub, st in zip(subs, states):
+                e = float(st["energy"].mean())
+                q = float(sub.link_overlap(st["spins"][0::2], st["spins"][1::2]).double().mean())
+                d.append(e / nV + beta * (nE - q) / nV)
+            return float(np.mean(d))
+
+        series = [delta_now()]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for t in range(steps):
+            s.mh_step_multi(states, SEED, t)
+            if nsw:
+                for sub, st in zip(subs, states):
+                    sub.metropolis_sweeps(st, nsw, SEED, t)
+            series.append(delta_now())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        acc = sum(sub.stats()["accepted"] for sub in subs)
+        prop = sum(sub.stats()["proposed"] for sub in subs)
+        first = {str(th): next((t for t, v in enumerate(series) if v < th), None) for th in thresholds}
+        out[mode] = {"delta": series, "steps_to_reach": first, "acceptance": acc / max(prop, 1),
+                     "ms_per_step": wall * 1e3 / steps}
+        log(f"[bench] delta {mode}: Delta(0) {series[0]:.3f}, Delta({steps}) {series[-1]:.4f}, "
+            f"steps to reach {first}, acceptance {acc / max(prop, 1):.4f}")
     s.close()
     return out
 
@@ -477,7 +539,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="ferro64",
-                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid"],
+                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -491,6 +553,10 @@ def main():
             out = run_antiferro256(min(args.steps, 20), min(args.warmup, 2))
         elif args.workload == "hybrid":
             out = run_hybrid()
+        elif args.workload == "delta":
+            from paper_2104_13264_amd import FP64, FP32
+            out = {"fp64": run_delta(prec=FP64),
+                   "fp32": run_delta(prec=FP32, modes=(("tnmh+metropolis", 1),))}
         else:
             out = run_frustrated128()
         print(json.dumps(out), flush=True)

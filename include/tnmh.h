@@ -201,6 +201,14 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
 int tn_metropolis_sweeps(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step,
                          int8_t *state_spins, double *state_logq, double *state_energy);
 
+/* Link overlap of configuration pairs: q[k] = sum over the bonds <ij> of
+ * a_i a_j b_i b_j (k < n), the two-replica estimate of sum_<ij> <s_i s_j>^2 in
+ * the equilibration test of Sec. 3, Eq. (Delta).
+ *   a, b (dev, int8 [n][Ly][Lx]) on this context's lattice; q (dev, int32 [n]).
+ * Errors: TN_ESTATE without an environment (the lattice size comes from it),
+ * TN_EINVAL for n < 0 or NULL buffers. */
+int tn_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_t *q);
+
 /* ---- Batched uneven instances -------------------------------------------
  * Many independent instances (lattice, couplings, beta, bond cap) sampled
  * together: their environment builds run side by side (one workgroup per

@@ -35,3 +35,28 @@ def tau_int(series, burn=0.1, c_window=6.0):
         if W >= c_window * tau:
             return tau, W
     return tau, len(C) - 1
+
+
+# ---------------------------------------------------------------------------
+# Equilibration test of Sec. 3, Eq. (Delta), for spin glasses with Gaussian
+# couplings of unit variance and no field.  Integrating by parts over one
+# Gaussian coupling gives E_J[J <s_i s_j>] = beta E_J[1 - <s_i s_j>^2], so at
+# equilibrium the disorder-averaged energy per site and the link overlap
+# satisfy
+#     Delta = [<H>]_av / |V| + beta (|E| - sum_<ij> [<s_i s_j>^2]_av) / |V| = 0,
+# |V| sites, |E| bonds.  <s_i s_j>^2 is estimated from two independent
+# replicas a, b of the same instance: s_i^a s_j^a s_i^b s_j^b.
+
+def link_overlap(a, b):
+    """sum over the bonds <ij> of a_i a_j b_i b_j, per configuration pair
+    (a, b: int arrays [..., Ly, Lx] of +-1)."""
+    a = np.asarray(a, dtype=np.int64)
+    b = np.asarray(b, dtype=np.int64)
+    ab = a * b
+    return ((ab[..., :, :-1] * ab[..., :, 1:]).sum(axis=(-1, -2))
+            + (ab[..., :-1, :] * ab[..., 1:, :]).sum(axis=(-1, -2)))
+
+
+def delta(mean_energy, mean_link_overlap, beta, n_sites, n_bonds):
+    """Eq. (Delta) from the disorder averages of <H> and of sum_<ij> <s_i s_j>^2."""
+    return mean_energy / n_sites + beta * (n_bonds - mean_link_overlap) / n_sites

@@ -501,6 +501,17 @@ int tn_metropolis_sweeps(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, ui
     return tn_run_mfma(ctx, chains, 0, 0, chains, 0, state_spins, true, state_logq, state_energy);
 }
 
+int tn_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_t *q) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (n < 0) return tn_fail(ctx, TN_EINVAL, "n < 0");
+    if (n == 0) return TN_OK;
+    if (!a || !b || !q) return tn_fail(ctx, TN_EINVAL, "NULL buffer");
+    return tn_launch_link_overlap(ctx, n, a, b, q);
+}
+
 int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
                  const int8_t *prop_spins, const double *prop_logq, const double *prop_energy,
                  int8_t *state_spins, double *state_logq, double *state_energy,

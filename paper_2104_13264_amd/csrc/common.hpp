@@ -262,6 +262,9 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
 // Metropolis sweeps of `chains` states in place (metropolis.hip)
 int tn_launch_metropolis(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step, int8_t *spins);
 
+// Link overlaps of configuration pairs (stats.hip)
+int tn_launch_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_t *q);
+
 // MH accept kernel launcher (mh.hip)
 // One instance's MH acceptance launch as the kernel sees it.
 struct tn_acc_desc {

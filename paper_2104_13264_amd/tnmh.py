@@ -80,6 +80,7 @@ def lib():
         "tn_autotune": (i, [vp, i, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "tn_autotune_multi": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i)]),
         "tn_metropolis_sweeps": (i, [vp, i, i, u64, u64, vp, vp, vp]),
+        "tn_link_overlap": (i, [vp, i, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -96,7 +97,7 @@ def exported_symbols():
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
-            "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps"]
+            "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap"]
 
 
 def _ptr(t):
@@ -311,6 +312,15 @@ class Sampler:
                                                _ptr(state["spins"]), _ptr(state["logq"]),
                                                _ptr(state["energy"])))
         return state
+
+    def link_overlap(self, a, b):
+        """sum over the bonds of a_i a_j b_i b_j per configuration pair
+        (tn_link_overlap); a, b: int8 [n][Ly][Lx] on the device."""
+        a = torch.as_tensor(a, dtype=torch.int8, device=self.device).contiguous()
+        b = torch.as_tensor(b, dtype=torch.int8, device=self.device).contiguous()
+        q = torch.empty(a.shape[0], dtype=torch.int32, device=self.device)
+        self._check(lib().tn_link_overlap(self._ctx, a.shape[0], _ptr(a), _ptr(b), _ptr(q)))
+        return q
 
     def mh_accept(self, proposal, state, seed, step):
         """Acceptance half of an MH step for proposals drawn with sample()."""

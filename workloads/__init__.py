@@ -71,6 +71,15 @@ def ea_pm(L, beta, D, seed, chains=1, steps=1):
     return Instance(f"ea_pm{L}_s{seed}", Jh, Jv, None, beta, D, chains, steps)
 
 
+def ea_gauss(L, beta, D, seed, chains=1, steps=1):
+    """Edwards-Anderson instance with iid standard Gaussian couplings from
+    numpy's PCG64 stream seeded with `seed`, no field."""
+    rng = np.random.default_rng(seed)
+    Jh = rng.normal(size=(L, L - 1))
+    Jv = rng.normal(size=(L - 1, L))
+    return Instance(f"ea_gauss{L}_s{seed}", Jh, Jv, None, beta, D, chains, steps)
+
+
 def random_instance(Ly, Lx, beta, D, seed, field_scale=0.0, gaussian=True):
     """Small random instance for parity tests (Gaussian or +-1 couplings)."""
     rng = np.random.default_rng(seed)
@@ -119,6 +128,19 @@ def frustrated_128():
 def antiferro_256():
     """256x256 antiferromagnet, beta = 0.4407, D = 64; 16384 proposals/step."""
     return antiferro(256, 0.4407, 64, chains=16384, steps=20)
+
+
+def ea_gauss_set(n=64, L=32, T=0.212, D=16, chains=30):
+    """n Gaussian EA instances at temperature T (the setting of the paper's
+    equilibration test, Fig. hb b: 32x32 open, T = 0.212, D = 16, 30 chains
+    per instance), seeds SEED + 1000 + i."""
+    return [ea_gauss(L, 1.0 / T, D, SEED + 1000 + i, chains=chains) for i in range(n)]
+
+
+def random_spins(chains, Ly, Lx, seed):
+    """Independent uniform +-1 configurations (an easy starting distribution)."""
+    rng = np.random.default_rng(seed)
+    return rng.choice(np.array([-1, 1], dtype=np.int8), size=(chains, Ly, Lx))
 
 
 def all_up(chains, Ly, Lx):
