@@ -555,8 +555,7 @@ def main():
             out = run_hybrid()
         elif args.workload == "delta":
             from paper_2104_13264_amd import FP64, FP32
-            out = {"fp64": run_delta(prec=FP64),
-                   "fp32": run_delta(prec=FP32, modes=(("tnmh+metropolis", 1),))}
+            out = {"fp32": run_delta(prec=FP32), "fp64": run_delta(prec=FP64)}
         else:
             out = run_frustrated128()
         print(json.dumps(out), flush=True)

@@ -124,8 +124,11 @@ int tn_set_instance(tn_ctx *ctx, int inst);
  *   spins  (dev, int8 [batch][Ly][Lx])  drawn configurations
  *   logq   (dev, fp64 [batch])          ln q(s) of the arithmetic that drew s
  *   energy (dev, fp64 [batch])          H(s)
- * Negative conditional weights are clamped to 0 (counted in tn_stats); if
- * both are <= 0 the draw uses p+ = 1/2.  TN_ESTATE before an environment. */
+ * Negative conditional weights are clamped to 0 by the FP64 path; the FP32
+ * and BF16 paths raise every weight below 2^-24 of |w+| + |w-| to that floor,
+ * so that each configuration keeps a positive proposal probability (either
+ * way counted in tn_stats).  If both are <= 0 the draw uses p+ = 1/2.
+ * TN_ESTATE before an environment. */
 int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
               int8_t *spins, double *logq, double *energy);
 
@@ -321,7 +324,7 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
 int tn_autotune_multi(tn_ctx *ctx, const char *cache_path, int *variants_out);
 
 typedef struct {
-    uint64_t clamps;        /* conditional weights clamped to 0 */
+    uint64_t clamps;        /* conditional weights clamped (FP64: negative, to 0; FP32/BF16: below the floor) */
     uint64_t both_nonpos;   /* sites drawn with p+ = 1/2 */
     uint64_t near_threshold;/* draws with |u - p+| < 1e-6 */
     uint64_t accepted;      /* accepted MH moves since the last reset */

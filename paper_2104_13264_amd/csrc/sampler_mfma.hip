@@ -22,7 +22,8 @@
 // all tiles); powers of two are exact, so this equals rescaling the input first.
 // ln q is accumulated as two fp64 products, of the drawn weights and of the
 // weight totals, each with a separate binary exponent, and evaluated once at
-// the end; the spin is +1 iff u * (w+ + w-) < w+.
+// the end; the spin is +1 iff u * (w+ + w-) < w+.  Weights below 2^-24 of
+// |w+| + |w-| are raised to that floor.
 //
 // Proposal j of the launch has id first_id + j % per_step and MH step
 // step0 + j / per_step (several steps' proposals may share a launch; the
@@ -494,9 +495,14 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     const float dd1 = (SE == 2 && ds) ? d1[SE - 1] : d1[0];
                     double w0 = vv.x * (double)dd0;
                     double w1 = vv.y * (double)dd1;
-                    n_clamp += (w0 < 0.0) + (w1 < 0.0);
-                    w0 = fmax(w0, 0.0);
-                    w1 = fmax(w1, 0.0);
+                    // a weight below the FP32 resolution of |w+| + |w-| (negative
+                    // ones included) is not resolved: it is raised to 2^-24 of
+                    // that sum (counted), so that every configuration keeps a
+                    // positive proposal probability and a finite ln q
+                    const double fl = 0x1p-24 * (fabs(w0) + fabs(w1));
+                    n_clamp += (w0 < fl) + (w1 < fl);
+                    w0 = fmax(w0, fl);
+                    w1 = fmax(w1, fl);
                     const double tot = w0 + w1;
                     const bool bad = !(tot > 0.0 && tot <= 1.79e308);
                     n_both += bad;
