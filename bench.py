@@ -325,7 +325,7 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     out = {"workload": "hybrid_ea32_T0.212_D16", "chains": chains, "steps": steps, "env_build_s": build_s,
            "logZ": s.stats()["logZ"]}
     stream = torch.cuda.current_stream()
-    for mode, nsw in modes:
+    for mode in ("tnmh", "tnmh+metropolis"):
         state = s.init_state(chains)
         s.stats(reset=True)
         E = np.zeros(steps)
