@@ -21,6 +21,9 @@ Modules
     mh       Algorithm 1 (TNMH Markov chain) with Eqs. (mh-acc), (tns-prior)
     stats    Eqs. (cauto), (c-auto-int): autocorrelation, tau_int
     grad     derivative of ln Z~ with frozen truncation isometries
+    metropolis  single-spin-flip sweeps interleaved with TNMH steps
+    periodic periodic boundaries by alternately frozen lines (Sec.
+             "Arbitrary boundary conditions")
 
 Parity status: every function is pinned by the CPU tests (tests/test_oracle_*.py)
 against brute force, exact transfer matrices, closed forms, invariants or an

@@ -65,7 +65,7 @@ def _pow2_rescale(x, axes):
 
 
 def run_rows(model, envs, batch, seed=0, step=0, first_id=0, inst=0,
-             spins=None, near=1e-6):
+             spins=None, near=1e-6, ids=None):
     """Sample (spins None) or evaluate (spins [B,Ly,Lx] given) proposals.
 
     Returns dict(spins int8 [B,Ly,Lx], logq [B], energy [B],
@@ -79,7 +79,9 @@ def run_rows(model, envs, batch, seed=0, step=0, first_id=0, inst=0,
         out = np.asarray(spins, dtype=np.int8).copy()
     else:
         out = np.zeros((B, Ly, Lx), dtype=np.int8)
-        u_all = site_uniforms(Ly * Lx, first_id + np.arange(B), seed, step, inst)
+        if ids is None:
+            ids = first_id + np.arange(B)
+        u_all = site_uniforms(Ly * Lx, ids, seed, step, inst)
     logq = np.zeros(B)
     clamps = np.zeros(B, dtype=np.int64)
     both = np.zeros(B, dtype=np.int64)
@@ -177,9 +179,9 @@ def run_rows(model, envs, batch, seed=0, step=0, first_id=0, inst=0,
                 both_nonpos=both, near=nnear, min_gap=min_gap)
 
 
-def sample(model, envs, batch, seed, step=0, first_id=0, inst=0):
-    """Draw `batch` proposals; proposal j uses id = first_id + j."""
-    return run_rows(model, envs, batch, seed, step, first_id, inst)
+def sample(model, envs, batch, seed, step=0, first_id=0, inst=0, ids=None):
+    """Draw `batch` proposals; proposal j uses id = first_id + j (or ids[j])."""
+    return run_rows(model, envs, batch, seed, step, first_id, inst, ids=ids)
 
 
 def eval_logq(model, envs, spins):
