@@ -323,6 +323,77 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
  * tn_build_env_multi. */
 int tn_autotune_multi(tn_ctx *ctx, const char *cache_path, int *variants_out);
 
+/* ---- Periodic boundaries by frozen lines ---------------------------------
+ * Section "Arbitrary boundary conditions": a lattice whose opposite edges are
+ * identified (a cylinder along x or y, or a torus) is sampled by keeping one
+ * line of spins fixed during a TNMH step; the frozen spins act on their free
+ * neighbours as fields and the free spins form an open lattice, sampled and
+ * accepted as before.  Every chain gets its own open model (its frozen spins
+ * differ), so a step builds one environment stack per chain, in one batched
+ * build, and draws one proposal per chain.
+ *
+ * Geometry.  Ly x Lx sites, wrapped along x (wrap_x != 0) and/or y.  A wrapped
+ * direction has at least 3 sites.  Jh[r][c] couples (r,c)-(r,(c+1) mod Lx):
+ * [Ly][Lx] when wrapped along x, [Ly][Lx-1] otherwise; Jv[r][c] couples
+ * (r,c)-((r+1) mod Ly,c): [Ly][Lx] when wrapped along y, [Ly-1][Lx] otherwise;
+ * h [Ly][Lx] or NULL.  The energy is Eq. (ising) over every bond.
+ *
+ * Cut.  A step freezes column cut_col (if wrapped along x) and row cut_row (if
+ * wrapped along y).  The open lattice is (Ly - wrap_y) x (Lx - wrap_x); its site
+ * (r', c') is ((cut_row + 1 + r') mod Ly, (cut_col + 1 + c') mod Lx) in a
+ * wrapped direction and (r', c') otherwise.  A free site next to the frozen
+ * line gets the field J s_frozen of that bond, added to its own field in the
+ * order left, right, up, down.  The acceptance of Eq. (mh-acc) uses the open
+ * model's ln q and energies (they differ from the periodic energies by a term
+ * of the frozen spins alone).  The caller chooses the cuts: any sequence
+ * chosen independently of the states keeps the periodic Boltzmann law; on a
+ * torus two fixed crosses leave the two sites where the row of one meets the
+ * column of the other frozen for good, so cycle through three or more.
+ *
+ * Random numbers.  Chain j of instance m draws its proposal with id j and
+ * instance m at step `step`, and its acceptance from counter
+ * (0, j, step, m << 2 | 1), as chain j of instance m of tn_mh_step_multi. */
+typedef struct {
+    const double *Jh, *Jv, *h;   /* (dev, fp64) couplings and field (h may be NULL) */
+    double beta;
+    int chains;                  /* chains of this instance (>= 0) */
+} tn_periodic_instance;
+
+/* Set up n instances of one periodic lattice shape for tn_periodic_step.  The
+ * couplings are copied; the context allocates the open models, environment
+ * stacks and sampler buffers of every chain.  D (1..64) and prec (TN_FP64,
+ * TN_FP32, TN_BF16) as in tn_build_env.  Errors: TN_EINVAL for bad shapes
+ * (Lx, Ly >= 1, a wrapped direction >= 3 sites, open lattice at most 256
+ * columns, at most 65536 sites, at least one chain), TN_ENOMEM.  Replaces an
+ * earlier periodic set-up; independent of tn_build_env's instance.
+ * Synchronises the stream. */
+int tn_periodic_setup(tn_ctx *ctx, int Lx, int Ly, int wrap_x, int wrap_y, int D, int prec, int n,
+                      const tn_periodic_instance *inst);
+
+/* One TNMH step of every chain with the given cut.
+ *   spins (dev, int8 [total chains][Ly][Lx], instance 0's chains first):
+ *     updated in place (the frozen lines never change).
+ *   energy (dev, fp64 [total chains]): periodic energies after the step.
+ *   accepted (dev, uint8 [total chains]): 1 where the proposal was taken.
+ *   cut_row, cut_col: in 0..Ly-1 / 0..Lx-1 for a wrapped direction, ignored
+ *   otherwise.
+ * Errors: TN_ESTATE before tn_periodic_setup or while capturing; TN_EINVAL
+ * for NULL buffers or a cut out of range; TN_ENONPOS / TN_ENOCONV if a chain's
+ * environment build fails (its step is not taken).  Synchronises the stream
+ * (each step checks its builds). */
+int tn_periodic_step(tn_ctx *ctx, uint64_t seed, uint64_t step, int cut_row, int cut_col, int8_t *spins,
+                     double *energy, uint8_t *accepted);
+
+/* Periodic energies of given states (dev, int8 [total chains][Ly][Lx]) into
+ * energy (dev, fp64 [total chains]).  TN_ESTATE before tn_periodic_setup. */
+int tn_periodic_energy(tn_ctx *ctx, const int8_t *spins, double *energy);
+
+/* Link overlap over every bond of the periodic lattice, sum of
+ * a_i a_j b_i b_j, of n configuration pairs (dev, int8 [n][Ly][Lx]) into
+ * q (dev, int32 [n]); the periodic counterpart of tn_link_overlap for
+ * Eq. (Delta).  TN_ESTATE before tn_periodic_setup. */
+int tn_periodic_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_t *q);
+
 typedef struct {
     uint64_t clamps;        /* conditional weights clamped (FP64: negative, to 0; FP32/BF16: below the floor) */
     uint64_t both_nonpos;   /* sites drawn with p+ = 1/2 */

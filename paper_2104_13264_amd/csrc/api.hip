@@ -80,6 +80,7 @@ void tn_multi_groups(tn_ctx *ctx, std::vector<tn_samp_desc> &sd, std::vector<tn_
 namespace {
 
 void free_all(tn_ctx *ctx) {
+    tn_periodic_free(ctx);
     for (tn_ctx *k : ctx->kids) {
         free_all(k);
         delete k;
@@ -103,6 +104,12 @@ void free_all(tn_ctx *ctx) {
     delete (tn_build_plan *)ctx->build_plan;
     ctx->build_plan = nullptr;
 }
+
+}  // namespace
+
+void tn_free_ctx(tn_ctx *ctx) { free_all(ctx); }
+
+namespace {
 
 int check_prec(tn_ctx *ctx, int prec) {
     if (prec != TN_FP64 && prec != TN_FP32 && prec != TN_BF16)

@@ -125,9 +125,16 @@ struct tn_ctx {
     // group of tn_mh_step_multi (-1: not tuned, variant 0)
     tn_tuned tuned;
     int multi_variant[2][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
+
+    // periodic lattices (tn_periodic_setup): tn_periodic, owned
+    void *per = nullptr;
 };
 
 int tn_fail(tn_ctx *ctx, int code, const std::string &msg);
+// Frees every buffer a context owns (not the context itself).
+void tn_free_ctx(tn_ctx *ctx);
+// Frees the periodic-lattice state of a context (periodic.hip).
+void tn_periodic_free(tn_ctx *ctx);
 
 #define TN_HIP(ctx, call)                                                          \
     do {                                                                           \
@@ -175,6 +182,10 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
 int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err);
 int tn_env_build_finish(tn_ctx *const *ctxs, int n, tn_build_plan *plan, hipStream_t stream,
                         std::string *err);
+// The top overlap of every instance of a plan after its row steps, and each
+// instance's outcome in status[i] (device, int [n]): 0 usable, 1 Z~ not
+// positive or not finite, 2 SVD not converged.  No synchronisation.
+int tn_env_build_top_status(const tn_build_plan *plan, int *status, hipStream_t stream);
 int tn_env_build_device(tn_ctx *ctx, double *logZ_out);
 int tn_make_operands(tn_ctx *ctx, int prec);
 
@@ -236,8 +247,9 @@ inline bool tn_tuned_here(const tn_ctx *ctx) {
     return t.valid && t.Lx == ctx->Lx && t.Ly == ctx->Ly && t.Dp == ctx->Dp && t.prec == ctx->prec;
 }
 inline int tn_ctx_variant(const tn_ctx *ctx) { return tn_tuned_here(ctx) ? ctx->tuned.variant : 0; }
+// eval: the descriptors' spins are given and only ln q and E are computed
 int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp_desc *descs, int n,
-                      int blocks, int maxLx, uint64_t seed, uint64_t step0);
+                      int blocks, int maxLx, uint64_t seed, uint64_t step0, bool eval = false);
 // tn_mh_step_multi's proposal draws: every instance's proposal buffers and
 // scratch (allocated on first use; refused while capturing), and the sampler
 // descriptors grouped by (bf16, bond class), each group one launch.
@@ -264,6 +276,9 @@ int tn_launch_metropolis(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, ui
 
 // Link overlaps of configuration pairs (stats.hip)
 int tn_launch_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_t *q);
+// The same on a given lattice, with the bonds that wrap along x / y if wx / wy
+int tn_launch_link_overlap_lattice(tn_ctx *ctx, int Lx, int Ly, int wx, int wy, int n, const int8_t *a,
+                                   const int8_t *b, int32_t *q);
 
 // MH accept kernel launcher (mh.hip)
 // One instance's MH acceptance launch as the kernel sees it.

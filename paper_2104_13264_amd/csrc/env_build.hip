@@ -736,7 +736,31 @@ __global__ void __launch_bounds__(256) k_env_top(const tn_env_desc *__restrict__
     top_overlap(dsc);
 }
 
+// Outcome of every instance's build, for callers that rebuild many instances
+// each step without a host round trip per instance: 0 usable, 1 Z~ not
+// positive or ln Z~ not finite, 2 the Jacobi SVD did not converge.  Clears
+// the convergence counter for the next build.
+__global__ void __launch_bounds__(256) k_env_status(const tn_env_desc *__restrict__ descs, int n,
+                                                    int *__restrict__ status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const tn_env_desc d = descs[i];
+    double lz = d.scal[0];
+    for (int k = 1; k < d.Ly; ++k) lz += d.ell[k];
+    const unsigned long long nc = d.counters[CNT_NOCONV];
+    d.counters[CNT_NOCONV] = 0ull;
+    status[i] = nc ? 2 : ((!(d.scal[1] > 0.0) || !isfinite(lz)) ? 1 : 0);
+}
+
 }  // namespace
+
+int tn_env_build_top_status(const tn_build_plan *plan, int *status, hipStream_t stream) {
+    if (plan->n <= 0) return TN_OK;
+    hipLaunchKernelGGL(k_env_top, dim3(plan->n), dim3(256), 0, stream, plan->dd);
+    hipLaunchKernelGGL(k_env_status, dim3((plan->n + 255) / 256), dim3(256), 0, stream, plan->dd, plan->n,
+                       status);
+    return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+}
 
 int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err,
                          tn_build_plan *plan) {
@@ -817,6 +841,17 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
 
 int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err) {
     auto t0 = std::chrono::steady_clock::now();
+    // the LDS limits again: another plan may have lowered them since this one
+    // was prepared
+    if ((plan->lds_small && hipFuncSetAttribute((const void *)k_env_row<false>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)plan->lds_small) != hipSuccess) ||
+        (plan->lds_big && hipFuncSetAttribute((const void *)k_env_row<true>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)plan->lds_big) != hipSuccess)) {
+        if (err) *err = "LDS size not accepted";
+        return TN_EHIP;
+    }
     for (int step = s0; step < s1 && step + 1 < plan->maxLy; ++step) {
         if (plan->lds_small)
             hipLaunchKernelGGL(k_env_row<false>, dim3(plan->n), dim3(512), plan->lds_small, stream,

@@ -613,7 +613,7 @@ k_sampler_team(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step
 
 template <int NT, bool BF16, int V>
 __global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16, V>::WPE, 8)))
-k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0, uint32_t k1,
+k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, int eval, uint32_t k0, uint32_t k1,
                      uint64_t step0, const uint64_t *__restrict__ step_base) {
     const int u0 = (int)blockIdx.x * TW * TeamCfg<NT, BF16, V>::SETS;
     int lo = 0, hi = n - 1;
@@ -623,7 +623,7 @@ k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, uint32_t k0,
         else hi = mid - 1;
     }
     const tn_samp_desc A = descs[lo];
-    team_body<NT, BF16, V>(A, u0 - A.blk0, 0, k0, k1, step0 + *step_base);
+    team_body<NT, BF16, V>(A, u0 - A.blk0, eval, k0, k1, step0 + *step_base);
 }
 
 template <int NT, bool BF16, int V>
@@ -645,7 +645,7 @@ int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 // blocks counts 16-proposal units, a whole number of teams per instance
 template <int NT, bool BF16, int V>
 int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks, int maxLx,
-                      uint64_t seed, uint64_t step0) {
+                      uint64_t seed, uint64_t step0, int eval) {
     using CF = TeamCfg<NT, BF16, V>;
     static_assert(8 % (TW * CF::SETS) == 0, "an instance's eight-unit blocks must split into teams");
     const TeamSmem T(maxLx, CF::STAGE, CF::TL, CF::PT);
@@ -654,7 +654,7 @@ int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks,
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
     hipLaunchKernelGGL(kern, dim3((blocks + TW * CF::SETS - 1) / (TW * CF::SETS)), dim3(TW * 64), T.total,
-                       ctx->stream, descs, n,
+                       ctx->stream, descs, n, eval,
                        (uint32_t)seed, (uint32_t)(seed >> 32), step0, ctx->dstep);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
@@ -673,12 +673,12 @@ int launch_variant(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq
 
 template <int NT, bool BF16>
 int launch_variant_multi(tn_ctx *ctx, int V, const tn_samp_desc *descs, int n, int blocks, int maxLx,
-                         uint64_t seed, uint64_t step0) {
+                         uint64_t seed, uint64_t step0, int eval) {
     if constexpr (NT <= 2) {
-        if (V == 1) return launch_mfma_multi<NT, BF16, 1>(ctx, descs, n, blocks, maxLx, seed, step0);
-        if (V == 2) return launch_mfma_multi<NT, BF16, 2>(ctx, descs, n, blocks, maxLx, seed, step0);
+        if (V == 1) return launch_mfma_multi<NT, BF16, 1>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
+        if (V == 2) return launch_mfma_multi<NT, BF16, 2>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
     }
-    return launch_mfma_multi<NT, BF16, 0>(ctx, descs, n, blocks, maxLx, seed, step0);
+    return launch_mfma_multi<NT, BF16, 0>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
 }
 
 template <bool BF16>
@@ -711,19 +711,19 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
 }
 
 int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp_desc *descs, int n,
-                      int blocks, int maxLx, uint64_t seed, uint64_t step0) {
+                      int blocks, int maxLx, uint64_t seed, uint64_t step0, bool eval) {
     if (blocks == 0) return TN_OK;
     if (maxLx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     if (NT < 1 || NT > 4) return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
     if (variant < 0 || variant >= tn_team_variants(NT)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     switch (NT * 2 + (bf16 ? 1 : 0)) {
-    case 2: return launch_variant_multi<1, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    case 3: return launch_variant_multi<1, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    case 4: return launch_variant_multi<2, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    case 5: return launch_variant_multi<2, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    case 6: return launch_variant_multi<3, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    case 7: return launch_variant_multi<3, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    case 8: return launch_variant_multi<4, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
-    default: return launch_variant_multi<4, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0);
+    case 2: return launch_variant_multi<1, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 3: return launch_variant_multi<1, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 4: return launch_variant_multi<2, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 5: return launch_variant_multi<2, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 6: return launch_variant_multi<3, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 7: return launch_variant_multi<3, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 8: return launch_variant_multi<4, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    default: return launch_variant_multi<4, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
     }
 }

@@ -27,6 +27,11 @@ class _Instance(ctypes.Structure):
                 ("h", ctypes.c_void_p), ("chains", ctypes.c_int)]
 
 
+class _PeriodicInstance(ctypes.Structure):
+    _fields_ = [("Jh", ctypes.c_void_p), ("Jv", ctypes.c_void_p), ("h", ctypes.c_void_p),
+                ("beta", ctypes.c_double), ("chains", ctypes.c_int)]
+
+
 class TNError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_STATUS.get(code, code)}: {msg}")
@@ -81,6 +86,10 @@ def lib():
         "tn_autotune_multi": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i)]),
         "tn_metropolis_sweeps": (i, [vp, i, i, u64, u64, vp, vp, vp]),
         "tn_link_overlap": (i, [vp, i, vp, vp, vp]),
+        "tn_periodic_setup": (i, [vp, i, i, i, i, i, i, i, vp]),
+        "tn_periodic_step": (i, [vp, u64, u64, i, i, vp, vp, vp]),
+        "tn_periodic_energy": (i, [vp, vp, vp]),
+        "tn_periodic_link_overlap": (i, [vp, i, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -97,7 +106,8 @@ def exported_symbols():
             "tn_eval_logq", "tn_mh_step", "tn_mh_accept", "tn_sample_steps", "tn_mh_run",
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
-            "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap"]
+            "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
+            "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap"]
 
 
 def _ptr(t):
@@ -320,6 +330,53 @@ class Sampler:
         b = torch.as_tensor(b, dtype=torch.int8, device=self.device).contiguous()
         q = torch.empty(a.shape[0], dtype=torch.int32, device=self.device)
         self._check(lib().tn_link_overlap(self._ctx, a.shape[0], _ptr(a), _ptr(b), _ptr(q)))
+        return q
+
+    # -- periodic boundaries by frozen lines ------------------------------
+    def periodic_setup(self, instances, Lx, Ly, wrap_x, wrap_y, D, prec=FP32):
+        """instances: dicts with Jh, Jv, h (or None), beta, chains; couplings
+        in the periodic layout of tn_periodic_setup."""
+        n = len(instances)
+        arr = (_PeriodicInstance * n)()
+        keep = []
+        for k, it in enumerate(instances):
+            Jh, Jv, h = (_dev64(it.get(x), self.device) for x in ("Jh", "Jv", "h"))
+            keep.append((Jh, Jv, h))
+            arr[k] = _PeriodicInstance(Jh.data_ptr() if Jh.numel() else None,
+                                       Jv.data_ptr() if Jv.numel() else None,
+                                       h.data_ptr() if h is not None else None,
+                                       float(it["beta"]), int(it["chains"]))
+        self._check(lib().tn_periodic_setup(self._ctx, int(Lx), int(Ly), int(bool(wrap_x)),
+                                            int(bool(wrap_y)), int(D), int(prec), n, arr))
+        self._periodic = (int(Lx), int(Ly), sum(int(it["chains"]) for it in instances))
+        return self
+
+    def periodic_step(self, spins, seed, step, cut_row, cut_col, energy=None, accepted=None):
+        """One TNMH step of every chain with the given cut; spins (int8
+        [chains][Ly][Lx] on the device) are updated in place.  Returns the
+        periodic energies and the accept flags."""
+        if spins.dtype != torch.int8 or not spins.is_contiguous() or spins.device != self.device:
+            raise ValueError("spins must be a contiguous int8 tensor on the context's device")
+        T = spins.shape[0]
+        if energy is None:
+            energy = torch.empty(T, dtype=torch.float64, device=self.device)
+        if accepted is None:
+            accepted = torch.empty(T, dtype=torch.uint8, device=self.device)
+        self._check(lib().tn_periodic_step(self._ctx, int(seed), int(step), int(cut_row), int(cut_col),
+                                           _ptr(spins), _ptr(energy), _ptr(accepted)))
+        return energy, accepted
+
+    def periodic_energy(self, spins):
+        spins = torch.as_tensor(spins, dtype=torch.int8, device=self.device).contiguous()
+        E = torch.empty(spins.shape[0], dtype=torch.float64, device=self.device)
+        self._check(lib().tn_periodic_energy(self._ctx, _ptr(spins), _ptr(E)))
+        return E
+
+    def periodic_link_overlap(self, a, b):
+        a = torch.as_tensor(a, dtype=torch.int8, device=self.device).contiguous()
+        b = torch.as_tensor(b, dtype=torch.int8, device=self.device).contiguous()
+        q = torch.empty(a.shape[0], dtype=torch.int32, device=self.device)
+        self._check(lib().tn_periodic_link_overlap(self._ctx, a.shape[0], _ptr(a), _ptr(b), _ptr(q)))
         return q
 
     def mh_accept(self, proposal, state, seed, step):

@@ -137,6 +137,30 @@ def ea_gauss_set(n=64, L=32, T=0.212, D=16, chains=30):
     return [ea_gauss(L, 1.0 / T, D, SEED + 1000 + i, chains=chains) for i in range(n)]
 
 
+def periodic_couplings(Ly, Lx, wrap_x, wrap_y, seed, gaussian=True, field_scale=0.0):
+    """Couplings of a lattice wrapped along x and/or y (Jh [Ly][Lx] when wrapped
+    along x, else [Ly][Lx-1]; Jv [Ly][Lx] when wrapped along y, else
+    [Ly-1][Lx]): iid standard Gaussian or +-1 from numpy's PCG64 stream, with
+    an optional Gaussian field."""
+    rng = np.random.default_rng(seed)
+    sh = (Ly, Lx if wrap_x else Lx - 1)
+    sv = (Ly if wrap_y else Ly - 1, Lx)
+    if gaussian:
+        Jh, Jv = rng.normal(size=sh), rng.normal(size=sv)
+    else:
+        Jh, Jv = rng.choice([-1.0, 1.0], size=sh), rng.choice([-1.0, 1.0], size=sv)
+    h = rng.normal(size=(Ly, Lx)) * field_scale if field_scale else None
+    return dict(Jh=Jh, Jv=Jv, h=h)
+
+
+def ea_gauss_torus_set(n=64, L=32, T=0.212, chains=30):
+    """n Gaussian EA instances on the L x L torus at temperature T (the
+    periodic counterpart of ea_gauss_set), seeds SEED + 2000 + i; dicts for
+    Sampler.periodic_setup."""
+    return [dict(periodic_couplings(L, L, True, True, SEED + 2000 + i), beta=1.0 / T, chains=chains)
+            for i in range(n)]
+
+
 def random_spins(chains, Ly, Lx, seed):
     """Independent uniform +-1 configurations (an easy starting distribution)."""
     rng = np.random.default_rng(seed)
