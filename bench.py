@@ -432,6 +432,69 @@ def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("t
     return out
 
 
+def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None):
+    """Equilibration test of Eq. (Delta) with periodic boundaries (Section
+    "Arbitrary boundary conditions", table of TNMH iterations on periodic
+    Gaussian spin glasses): n_inst 32x32 tori at T = 0.212, D = 16, 30 chains
+    each (15 replica pairs) from uniform random configurations; every step
+    freezes a cross (row and column) drawn uniformly at random, builds every
+    chain's open model and takes one TNMH step per chain.  Delta(t) as in
+    run_delta with the 2 L^2 bonds of the torus."""
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler, FP32
+    from workloads import ea_gauss_torus_set, random_spins, SEED
+    prec = FP32 if prec is None else prec
+    insts = ea_gauss_torus_set(n=n_inst, chains=chains)
+    L = insts[0]["Jh"].shape[0]
+    nV, nE = L * L, 2 * L * L
+    beta = insts[0]["beta"]
+    s = Sampler()
+    t0 = time.perf_counter()
+    s.periodic_setup(insts, L, L, True, True, D, prec)
+    setup_s = time.perf_counter() - t0
+    T = n_inst * chains
+    spins = torch.as_tensor(np.concatenate([random_spins(chains, L, L, SEED + 77 + k) for k in range(n_inst)]),
+                            device=s.device).contiguous()
+    E = s.periodic_energy(spins)
+    rng = np.random.default_rng(SEED + 5)
+    cut = rng.integers(0, L, size=(steps, 2))
+    log(f"[bench] periodic: {n_inst} tori x {chains} chains set up in {setup_s:.2f} s")
+
+    def delta_now(E):
+        q = s.periodic_link_overlap(spins[0::2], spins[1::2]).double().view(n_inst, chains // 2).mean(1)
+        e = E.view(n_inst, chains).mean(1)
+        return float((e / nV + beta * (nE - q) / nV).mean())
+
+    series = [delta_now(E)]
+    s.stats(reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_ms = []
+    for t in range(steps):
+        ts = time.perf_counter()
+        E, acc = s.periodic_step(spins, SEED, t, int(cut[t, 0]), int(cut[t, 1]))
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        series.append(delta_now(E))
+        if t % 10 == 9:
+            log(f"[bench] periodic step {t + 1}: Delta {series[-1]:.4f}")
+    wall = time.perf_counter() - t1
+    st = s.stats()
+    thresholds = (0.25, 0.15, 0.05, 0.025)
+    first = {str(th): next((t for t, v in enumerate(series) if v < th), None) for th in thresholds}
+    s.close()
+    out = {"workload": f"periodic_ea_gauss_torus{L}_T0.212_D{D}", "instances": n_inst, "chains": chains,
+           "chains_total": T, "steps": steps, "setup_s": setup_s, "cuts": "uniform random cross per step",
+           "delta": series, "steps_to_reach": first,
+           "acceptance": st["accepted"] / max(st["proposed"], 1),
+           "ms_per_step": wall * 1e3 / steps, "ms_per_step_median": float(np.median(step_ms)),
+           "chain_steps_per_s": T * steps / wall}
+    log(f"[bench] periodic: Delta(0) {series[0]:.3f}, Delta({steps}) {series[-1]:.4f}, steps to reach {first}, "
+        f"acceptance {out['acceptance']:.4f}, {out['ms_per_step']:.1f} ms per step")
+    return out
+
+
 def run_frustrated128(chains=1024, steps=60, warmup=20, bonds=8, fd_bonds=2):
     """128x128 fully frustrated lattice, beta = 1, D = 32: d ln Z~ / dJ and
     d ln Z~ / d beta (tn_grad), timed, beside the chain's own estimates of
@@ -538,8 +601,11 @@ def main():
                     help="MH steps per sampler launch (default: enough for two four-wave teams per CU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--periodic-steps", type=int, default=60,
+                    help="TNMH steps of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
-                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta"],
+                    choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta",
+                             "periodic"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -556,6 +622,8 @@ def main():
         elif args.workload == "delta":
             from paper_2104_13264_amd import FP64, FP32
             out = {"fp32": run_delta(prec=FP32), "fp64": run_delta(prec=FP64)}
+        elif args.workload == "periodic":
+            out = run_periodic(steps=args.periodic_steps)
         else:
             out = run_frustrated128()
         print(json.dumps(out), flush=True)

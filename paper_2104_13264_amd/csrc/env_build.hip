@@ -645,8 +645,12 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
 // One kernel per class of bond cap (the instances of the other class return
 // at once): D <= 32 with 512 threads and the work matrices in LDS, D 33-64
 // with 1024 threads (one 16-lane row per row pair of the 2 D-row SVD matrix).
+// The 512-thread kernel is held to 128 VGPRs (four waves per SIMD), so that
+// two workgroups share a compute unit when many instances build together; it
+// needs no spills for that.
 template <bool BIG>
-__global__ void __launch_bounds__(BIG ? 1024 : 512) k_env_row(const tn_env_desc *__restrict__ descs, int step) {
+__global__ void __launch_bounds__(BIG ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(BIG ? 1 : 4, 8)))
+k_env_row(const tn_env_desc *__restrict__ descs, int step) {
     extern __shared__ double lds[];
     const tn_env_desc dsc = descs[blockIdx.x];
     const int k = dsc.Ly - 1 - step;
