@@ -171,12 +171,15 @@ int tn_env_build_many(tn_ctx *const *ctxs, int n, hipStream_t stream, std::strin
 // build reported row chunk by row chunk.
 struct tn_build_plan {
     int n = 0, maxLy = 0;
-    // the two kernel classes: D <= 32 (512 threads, matrices in LDS) and
-    // D 33-64 (1024 threads); LDS bytes 0 where no instance is of the class
-    size_t lds_small = 0, lds_big = 0;
+    // the three kernel classes: D <= 16 (256 threads), D 17-32 (512 threads),
+    // both with their matrices in LDS, and D 33-64 (1024 threads); LDS bytes
+    // 0 where no instance is of the class
+    size_t lds_tiny = 0, lds_small = 0, lds_big = 0;
     tn_env_desc *dd = nullptr;
     double ms = 0.0;
 };
+// threads of the row kernel that builds an instance of bond dimension D
+__host__ __device__ constexpr int tn_env_class_threads(int D) { return D <= 16 ? 256 : (D <= 32 ? 512 : 1024); }
 int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::string *err,
                          tn_build_plan *plan);
 int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err);

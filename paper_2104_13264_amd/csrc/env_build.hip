@@ -645,20 +645,22 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
 // One kernel per class of bond cap (the instances of the other class return
 // at once): D <= 32 with 512 threads and the work matrices in LDS, D 33-64
 // with 1024 threads (one 16-lane row per row pair of the 2 D-row SVD matrix).
-// The 512-thread kernel is held to 128 VGPRs (four waves per SIMD), so that
-// two workgroups share a compute unit when many instances build together; it
-// needs no spills for that.
-template <bool BIG>
-__global__ void __launch_bounds__(BIG ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(BIG ? 1 : 4, 8)))
+// The kernels for D <= 32 are held to 128 VGPRs (four waves per SIMD), so
+// that several workgroups share a compute unit when many instances build
+// together; they need no spills for that.  D <= 16 takes 256 threads: its
+// Jacobi rounds have at most 16 row pairs, one per 16-lane row, and four of
+// its workgroups fit a compute unit's LDS.
+template <int NTH>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 1024 ? 1 : 4, 8)))
 k_env_row(const tn_env_desc *__restrict__ descs, int step) {
     extern __shared__ double lds[];
     const tn_env_desc dsc = descs[blockIdx.x];
     const int k = dsc.Ly - 1 - step;
-    if (k < 1 || (dsc.D > 32) != BIG) return;
+    if (k < 1 || tn_env_class_threads(dsc.D) != NTH) return;
     if (step == 0)   // trivial env below the last row: bond 1 everywhere
         for (int c = threadIdx.x; c <= dsc.Lx; c += blockDim.x) dsc.dims[(size_t)dsc.Ly * (dsc.Lx + 1) + c] = 1;
     mpo_apply_row(dsc, k);
-    truncate_row<!BIG>(dsc, k, lds);
+    truncate_row<NTH < 1024>(dsc, k, lds);
 }
 
 // ln <top|env_1>: row 0 (no up legs) contracted with env 1 left to right,
@@ -776,7 +778,7 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
     };
     std::vector<tn_env_desc> ds(n);
     int maxLy = 1, maxD = 1;
-    size_t lds_small = 0, lds_big = 0;   // doubles
+    size_t lds_tiny = 0, lds_small = 0, lds_big = 0;   // doubles
     for (int i = 0; i < n; ++i) {
         tn_ctx *ctx = ctxs[i];
         const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
@@ -811,7 +813,7 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
         d.counters = ctx->counters;
         maxLy = Ly > maxLy ? Ly : maxLy;
         maxD = D > maxD ? D : maxD;
-        size_t &lds_cls = D <= 32 ? lds_small : lds_big;
+        size_t &lds_cls = D <= 16 ? lds_tiny : (D <= 32 ? lds_small : lds_big);
         const size_t need = D <= 32 ? 2 * tn_qr_area(D) : tn_svd_area(D);
         lds_cls = need > lds_cls ? need : lds_cls;
     }
@@ -826,16 +828,9 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
         if (hipMemsetAsync(ctxs[i]->counters + CNT_NOCONV, 0, sizeof(unsigned long long), stream) !=
             hipSuccess)
             return fail(TN_EHIP, "counter reset failed");
-    if (lds_small && hipFuncSetAttribute((const void *)k_env_row<false>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(lds_small * sizeof(double))) != hipSuccess)
-        return fail(TN_EHIP, "LDS size not accepted");
-    if (lds_big && hipFuncSetAttribute((const void *)k_env_row<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(lds_big * sizeof(double))) != hipSuccess)
-        return fail(TN_EHIP, "LDS size not accepted");
     plan->n = n;
     plan->maxLy = maxLy;
+    plan->lds_tiny = lds_tiny * sizeof(double);
     plan->lds_small = lds_small * sizeof(double);
     plan->lds_big = lds_big * sizeof(double);
     plan->dd = dd;
@@ -845,23 +840,29 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
 
 int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, std::string *err) {
     auto t0 = std::chrono::steady_clock::now();
-    // the LDS limits again: another plan may have lowered them since this one
-    // was prepared
-    if ((plan->lds_small && hipFuncSetAttribute((const void *)k_env_row<false>,
+    // the LDS limits, set here (not when the plan is prepared): another plan
+    // may have lowered them since
+    if ((plan->lds_tiny && hipFuncSetAttribute((const void *)k_env_row<256>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)plan->lds_tiny) != hipSuccess) ||
+        (plan->lds_small && hipFuncSetAttribute((const void *)k_env_row<512>,
                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                                 (int)plan->lds_small) != hipSuccess) ||
-        (plan->lds_big && hipFuncSetAttribute((const void *)k_env_row<true>,
+        (plan->lds_big && hipFuncSetAttribute((const void *)k_env_row<1024>,
                                               hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)plan->lds_big) != hipSuccess)) {
         if (err) *err = "LDS size not accepted";
         return TN_EHIP;
     }
     for (int step = s0; step < s1 && step + 1 < plan->maxLy; ++step) {
+        if (plan->lds_tiny)
+            hipLaunchKernelGGL(k_env_row<256>, dim3(plan->n), dim3(256), plan->lds_tiny, stream,
+                               plan->dd, step);
         if (plan->lds_small)
-            hipLaunchKernelGGL(k_env_row<false>, dim3(plan->n), dim3(512), plan->lds_small, stream,
+            hipLaunchKernelGGL(k_env_row<512>, dim3(plan->n), dim3(512), plan->lds_small, stream,
                                plan->dd, step);
         if (plan->lds_big)
-            hipLaunchKernelGGL(k_env_row<true>, dim3(plan->n), dim3(1024), plan->lds_big, stream,
+            hipLaunchKernelGGL(k_env_row<1024>, dim3(plan->n), dim3(1024), plan->lds_big, stream,
                                plan->dd, step);
         if (hipGetLastError() != hipSuccess) {
             if (err) *err = "row kernel launch failed";
