@@ -432,14 +432,17 @@ def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("t
     return out
 
 
-def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None):
+def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None, cuts="random"):
     """Equilibration test of Eq. (Delta) with periodic boundaries (Section
     "Arbitrary boundary conditions", table of TNMH iterations on periodic
     Gaussian spin glasses): n_inst 32x32 tori at T = 0.212, D = 16, 30 chains
     each (15 replica pairs) from uniform random configurations; every step
     freezes a cross (row and column) drawn uniformly at random, builds every
     chain's open model and takes one TNMH step per chain.  Delta(t) as in
-    run_delta with the 2 L^2 bonds of the torus."""
+    run_delta with the 2 L^2 bonds of the torus.  cuts: "opposite" alternates
+    between two opposite crosses, (k, k) and (k + L/2, k + L/2) with k = t // 2
+    (the torus analogue of the paper's alternating opposite lines, shifted so
+    that no site stays frozen), "random" draws a uniform cross per step."""
     import numpy as np
     import torch
     from paper_2104_13264_amd import Sampler, FP32
@@ -457,8 +460,11 @@ def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None):
     spins = torch.as_tensor(np.concatenate([random_spins(chains, L, L, SEED + 77 + k) for k in range(n_inst)]),
                             device=s.device).contiguous()
     E = s.periodic_energy(spins)
-    rng = np.random.default_rng(SEED + 5)
-    cut = rng.integers(0, L, size=(steps, 2))
+    if cuts == "random":
+        cut = np.random.default_rng(SEED + 5).integers(0, L, size=(steps, 2))
+    else:
+        k = np.arange(steps) // 2 + (np.arange(steps) % 2) * (L // 2)
+        cut = np.stack([k % L, k % L], axis=1)
     log(f"[bench] periodic: {n_inst} tori x {chains} chains set up in {setup_s:.2f} s")
 
     def delta_now(E):
@@ -485,7 +491,8 @@ def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None):
     first = {str(th): next((t for t, v in enumerate(series) if v < th), None) for th in thresholds}
     s.close()
     out = {"workload": f"periodic_ea_gauss_torus{L}_T0.212_D{D}", "instances": n_inst, "chains": chains,
-           "chains_total": T, "steps": steps, "setup_s": setup_s, "cuts": "uniform random cross per step",
+           "chains_total": T, "steps": steps, "setup_s": setup_s,
+           "cuts": "uniform random cross per step" if cuts == "random" else "alternating opposite crosses",
            "delta": series, "steps_to_reach": first,
            "acceptance": st["accepted"] / max(st["proposed"], 1),
            "ms_per_step": wall * 1e3 / steps, "ms_per_step_median": float(np.median(step_ms)),
@@ -603,6 +610,8 @@ def main():
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--periodic-steps", type=int, default=60,
                     help="TNMH steps of the periodic workload")
+    ap.add_argument("--periodic-cuts", default="random", choices=["random", "opposite"],
+                    help="cut schedule of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
                     choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta",
                              "periodic"],
@@ -623,7 +632,7 @@ def main():
             from paper_2104_13264_amd import FP64, FP32
             out = {"fp32": run_delta(prec=FP32), "fp64": run_delta(prec=FP64)}
         elif args.workload == "periodic":
-            out = run_periodic(steps=args.periodic_steps)
+            out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts)
         else:
             out = run_frustrated128()
         print(json.dumps(out), flush=True)
