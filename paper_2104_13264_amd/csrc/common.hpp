@@ -191,6 +191,22 @@ int tn_env_build_finish(tn_ctx *const *ctxs, int n, tn_build_plan *plan, hipStre
 int tn_env_build_top_status(const tn_build_plan *plan, int *status, hipStream_t stream);
 int tn_env_build_device(tn_ctx *ctx, double *logZ_out);
 int tn_make_operands(tn_ctx *ctx, int prec);
+// One instance's operand build as the batched kernels see it (the buffers
+// of the instance's precision; the others NULL).
+struct tn_ops_desc {
+    int Lx, Ly, D, Dp;
+    double beta;
+    const double *Jh, *Jv, *h, *env;
+    const int *dims;
+    double *fac, *G64r, *G64c;
+    float *G32R, *G32L;
+    uint16_t *G16R, *G16L;
+};
+// after tn_make_operands has allocated the context's operand buffers
+tn_ops_desc tn_ops_desc_of(const tn_ctx *ctx, int prec);
+// The operands of n instances (device descriptors) in two launches on
+// ctx's stream; maxDp: the largest padded bond dimension among them.
+int tn_make_operands_many(tn_ctx *ctx, const tn_ops_desc *descs, int n, int maxLx, int maxLy, int maxDp);
 
 // samplers
 // One instance's batched-sampler launch as the kernel sees it.  Block blk of

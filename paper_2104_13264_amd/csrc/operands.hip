@@ -24,6 +24,8 @@
 // (1 where the bond or the field is absent).
 #include "common.hpp"
 
+#pragma clang fp contract(off)
+
 namespace {
 
 __device__ __forceinline__ uint16_t tn_bf16_rne(float f) {
@@ -33,18 +35,14 @@ __device__ __forceinline__ uint16_t tn_bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__global__ void __launch_bounds__(256)
-k_make_ops(int Lx, int Ly, int D, int Dp, double beta, const double *__restrict__ Jv,
-           const double *__restrict__ env, const int *__restrict__ dims,
-           double *__restrict__ G64r, double *__restrict__ G64c, float *__restrict__ G32R,
-           float *__restrict__ G32L, uint16_t *__restrict__ G16R, uint16_t *__restrict__ G16L) {
-    extern __shared__ double gsh[];   // [2][Dp][Dp]
-    const int c = blockIdx.x, r = blockIdx.y;
+// Operands of site (r, c) of one instance; gsh: LDS [2][Dp][Dp].
+__device__ void ops_site(const tn_ops_desc &O, int r, int c, double *gsh) {
+    const int Lx = O.Lx, Ly = O.Ly, D = O.D, Dp = O.Dp;
     const bool last = (r == Ly - 1);
-    const int Dl = last ? 1 : dims[(r + 1) * (Lx + 1) + c];
-    const int Dr = last ? 1 : dims[(r + 1) * (Lx + 1) + c + 1];
-    const double K = last ? 0.0 : beta * Jv[r * Lx + c];
-    const double *E = env + ((size_t)(r + 1) * Lx + c) * 2 * D * D;
+    const int Dl = last ? 1 : O.dims[(r + 1) * (Lx + 1) + c];
+    const int Dr = last ? 1 : O.dims[(r + 1) * (Lx + 1) + c + 1];
+    const double K = last ? 0.0 : O.beta * O.Jv[r * Lx + c];
+    const double *E = O.env + ((size_t)(r + 1) * Lx + c) * 2 * D * D;
     for (int t = threadIdx.x; t < 2 * Dp * Dp; t += blockDim.x) {
         const int s = t / (Dp * Dp), a = (t / Dp) % Dp, b = t % Dp;
         double g = 0.0;
@@ -52,53 +50,52 @@ k_make_ops(int Lx, int Ly, int D, int Dp, double beta, const double *__restrict_
             if (last)
                 g = 1.0;
             else
-                g = tn_pleg(K, s, 0) * E[a * 2 * D + b] + tn_pleg(K, s, 1) * E[a * 2 * D + D + b];
+                g = fma(tn_pleg(K, s, 0), E[a * 2 * D + b], tn_pleg(K, s, 1) * E[a * 2 * D + D + b]);
         }
         gsh[t] = g;
     }
     __syncthreads();
     const size_t site = (size_t)r * Lx + c;
-    if (G64r) {
+    if (O.G64r) {
         for (int t = threadIdx.x; t < 2 * D * D; t += blockDim.x) {
             const int s = t / (D * D), a = (t / D) % D, b = t % D;
-            G64r[site * 2 * D * D + t] = gsh[(s * Dp + a) * Dp + b];
-            G64c[site * 2 * D * D + (s * D + b) * D + a] = gsh[(s * Dp + a) * Dp + b];
+            O.G64r[site * 2 * D * D + t] = gsh[(s * Dp + a) * Dp + b];
+            O.G64c[site * 2 * D * D + (s * D + b) * D + a] = gsh[(s * Dp + a) * Dp + b];
         }
     }
     const int NT = Dp / 16;
-    if (G32R) {
+    if (O.G32R) {
         // [s][mo][mt][lane][i]: lane holds k-chunks q = 4 mt + i (i = 0..3) of
         // output block mo, 16 contiguous bytes
         for (int t = threadIdx.x; t < 2 * Dp * Dp; t += blockDim.x) {
             const int i = t & 3, lane = (t >> 2) & 63, mt = (t >> 8) % NT, mo = (t >> 8) / NT % NT;
             const int s = t / (Dp * Dp);
             const int row = 16 * mo + (lane & 15), col = 16 * mt + 4 * (lane >> 4) + i;
-            G32R[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + row) * Dp + col];
-            G32L[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + col) * Dp + row];
+            O.G32R[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + row) * Dp + col];
+            O.G32L[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + col) * Dp + row];
         }
     }
-    if (G16R) {
+    if (O.G16R) {
         // one 16x16x16 chunk per (mo, mt): lane holds 4 consecutive k values
         for (int t = threadIdx.x; t < 2 * Dp * Dp; t += blockDim.x) {
             const int i = t & 3, lane = (t >> 2) & 63, mt = (t >> 8) % NT, mo = (t >> 8) / NT % NT;
             const int s = t / (Dp * Dp);
             const int row = 16 * mo + (lane & 15), col = 16 * mt + 4 * (lane >> 4) + i;
-            G16R[site * 2 * Dp * Dp + t] = tn_bf16_rne((float)gsh[(s * Dp + row) * Dp + col]);
-            G16L[site * 2 * Dp * Dp + t] = tn_bf16_rne((float)gsh[(s * Dp + col) * Dp + row]);
+            O.G16R[site * 2 * Dp * Dp + t] = tn_bf16_rne((float)gsh[(s * Dp + row) * Dp + col]);
+            O.G16L[site * 2 * Dp * Dp + t] = tn_bf16_rne((float)gsh[(s * Dp + col) * Dp + row]);
         }
     }
 }
 
-__global__ void k_make_factors(int Lx, int Ly, double beta, const double *__restrict__ Jh,
-                               const double *__restrict__ Jv, const double *__restrict__ h,
-                               double *__restrict__ fac) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Lx * Ly) return;
+// Boltzmann factors of site t = r Lx + c of one instance.
+__device__ void factor_site(const tn_ops_desc &O, int t) {
+    const int Lx = O.Lx;
     const int r = t / Lx, c = t % Lx;
-    const double ah = h ? beta * h[t] : 0.0;
-    const double av = r > 0 ? beta * Jv[(r - 1) * Lx + c] : 0.0;
-    const double aj = c > 0 ? beta * Jh[r * (Lx - 1) + c - 1] : 0.0;
-    double *f = fac + (size_t)t * 6;
+    const double beta = O.beta;
+    const double ah = O.h ? beta * O.h[t] : 0.0;
+    const double av = r > 0 ? beta * O.Jv[(r - 1) * Lx + c] : 0.0;
+    const double aj = c > 0 ? beta * O.Jh[r * (Lx - 1) + c - 1] : 0.0;
+    double *f = O.fac + (size_t)t * 6;
     f[0] = exp(ah);
     f[1] = exp(-ah);
     f[2] = exp(av);
@@ -107,9 +104,53 @@ __global__ void k_make_factors(int Lx, int Ly, double beta, const double *__rest
     f[5] = exp(-aj);
 }
 
+__global__ void __launch_bounds__(256) k_make_ops(tn_ops_desc O) {
+    extern __shared__ double gsh[];   // [2][Dp][Dp]
+    ops_site(O, blockIdx.y, blockIdx.x, gsh);
+}
+
+// Instance blockIdx.z of n; the grid covers the widest and tallest lattice.
+__global__ void __launch_bounds__(256) k_make_ops_many(const tn_ops_desc *__restrict__ descs) {
+    extern __shared__ double gsh[];
+    const tn_ops_desc O = descs[blockIdx.z];
+    if ((int)blockIdx.x >= O.Lx || (int)blockIdx.y >= O.Ly) return;
+    ops_site(O, blockIdx.y, blockIdx.x, gsh);
+}
+
+__global__ void __launch_bounds__(256) k_make_factors(tn_ops_desc O) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < O.Lx * O.Ly) factor_site(O, t);
+}
+
+__global__ void __launch_bounds__(256) k_make_factors_many(const tn_ops_desc *__restrict__ descs) {
+    const tn_ops_desc O = descs[blockIdx.y];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < O.Lx * O.Ly) factor_site(O, t);
+}
+
 }  // namespace
 
-int tn_make_factors(tn_ctx *ctx, double *fac);
+tn_ops_desc tn_ops_desc_of(const tn_ctx *ctx, int prec) {
+    tn_ops_desc O;
+    O.Lx = ctx->Lx;
+    O.Ly = ctx->Ly;
+    O.D = ctx->D;
+    O.Dp = ((ctx->D + 15) / 16) * 16;
+    O.beta = ctx->beta;
+    O.Jh = ctx->Jh;
+    O.Jv = ctx->Jv;
+    O.h = ctx->h;
+    O.env = ctx->env;
+    O.dims = ctx->dims;
+    O.fac = ctx->fac;
+    O.G64r = prec == TN_FP64 ? ctx->G64r : nullptr;
+    O.G64c = prec == TN_FP64 ? ctx->G64c : nullptr;
+    O.G32R = prec == TN_FP32 ? ctx->G32R : nullptr;
+    O.G32L = prec == TN_FP32 ? ctx->G32L : nullptr;
+    O.G16R = prec == TN_BF16 ? ctx->G16R : nullptr;
+    O.G16L = prec == TN_BF16 ? ctx->G16L : nullptr;
+    return O;
+}
 
 int tn_make_operands(tn_ctx *ctx, int prec) {
     const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
@@ -119,46 +160,46 @@ int tn_make_operands(tn_ctx *ctx, int prec) {
     const size_t sites = (size_t)Lx * Ly;
     if ((rc = tn_ensure(ctx, (void **)&ctx->fac, &ctx->fac_cap, sites * 6 * sizeof(double))))
         return rc;
-    if ((rc = tn_make_factors(ctx, ctx->fac))) return rc;
-    double *G64r = nullptr, *G64c = nullptr;
-    float *G32R = nullptr, *G32L = nullptr;
-    uint16_t *G16R = nullptr, *G16L = nullptr;
     if (prec == TN_FP64) {
         const size_t n = sites * 2 * D * D;
         if ((rc = tn_ensure(ctx, (void **)&ctx->G64r, &ctx->ops_cap64, 2 * n * sizeof(double))))
             return rc;
         ctx->G64c = ctx->G64r + n;
-        G64r = ctx->G64r;
-        G64c = ctx->G64c;
     } else if (prec == TN_FP32) {
         const size_t n = sites * 2 * Dp * Dp;
         if ((rc = tn_ensure(ctx, (void **)&ctx->G32R, &ctx->ops_cap32, 2 * n * sizeof(float))))
             return rc;
         ctx->G32L = ctx->G32R + n;
-        G32R = ctx->G32R;
-        G32L = ctx->G32L;
     } else {
         const size_t n = sites * 2 * Dp * Dp;
         if ((rc = tn_ensure(ctx, (void **)&ctx->G16R, &ctx->ops_cap16, 2 * n * sizeof(uint16_t))))
             return rc;
         ctx->G16L = ctx->G16R + n;
-        G16R = ctx->G16R;
-        G16L = ctx->G16L;
     }
+    const tn_ops_desc O = tn_ops_desc_of(ctx, prec);
+    hipLaunchKernelGGL(k_make_factors, dim3((unsigned)((sites + 255) / 256)), dim3(256), 0, ctx->stream, O);
+    TN_HIP(ctx, hipGetLastError());
     const size_t lds = (size_t)2 * Dp * Dp * sizeof(double);
     TN_HIP(ctx, hipFuncSetAttribute((const void *)k_make_ops,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_make_ops, dim3(Lx, Ly), dim3(256), lds, ctx->stream, Lx, Ly, D, Dp,
-                       ctx->beta, ctx->Jv, ctx->env, ctx->dims, G64r, G64c, G32R, G32L, G16R,
-                       G16L);
+    hipLaunchKernelGGL(k_make_ops, dim3(Lx, Ly), dim3(256), lds, ctx->stream, O);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
 }
 
-int tn_make_factors(tn_ctx *ctx, double *fac) {
-    const int n = ctx->Lx * ctx->Ly;
-    hipLaunchKernelGGL(k_make_factors, dim3((n + 255) / 256), dim3(256), 0, ctx->stream,
-                       ctx->Lx, ctx->Ly, ctx->beta, ctx->Jh, ctx->Jv, ctx->h, fac);
-    TN_HIP(ctx, hipGetLastError());
+int tn_make_operands_many(tn_ctx *ctx, const tn_ops_desc *descs, int n, int maxLx, int maxLy, int maxDp) {
+    if (n <= 0) return TN_OK;
+    const size_t sites = (size_t)maxLx * maxLy;
+    const size_t lds = (size_t)2 * maxDp * maxDp * sizeof(double);
+    TN_HIP(ctx, hipFuncSetAttribute((const void *)k_make_ops_many,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    constexpr int CHUNK = 32768;   // instances per launch (grid y / z limit)
+    for (int base = 0; base < n; base += CHUNK) {
+        const int m = n - base < CHUNK ? n - base : CHUNK;
+        hipLaunchKernelGGL(k_make_factors_many, dim3((unsigned)((sites + 255) / 256), m), dim3(256), 0,
+                           ctx->stream, descs + base);
+        hipLaunchKernelGGL(k_make_ops_many, dim3(maxLx, maxLy, m), dim3(256), lds, ctx->stream, descs + base);
+        TN_HIP(ctx, hipGetLastError());
+    }
     return TN_OK;
 }

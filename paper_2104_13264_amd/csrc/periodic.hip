@@ -12,7 +12,8 @@
 //              its open couplings (the site map and field order of tnmh.h)
 //   row steps  the batched environment build of every chain (env_build.hip)
 //   status     top overlaps and each build's outcome, one copy to the host
-//   operands   the sampler operands of every chain (operands.hip)
+//   operands   the sampler operands of every chain, one batched launch pair
+//              (operands.hip)
 //   eval       ln q and E of the current free spins under the new cut
 //   sample     one proposal per chain (id j, instance m)
 //   accept     Eq. (mh-acc) per chain with the open model's ln q and energies
@@ -54,8 +55,9 @@ struct tn_periodic {
     size_t gscr_per = 0;
     tn_samp_desc *sd_eval = nullptr, *sd_samp = nullptr;   // [total] each
     tn_acc_desc *ad = nullptr;    // [instances with chains]
+    tn_ops_desc *od = nullptr;    // [total]: every chain's operand build
     int nacc = 0;
-    bool descs_ready = false;
+    bool descs_ready = false, ops_ready = false;
     tn_build_plan plan;
     std::vector<int> hstatus;
 };
@@ -289,6 +291,7 @@ int tn_periodic_setup(tn_ctx *ctx, int Lx, int Ly, int wrap_x, int wrap_y, int D
     const size_t o_q = take((size_t)4 * T * sizeof(double)), o_acc = take(T), o_st = take(T * sizeof(int));
     const size_t o_gs = prec == TN_FP64 ? take(0) : take((size_t)T * P->gscr_per * sizeof(float));
     const size_t o_sd = take((size_t)2 * T * sizeof(tn_samp_desc)), o_ad = take((size_t)n * sizeof(tn_acc_desc));
+    const size_t o_od = take((size_t)T * sizeof(tn_ops_desc));
     const size_t o_small = take((size_t)T * small);
     if (hipMalloc(&P->arena, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -313,6 +316,7 @@ int tn_periodic_setup(tn_ctx *ctx, int Lx, int Ly, int wrap_x, int wrap_y, int D
     P->sd_eval = (tn_samp_desc *)(A + o_sd);
     P->sd_samp = P->sd_eval + T;
     P->ad = (tn_acc_desc *)(A + o_ad);
+    P->od = (tn_ops_desc *)(A + o_od);
     int rc = TN_OK;
     auto bail = [&](int code, const std::string &msg) {
         tn_periodic_free(ctx);
@@ -410,8 +414,17 @@ int tn_periodic_step(tn_ctx *ctx, uint64_t seed, uint64_t step, int cut_row, int
                            std::string(P->hstatus[g] == 2 ? "Jacobi SVD did not converge"
                                                           : "approximate partition function is not positive") +
                                " for chain " + std::to_string(g) + " under this cut");
-    for (tn_ctx *k : P->kids)
-        if ((rc = tn_make_operands(k, P->prec))) return tn_fail(ctx, rc, k->err);
+    if (!P->ops_ready) {   // first step: allocates every chain's operand buffers
+        std::vector<tn_ops_desc> od(T);
+        for (int g = 0; g < T; ++g) {
+            if ((rc = tn_make_operands(P->kids[g], P->prec))) return tn_fail(ctx, rc, P->kids[g]->err);
+            od[g] = tn_ops_desc_of(P->kids[g], P->prec);
+        }
+        TN_HIP(ctx, hipMemcpy(P->od, od.data(), T * sizeof(tn_ops_desc), hipMemcpyHostToDevice));
+        P->ops_ready = true;
+    } else if ((rc = tn_make_operands_many(ctx, P->od, T, P->Lxo, P->Lyo, ((P->D + 15) / 16) * 16))) {
+        return rc;
+    }
     if (P->prec == TN_FP64) {
         // one plain-sampler launch per chain for the current state and one for
         // the proposal; the chain's sampler counts go to this context

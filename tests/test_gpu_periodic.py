@@ -5,7 +5,7 @@ oracle.
   of uneven chain counts, with and without fields, follow the oracle's chains
   step by step: spins and accept flags bitwise (draws within ~1e-15 of a
   threshold could differ; none is expected), periodic energies to 1e-12.
-* FP32 / BF16: one step of every chain equals what the open-boundary entry
+* FP32 / BF16: two steps of every chain equal what the open-boundary entry
   points give on the chain's open model (couplings and fields from the
   oracle's cut, built by tn_build_env; proposal id j and instance m; the
   oracle's acceptance rule on their ln q and energies), bitwise, also on a
@@ -120,27 +120,31 @@ def test_batched_step_equals_open_contexts(case):
     s = Sampler()
     s.periodic_setup(inst, Lx, Ly, wx, wy, D, prec)
     spins = torch.as_tensor(s0, device=s.device).contiguous()
-    seed, t = 31 + case, 5
-    cr, cc = cuts(case, Ly, Lx)
-    E, acc = s.periodic_step(spins, seed, t, cr, cc)
-    got = spins.cpu().numpy()
-    acc = acc.cpu().numpy()
-    if wx:
-        np.testing.assert_array_equal(got[:, :, cc], s0[:, :, cc])
-    if wy:
-        np.testing.assert_array_equal(got[:, cr, :], s0[:, cr, :])
-    g0 = 0
-    for m, C in enumerate(chains):
-        np.testing.assert_allclose(
-            E.cpu().numpy()[g0:g0 + C],
-            periodic.energy(got[g0:g0 + C], inst[m]["Jh"], inst[m]["Jv"], inst[m].get("h"), wx, wy),
-            rtol=1e-13, atol=1e-12)
-        for j in (check if check is not None else range(C)):
-            want, ok = open_context_step(inst, s0[g0 + j], m, j, seed, t, cr, cc, D, prec, wx, wy)
-            assert bool(acc[g0 + j]) == ok, (m, j)
-            np.testing.assert_array_equal(got[g0 + j], want, err_msg=f"instance {m} chain {j}")
-        g0 += C
-    assert 0 < acc.sum()
+    seed = 31 + case
+    # two steps: the first builds every chain's operands one chain at a time
+    # (allocating them), later steps in one batched launch pair
+    for t in (5, 6):
+        before = spins.cpu().numpy()
+        cr, cc = cuts(case + t, Ly, Lx)
+        E, acc = s.periodic_step(spins, seed, t, cr, cc)
+        got = spins.cpu().numpy()
+        acc = acc.cpu().numpy()
+        if wx:
+            np.testing.assert_array_equal(got[:, :, cc], before[:, :, cc])
+        if wy:
+            np.testing.assert_array_equal(got[:, cr, :], before[:, cr, :])
+        g0 = 0
+        for m, C in enumerate(chains):
+            np.testing.assert_allclose(
+                E.cpu().numpy()[g0:g0 + C],
+                periodic.energy(got[g0:g0 + C], inst[m]["Jh"], inst[m]["Jv"], inst[m].get("h"), wx, wy),
+                rtol=1e-13, atol=1e-12)
+            for j in (check if check is not None else range(C)):
+                want, ok = open_context_step(inst, before[g0 + j], m, j, seed, t, cr, cc, D, prec, wx, wy)
+                assert bool(acc[g0 + j]) == ok, (t, m, j)
+                np.testing.assert_array_equal(got[g0 + j], want, err_msg=f"step {t} instance {m} chain {j}")
+            g0 += C
+        assert 0 < acc.sum()
     s.close()
 
 
