@@ -16,6 +16,18 @@ Readings adopted (the paper gives no more detail):
     the left neighbour.  Each stored env is right-orthonormal with its centre
     at column 0 and unit norm; the removed norms give ell_k.
   * ln Z~ = sum_k ell_k + ln <top|env_1>.
+  * Two-site variational compression (the alternative App. A names for the
+    Gaussian-disorder runs, after Schollwoeck's review): starting from the
+    successive-SVD result, sweeps of two-site updates fit the bond-D MPS psi
+    to the normalised product X^ (the left-canonical output of the QR sweep):
+    with the blocks of psi left and right of sites (c, c+1) orthonormal, the
+    two-site tensor that minimises ||X^ - psi|| is the contraction
+    Theta = L_c X^_c X^_{c+1} R_{c+2} of X^ with those blocks; its SVD,
+    truncated to D, gives the new psi_c, psi_{c+1} (left-canonical psi_c on a
+    left-to-right pass, right-canonical psi_{c+1} on a right-to-left pass).
+    One sweep is a left-to-right and a right-to-left pass; after the last one
+    psi is right-orthonormal with its centre at column 0, and
+    ell_k = ln ||X|| (removed by the QR sweep) + ln ||psi||.
 
 Each env tensor is stored as E[a, u, b] (left bond, physical leg, right bond).
 
@@ -44,13 +56,9 @@ def apply_row(model, k, env_below):
     return X
 
 
-def compress(X, D):
-    """Successive-SVD compression of an MPS to bond D (App. A; reading above).
-
-    Returns (tensors, ln of the removed norm, list of truncated bonds).  A bond
-    c (between columns c-1 and c) is "truncated" when chi < min(rows, cols) of
-    the SVD taken at column c.
-    """
+def qr_sweep(X):
+    """Left-to-right QR sweep: X becomes left-canonical with a unit-norm last
+    tensor; returns (tensors, ln of the removed norm)."""
     X = [x.copy() for x in X]
     Lx = len(X)
     # left-to-right QR sweep: X_c <- Q, X_{c+1} <- R X_{c+1}; the carried
@@ -69,6 +77,18 @@ def compress(X, D):
     n = np.linalg.norm(X[Lx - 1])
     X[Lx - 1] = X[Lx - 1] / n
     lognorm += np.log(n)
+    return X, lognorm
+
+
+def compress(X, D):
+    """Successive-SVD compression of an MPS to bond D (App. A; reading above).
+
+    Returns (tensors, ln of the removed norm, list of truncated bonds).  A bond
+    c (between columns c-1 and c) is "truncated" when chi < min(rows, cols) of
+    the SVD taken at column c.
+    """
+    X, lognorm = qr_sweep(X)
+    Lx = len(X)
     truncated = []
     # right-to-left SVD sweep with truncation to D
     for c in range(Lx - 1, 0, -1):
@@ -82,6 +102,65 @@ def compress(X, D):
     m = np.linalg.norm(X[0])
     X[0] = X[0] / m
     return X, lognorm + np.log(m), truncated
+
+
+def fit_two_site(Xh, psi, D, sweeps):
+    """Two-site variational sweeps fitting psi (right-canonical, centre at
+    column 0) to Xh; returns the fitted, unnormalised psi (right-canonical,
+    centre at column 0)."""
+    Lx = len(Xh)
+    psi = [p.copy() for p in psi]
+    if Lx == 1:                       # one site: the fit is Xh itself
+        return [Xh[0].copy()]
+    one = np.ones((1, 1))
+
+    def right_env(c, R):              # R_c[b_psi, B] from R_{c+1}
+        return np.einsum('aub,AuB,bB->aA', psi[c], Xh[c], R)
+
+    def left_env(c, L):               # L_{c+1}[a_psi, A] from L_c
+        return np.einsum('aub,aA,AuB->bB', psi[c], L, Xh[c])
+
+    for _ in range(sweeps):
+        R = [None] * (Lx + 1)
+        R[Lx] = one
+        for c in range(Lx - 1, 1, -1):
+            R[c] = right_env(c, R[c + 1])
+        L = one
+        for c in range(Lx - 1):       # left to right
+            Th = np.einsum('aA,AuM,MvB,bB->aubv', L, Xh[c], Xh[c + 1], R[c + 2])
+            a, u, b, v = Th.shape
+            U, S, Vt = np.linalg.svd(Th.transpose(0, 1, 3, 2).reshape(a * u, v * b), full_matrices=False)
+            chi = min(D, S.shape[0])
+            psi[c] = U[:, :chi].reshape(a, u, chi)
+            psi[c + 1] = (S[:chi, None] * Vt[:chi]).reshape(chi, v, b)
+            L = left_env(c, L)
+        Ls = [None] * Lx
+        Ls[0] = one
+        for c in range(Lx - 2):
+            Ls[c + 1] = left_env(c, Ls[c])
+        R = one
+        for c in range(Lx - 2, -1, -1):   # right to left
+            Th = np.einsum('aA,AuM,MvB,bB->aubv', Ls[c], Xh[c], Xh[c + 1], R)
+            a, u, b, v = Th.shape
+            U, S, Vt = np.linalg.svd(Th.transpose(0, 1, 3, 2).reshape(a * u, v * b), full_matrices=False)
+            chi = min(D, S.shape[0])
+            psi[c + 1] = Vt[:chi].reshape(chi, v, b)
+            psi[c] = (U[:, :chi] * S[:chi]).reshape(a, u, chi)
+            R = right_env(c + 1, R)
+    return psi
+
+
+def compress_variational(X, D, sweeps):
+    """Successive SVD followed by `sweeps` two-site variational sweeps (reading
+    above).  Returns (tensors, ln of the removed norm, truncated bonds of the
+    successive-SVD start)."""
+    Xh, lognorm = qr_sweep(X)
+    psi, lm, truncated = compress(Xh, D)
+    psi[0] = psi[0] * np.exp(lm)      # Xh ~ psi with the norm in the centre
+    psi = fit_two_site(Xh, psi, D, sweeps)
+    m = np.linalg.norm(psi[0])
+    psi[0] = psi[0] / m
+    return psi, lognorm + np.log(m), truncated
 
 
 def row_overlap(model, r, env_below):
@@ -100,8 +179,9 @@ def row_overlap(model, r, env_below):
     return logscale + np.log(abs(val)), np.sign(val)
 
 
-def build_envs(model, D):
-    """Bottom-up boundary-MPS environments and ln Z~.
+def build_envs(model, D, fit_sweeps=0):
+    """Bottom-up boundary-MPS environments and ln Z~ (fit_sweeps > 0: each
+    compression is refined by that many two-site variational sweeps).
 
     Returns a dict with
         env[k]   list over columns of E[a,u,b], k = 1..Ly (env[Ly] trivial)
@@ -117,7 +197,10 @@ def build_envs(model, D):
     env[Ly] = trivial_env(Lx)
     for k in range(Ly - 1, 0, -1):
         X = apply_row(model, k, env[k + 1])
-        env[k], ell[k], trunc[k] = compress(X, D)
+        if fit_sweeps > 0:
+            env[k], ell[k], trunc[k] = compress_variational(X, D, fit_sweeps)
+        else:
+            env[k], ell[k], trunc[k] = compress(X, D)
     lo, sign = row_overlap(model, 0, env[1])
     return dict(env=env, ell=ell, trunc=trunc, logZ=ell.sum() + lo, sign=sign,
                 D=D)
