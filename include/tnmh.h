@@ -117,6 +117,23 @@ int tn_set_precision(tn_ctx *ctx, int prec);
 /* Instance tag written into the Philox counter (inst << 2 | stream); 0..2^29-1. */
 int tn_set_instance(tn_ctx *ctx, int inst);
 
+/* Compression of the later builds on this context (tn_build_env, the
+ * incremental build, tn_build_env_multi, tn_periodic_setup).  App. A names two
+ * schemes: successive SVD (fit_sweeps = 0, the default) and two-site
+ * variational compression, used there for the Gaussian-disorder runs.  With
+ * fit_sweeps = n in 1..16 every row is first compressed by successive SVD,
+ * then n sweeps (each a left-to-right and a right-to-left pass) of two-site
+ * updates fit the bond-D MPS to the normalised MPO-MPS product: with the
+ * blocks left and right of a bond orthonormal, the two-site tensor is the
+ * product contracted with those blocks, split by an SVD truncated to D.  The
+ * stored env is right-orthonormal with its centre at column 0 as before and
+ * ell_k = ln of the product's norm removed by the QR sweep + ln |fit|.
+ * Supported for D <= 32 (a build with larger D fails with TN_EINVAL).  The
+ * frozen-truncation derivative tn_grad is defined for successive-SVD builds
+ * only (TN_ESTATE after a fitted build); tn_grad_two_sided works with either.
+ * Errors: TN_EINVAL for fit_sweeps outside 0..16. */
+int tn_set_compression(tn_ctx *ctx, int fit_sweeps);
+
 /* Draw `batch` independent proposals by the sequential Bayes chain rule
  * (Sec. 2, Eqs. bayes, pi-approx; App. A Eq. proba-ratio-apx), row-major
  * site order, each conditional normalised over s in {+1,-1} from the same

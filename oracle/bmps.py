@@ -115,10 +115,15 @@ def fit_two_site(Xh, psi, D, sweeps):
     one = np.ones((1, 1))
 
     def right_env(c, R):              # R_c[b_psi, B] from R_{c+1}
-        return np.einsum('aub,AuB,bB->aA', psi[c], Xh[c], R)
+        return np.einsum('aub,Aub->aA', psi[c], np.einsum('AuB,bB->Aub', Xh[c], R))
 
     def left_env(c, L):               # L_{c+1}[a_psi, A] from L_c
-        return np.einsum('aub,aA,AuB->bB', psi[c], L, Xh[c])
+        return np.einsum('aub,auB->bB', psi[c], np.einsum('aA,AuB->auB', L, Xh[c]))
+
+    def theta(L, c, R):               # Theta[a, u, b, v] = L X^_c X^_{c+1} R, pair by pair
+        t = np.einsum('aA,AuM->auM', L, Xh[c])
+        t = np.einsum('auM,MvB->auvB', t, Xh[c + 1])
+        return np.einsum('auvB,bB->aubv', t, R)
 
     for _ in range(sweeps):
         R = [None] * (Lx + 1)
@@ -127,7 +132,7 @@ def fit_two_site(Xh, psi, D, sweeps):
             R[c] = right_env(c, R[c + 1])
         L = one
         for c in range(Lx - 1):       # left to right
-            Th = np.einsum('aA,AuM,MvB,bB->aubv', L, Xh[c], Xh[c + 1], R[c + 2])
+            Th = theta(L, c, R[c + 2])
             a, u, b, v = Th.shape
             U, S, Vt = np.linalg.svd(Th.transpose(0, 1, 3, 2).reshape(a * u, v * b), full_matrices=False)
             chi = min(D, S.shape[0])
@@ -140,7 +145,7 @@ def fit_two_site(Xh, psi, D, sweeps):
             Ls[c + 1] = left_env(c, Ls[c])
         R = one
         for c in range(Lx - 2, -1, -1):   # right to left
-            Th = np.einsum('aA,AuM,MvB,bB->aubv', Ls[c], Xh[c], Xh[c + 1], R)
+            Th = theta(Ls[c], c, R)
             a, u, b, v = Th.shape
             U, S, Vt = np.linalg.svd(Th.transpose(0, 1, 3, 2).reshape(a * u, v * b), full_matrices=False)
             chi = min(D, S.shape[0])

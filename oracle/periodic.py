@@ -138,12 +138,13 @@ def frozen_key(spins, cut_row, cut_col, wrap_x, wrap_y):
     return b"".join(p.tobytes() for p in parts)
 
 
-def step(instances, spins, seed, t, cut_row, cut_col, D, wrap_x, wrap_y):
+def step(instances, spins, seed, t, cut_row, cut_col, D, wrap_x, wrap_y, fit_sweeps=0):
     """One TNMH step with the given cut for every chain.
 
     instances: list of dicts (Jh, Jv, h or None, beta, chains); spins
     [sum chains][Ly][Lx] int8, chains of instance 0 first.  Returns the new
-    spins, their periodic energies and the accept flags.
+    spins, their periodic energies and the accept flags.  fit_sweeps: the
+    compression of the environment builds (oracle.bmps.build_envs).
     """
     spins = np.array(spins, dtype=np.int8)
     out = spins.copy()
@@ -159,7 +160,7 @@ def step(instances, spins, seed, t, cut_row, cut_col, D, wrap_x, wrap_y):
         for js in groups.values():
             model, rows, cols = cut_model(it["Jh"], it["Jv"], it.get("h"), it["beta"], spins[g0 + js[0]],
                                           cut_row, cut_col, wrap_x, wrap_y)
-            envs = build_envs(model, D)
+            envs = build_envs(model, D, fit_sweeps)
             cur = spins[g0 + np.array(js)][:, rows][:, :, cols]
             ev = eval_logq(model, envs, cur)
             prop = sample(model, envs, len(js), seed, step=t, inst=m, ids=np.array(js))

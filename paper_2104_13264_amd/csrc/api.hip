@@ -94,7 +94,7 @@ void free_all(tn_ctx *ctx) {
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
                     ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters,
-                    ctx->cst,   ctx->gradscr, ctx->descs,
+                    ctx->cst,   ctx->gradscr, ctx->descs, ctx->fbuf,
                     ctx->own_dstep ? (void *)ctx->dstep : nullptr};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
@@ -224,7 +224,7 @@ int tn_build_env(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv
     if ((rc = tn_env_build_device(ctx, &lz))) return rc;
     if ((rc = tn_make_operands(ctx, prec))) return rc;
     ctx->has_env = true;
-    ctx->has_cst = true;
+    ctx->has_cst = ctx->fit_sweeps == 0;   // the frozen derivative needs SVD cuts
     if (logZ_out) {
         TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
         *logZ_out = lz;
@@ -286,7 +286,7 @@ int tn_build_env_end(tn_ctx *ctx, double *logZ_out) {
         return tn_fail(ctx, rc, e);
     if ((rc = tn_make_operands(ctx, ctx->prec))) return rc;
     ctx->has_env = true;
-    ctx->has_cst = true;
+    ctx->has_cst = ctx->fit_sweeps == 0;   // the frozen derivative needs SVD cuts
     if (logZ_out) *logZ_out = ctx->logZ;
     return TN_OK;
 }
@@ -358,6 +358,15 @@ int tn_set_precision(tn_ctx *ctx, int prec) {
     if ((rc = check_prec(ctx, prec))) return rc;
     if ((rc = tn_make_operands(ctx, prec))) return rc;
     ctx->prec = prec;
+    return TN_OK;
+}
+
+int tn_set_compression(tn_ctx *ctx, int fit_sweeps) {
+    (void)hipGetLastError();
+    if (!ctx) return TN_EINVAL;
+    ctx->err.clear();
+    if (fit_sweeps < 0 || fit_sweeps > 16) return tn_fail(ctx, TN_EINVAL, "fit_sweeps must be in 0..16");
+    ctx->fit_sweeps = fit_sweeps;
     return TN_OK;
 }
 
@@ -580,6 +589,7 @@ int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, do
         if ((rc = set_instance(k, I.Lx, I.Ly, I.Jh, I.Jv, I.h, I.beta, I.D, prec)))
             return tn_fail(ctx, rc, "instance " + std::to_string(i) + ": " + k->err);
         k->inst = i;
+        k->fit_sweeps = ctx->fit_sweeps;
         ctx->kid_chains[i] = I.chains;
     }
     std::string e;
@@ -589,7 +599,7 @@ int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, do
         if ((rc = tn_make_operands(k, prec)))
             return tn_fail(ctx, rc, "instance " + std::to_string(i) + ": " + k->err);
         k->has_env = true;
-        k->has_cst = true;
+        k->has_cst = k->fit_sweeps == 0;
         if (logZ_out) logZ_out[i] = k->logZ;
     }
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -805,6 +815,7 @@ int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
         }
         tn_ctx *f = ctx->flip;
         f->err.clear();
+        f->fit_sweeps = ctx->fit_sweeps;   // the same compression top-down
         rc = set_instance(f, Lx, Ly, nh ? fJh.data() : nullptr, nv ? fJv.data() : nullptr,
                           ctx->h ? fh.data() : nullptr, ctx->beta, ctx->D, TN_FP64);
         if (rc == TN_OK) rc = tn_env_build_device(f, nullptr);

@@ -75,6 +75,12 @@ struct tn_ctx {
     double *fac = nullptr;
     size_t fac_cap = 0;
 
+    // compression: 0 successive SVD; n > 0 followed by n two-site variational
+    // sweeps (tn_set_compression), with their scratch
+    int fit_sweeps = 0;
+    double *fbuf = nullptr;
+    size_t fbuf_cap = 0;
+
     // environment-build scratch
     double *xbox = nullptr;   // [Lx][2D][2][2D]
     double *wbuf = nullptr;   // global work buffers when LDS is too small
@@ -150,7 +156,7 @@ int tn_ensure(tn_ctx *ctx, void **ptr, size_t *cap, size_t bytes);
 // environment build (env_build.hip)
 // One instance's environment build as the row kernels see it (device copy).
 struct tn_env_desc {
-    int Lx, Ly, D, pad;
+    int Lx, Ly, D, fit;   // fit: two-site variational sweeps after the SVD sweep
     double beta;
     const double *Jh, *Jv, *h;
     double *env;
@@ -162,6 +168,7 @@ struct tn_env_desc {
     double *wbuf;
     double *scal;
     unsigned long long *counters;
+    double *fbuf;         // the variational sweeps' scratch (fit > 0)
 };
 // Builds the environments of n instances together (one workgroup per
 // instance and row step); fills each ctx's logZ.  ctxs[i] must have its
@@ -175,6 +182,8 @@ struct tn_build_plan {
     // both with their matrices in LDS, and D 33-64 (1024 threads); LDS bytes
     // 0 where no instance is of the class
     size_t lds_tiny = 0, lds_small = 0, lds_big = 0;
+    // the variational sweeps' kernel (0: no instance fits)
+    size_t lds_fit = 0;
     tn_env_desc *dd = nullptr;
     double ms = 0.0;
 };

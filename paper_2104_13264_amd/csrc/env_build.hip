@@ -422,6 +422,38 @@ __host__ __device__ constexpr size_t tn_qr_area(int D) {
                                                             : 2 * tn_svd_area(D);
 }
 
+// Scratch of the two-site variational sweeps, in doubles: [0] ln of the norm
+// the QR sweep removed; xh the normalised product X^ (left-canonical boxes of
+// xbox); ps the fitted MPS psi (same boxes); re / ls the right / left
+// overlaps of psi with X^ per column ([chi][A], row stride 2 D); t1, t2, th
+// the intermediate products of one two-site tensor.
+struct FitLayout {
+    size_t xh, ps, re, ls, t1, t2, th, total;
+};
+__host__ __device__ inline FitLayout fit_layout(int Lx, int D) {
+    const size_t box = (size_t)8 * D * D, m2 = (size_t)2 * D * D;
+    FitLayout f;
+    size_t o = 8;
+    f.xh = o;
+    o += (size_t)Lx * box;
+    f.ps = o;
+    o += (size_t)Lx * box;
+    f.re = o;
+    o += (size_t)(Lx + 1) * m2;
+    f.ls = o;
+    o += (size_t)(Lx + 1) * m2;
+    f.t1 = o;
+    o += (size_t)4 * D * D;
+    f.t2 = o;
+    o += (size_t)8 * D * D;
+    f.th = o;
+    o += (size_t)4 * D * D;
+    f.total = o;
+    return f;
+}
+// the bond dimensions of X^ are kept in xdims from this offset (ints)
+constexpr int FIT_DIMS = 1024;
+
 // Compress the MPO-MPS product of row k held in xbox and store env k.
 // Work areas (doubles): QA [8 D^2 + 4 D] the QR matrix, later the SVD matrix
 // W and a copy of it; QB (same size) Q, then the staged right neighbour,
@@ -525,6 +557,13 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
             X[r * ld + j] *= inv;
         }
         lognorm += log(nrm);
+        __syncthreads();
+    }
+    if (dsc.fit > 0) {   // keep the normalised product for the variational sweeps
+        const FitLayout F = fit_layout(Lx, D);
+        for (size_t t = threadIdx.x; t < (size_t)Lx * box; t += blockDim.x) dsc.fbuf[F.xh + t] = xbox[t];
+        for (int c = threadIdx.x; c <= Lx; c += blockDim.x) xdims[FIT_DIMS + c] = c < Lx ? mX[c] : nX[Lx - 1];
+        if (threadIdx.x == 0) dsc.fbuf[0] = lognorm;
         __syncthreads();
     }
 
@@ -637,6 +676,252 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
         cst[k] = cmin;
     }
     __syncthreads();
+}
+
+// ---- two-site variational sweeps (run after truncate_row stored env k) ----
+// Bond dimensions: hd[c] of X^ (left bond of column c, c = 0..Lx), pd[c] of
+// psi.  Boxes of X^ and psi: [(A * 2 + u) * 2D + B] per column, as xbox.
+
+// Theta of bond (c, c+1) as a [(a u)][(v b)] matrix in th:
+//   Theta = sum L[a][A] X^_c[A][u][M] X^_{c+1}[M][v][B] R[b][B]
+// with the left overlap L ([ca][A0]) and the right overlap R ([cb][A2]).
+__device__ void fit_theta(const double *XH, const double *Lm, const double *Rm, double *t1, double *t2,
+                          double *th, int c, int ca, int cb, int A0, int A1, int A2, int D) {
+    const int ld = 2 * D;
+    const size_t box = (size_t)8 * D * D;
+    const double *X0 = XH + (size_t)c * box, *X1 = XH + (size_t)(c + 1) * box;
+    for (int t = threadIdx.x; t < ca * 2 * A1; t += blockDim.x) {
+        const int r = t / A1, M = t % A1, a = r >> 1, u = r & 1;
+        double acc = 0.0;
+        for (int A = 0; A < A0; ++A) acc += Lm[a * ld + A] * X0[(A * 2 + u) * ld + M];
+        t1[t] = acc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ca * 2 * 2 * A2; t += blockDim.x) {
+        const int r = t / (2 * A2), e = t % (2 * A2), v = e / A2, B = e % A2;
+        double acc = 0.0;
+        for (int M = 0; M < A1; ++M) acc += t1[r * A1 + M] * X1[(M * 2 + v) * ld + B];
+        t2[t] = acc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ca * 2 * 2 * cb; t += blockDim.x) {
+        const int r = t / (2 * cb), e = t % (2 * cb), v = e / cb, b = e % cb;
+        double acc = 0.0;
+        for (int B = 0; B < A2; ++B) acc += t2[(r * 2 + v) * A2 + B] * Rm[b * ld + B];
+        th[t] = acc;
+    }
+    __syncthreads();
+}
+
+// SVD of Theta truncated to D by one-sided Jacobi on the rows of W.  A
+// left-to-right step (lr) takes W = Theta^T, so the rotated rows give U:
+// psi_c = U (left-canonical), psi_{c+1} = S V^T = (Theta^T U)^T.  A right-to-
+// left step takes W = Theta: psi_{c+1} = V^T (right-canonical),
+// psi_c = U S = Theta V.  Returns the kept bond dimension.
+__device__ int fit_split(const double *th, int ca, int cb, bool lr, double *W, double *Wo, int D, double *sv,
+                         double *nrm, int *idx, int *flag, double *red, unsigned long long *counters,
+                         double *Pc, double *Pc1) {
+    const int ld = 2 * D;
+    const int rows = lr ? 2 * cb : 2 * ca, len = lr ? 2 * ca : 2 * cb;
+    const int lenp = (len + 15) & ~15, ldw = lenp | 1;
+    const double eps = 2.220446049250313e-16;
+    double f2 = 0.0;
+    for (int t = threadIdx.x; t < rows * lenp; t += blockDim.x) {
+        const int i = t / lenp, e = t % lenp;
+        const double v = e < len ? (lr ? th[e * (2 * cb) + i] : th[i * (2 * cb) + e]) : 0.0;
+        W[i * ldw + e] = v;
+        Wo[i * ldw + e] = v;
+        f2 += v * v;
+    }
+    f2 = tn_block_sum(f2, red);
+    const double zero2 = f2 * (len * eps) * (len * eps);
+    const int sweeps = qw_jacobi<4>(W, rows, len, ldw, zero2, nrm, flag);   // len <= 2 D <= 64
+    if (sweeps < 0 && threadIdx.x == 0) atomicAdd(&counters[CNT_NOCONV], 1ull);
+    for (int i = TN_QW; i < rows; i += TN_NQW) {
+        double s2 = 0.0;
+        for (int e = TN_QL; e < lenp; e += 16) s2 += W[i * ldw + e] * W[i * ldw + e];
+        s2 = tn_row16_sum(s2);
+        if (TN_QL == 0) sv[i] = s2 > zero2 ? sqrt(s2) : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+        int r = 0;
+        const double si = sv[i];
+        for (int j = 0; j < rows; ++j) r += (sv[j] > si) || (sv[j] == si && j < i);
+        idx[r] = i;
+    }
+    __syncthreads();
+    const int chi = min(D, min(rows, len));
+    // orthonormal factor O[k][e] = W'[idx k][e] / s_k (length len); coefficients
+    // C[i][k] = sum_e Wo[i][e] O[k][e] (rows x chi)
+    for (int t = threadIdx.x; t < chi * len; t += blockDim.x) {
+        const int kq = t / len, e = t % len, ik = idx[kq];
+        const double s = sv[ik];
+        const double o = s > 0.0 ? W[ik * ldw + e] / s : 0.0;
+        if (lr) {   // e = (a u): psi_c[a][u][kq]
+            Pc[e * ld + kq] = o;
+        } else {    // e = (v b): psi_{c+1}[kq][v][b]
+            const int v = e / cb, b = e % cb;
+            Pc1[(kq * 2 + v) * ld + b] = o;
+        }
+    }
+    for (int t = threadIdx.x; t < rows * chi; t += blockDim.x) {
+        const int kq = t / rows, i = t % rows, ik = idx[kq];
+        const double s = sv[ik];
+        double acc = 0.0;
+        if (s > 0.0) {
+            for (int e = 0; e < len; ++e) acc += Wo[i * ldw + e] * W[ik * ldw + e];
+            acc /= s;
+        }
+        if (lr) {   // i = (v b): psi_{c+1}[kq][v][b]
+            const int v = i / cb, b = i % cb;
+            Pc1[(kq * 2 + v) * ld + b] = acc;
+        } else {    // i = (a u): psi_c[a][u][kq]
+            Pc[i * ld + kq] = acc;
+        }
+    }
+    __syncthreads();
+    return chi;
+}
+
+// R_j[a][A] = sum_{u, b, B} psi_j[a][u][b] X^_j[A][u][B] R_{j+1}[b][B]
+__device__ void fit_right(const double *XH, const double *PS, double *RE, double *t1, const int *hd,
+                          const int *pd, int j, int D) {
+    const int ld = 2 * D;
+    const size_t box = (size_t)8 * D * D, m2 = (size_t)2 * D * D;
+    const int cj = pd[j], cn = pd[j + 1], Aj = hd[j], An = hd[j + 1];
+    const double *X = XH + (size_t)j * box, *P = PS + (size_t)j * box, *Rn = RE + (size_t)(j + 1) * m2;
+    double *Rj = RE + (size_t)j * m2;
+    for (int t = threadIdx.x; t < Aj * 2 * cn; t += blockDim.x) {
+        const int r = t / cn, b = t % cn;
+        double acc = 0.0;
+        for (int B = 0; B < An; ++B) acc += X[r * ld + B] * Rn[b * ld + B];
+        t1[t] = acc;   // [(A u)][b]
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cj * Aj; t += blockDim.x) {
+        const int a = t / Aj, A = t % Aj;
+        double acc = 0.0;
+        for (int u = 0; u < 2; ++u)
+            for (int b = 0; b < cn; ++b) acc += P[(a * 2 + u) * ld + b] * t1[(A * 2 + u) * cn + b];
+        Rj[a * ld + A] = acc;
+    }
+    __syncthreads();
+}
+
+// L_{j+1}[k][M] = sum_{a, u, A} psi_j[a][u][k] L_j[a][A] X^_j[A][u][M]
+__device__ void fit_left(const double *XH, const double *PS, double *LS, double *t1, const int *hd,
+                         const int *pd, int j, int D) {
+    const int ld = 2 * D;
+    const size_t box = (size_t)8 * D * D, m2 = (size_t)2 * D * D;
+    const int cj = pd[j], cn = pd[j + 1], Aj = hd[j], An = hd[j + 1];
+    const double *X = XH + (size_t)j * box, *P = PS + (size_t)j * box, *Lj = LS + (size_t)j * m2;
+    double *Ln = LS + (size_t)(j + 1) * m2;
+    for (int t = threadIdx.x; t < cj * 2 * An; t += blockDim.x) {
+        const int r = t / An, M = t % An, a = r >> 1, u = r & 1;
+        double acc = 0.0;
+        for (int A = 0; A < Aj; ++A) acc += Lj[a * ld + A] * X[(A * 2 + u) * ld + M];
+        t1[t] = acc;   // [(a u)][M]
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn * An; t += blockDim.x) {
+        const int kq = t / An, M = t % An;
+        double acc = 0.0;
+        for (int r = 0; r < 2 * cj; ++r) acc += P[r * ld + kq] * t1[r * An + M];
+        Ln[kq * ld + M] = acc;
+    }
+    __syncthreads();
+}
+
+// The variational sweeps of row k: fit psi (starting from the stored env k
+// with its norm put back) to X^, then store the normalised psi as env k with
+// ell_k = ln |X| (QR sweep) + ln |psi|.
+__device__ void fit_row(const tn_env_desc &dsc, int k, double *lds) {
+    const int Lx = dsc.Lx, D = dsc.D, ld = 2 * D;
+    const size_t box = (size_t)8 * D * D, m2 = (size_t)2 * D * D;
+    const FitLayout F = fit_layout(Lx, D);
+    double *fb = dsc.fbuf;
+    double *XH = fb + F.xh, *PS = fb + F.ps, *RE = fb + F.re, *LS = fb + F.ls;
+    double *t1 = fb + F.t1, *t2 = fb + F.t2, *th = fb + F.th;
+    double *W = lds, *Wo = lds + tn_svd_area(D);
+    __shared__ int hd[4 * TN_MAX_D + 1], pd[4 * TN_MAX_D + 1];
+    __shared__ double sv[2 * TN_MAX_D], nrm[2 * TN_MAX_D];
+    __shared__ int idx[2 * TN_MAX_D];
+    __shared__ double red[16];
+    __shared__ int flag;
+    const double lnqr = fb[0];
+    const double m0 = exp(dsc.ell[k] - lnqr);   // norm of the SVD start, <= 1
+    for (int c = threadIdx.x; c <= Lx; c += blockDim.x) {
+        hd[c] = dsc.xdims[FIT_DIMS + c];
+        pd[c] = c < Lx ? dsc.dims[k * (Lx + 1) + c] : 1;
+    }
+    const double *E = dsc.env + (size_t)k * Lx * 2 * D * D;
+    for (size_t t = threadIdx.x; t < (size_t)Lx * 2 * D * D; t += blockDim.x) {
+        const int c = (int)(t / (2 * D * D));
+        const int rem = (int)(t % (2 * D * D));
+        const int a = rem / (2 * D), u = (rem / D) & 1, b = rem % D;
+        PS[c * box + (a * 2 + u) * ld + b] = c == 0 ? E[t] * m0 : E[t];
+    }
+    if (threadIdx.x == 0) {
+        LS[0] = 1.0;
+        RE[(size_t)Lx * m2] = 1.0;
+    }
+    __syncthreads();
+    if (Lx > 1) {
+        for (int j = Lx - 1; j >= 2; --j) fit_right(XH, PS, RE, t1, hd, pd, j, D);
+        for (int sweep = 0; sweep < dsc.fit; ++sweep) {
+            for (int c = 0; c + 1 < Lx; ++c) {   // left to right
+                fit_theta(XH, LS + (size_t)c * m2, RE + (size_t)(c + 2) * m2, t1, t2, th, c, pd[c], pd[c + 2],
+                          hd[c], hd[c + 1], hd[c + 2], D);
+                const int chi = fit_split(th, pd[c], pd[c + 2], true, W, Wo, D, sv, nrm, idx, &flag, red,
+                                          dsc.counters, PS + (size_t)c * box, PS + (size_t)(c + 1) * box);
+                if (threadIdx.x == 0) pd[c + 1] = chi;
+                __syncthreads();
+                fit_left(XH, PS, LS, t1, hd, pd, c, D);
+            }
+            for (int c = Lx - 2; c >= 0; --c) {   // right to left
+                fit_theta(XH, LS + (size_t)c * m2, RE + (size_t)(c + 2) * m2, t1, t2, th, c, pd[c], pd[c + 2],
+                          hd[c], hd[c + 1], hd[c + 2], D);
+                const int chi = fit_split(th, pd[c], pd[c + 2], false, W, Wo, D, sv, nrm, idx, &flag, red,
+                                          dsc.counters, PS + (size_t)c * box, PS + (size_t)(c + 1) * box);
+                if (threadIdx.x == 0) pd[c + 1] = chi;
+                __syncthreads();
+                fit_right(XH, PS, RE, t1, hd, pd, c + 1, D);
+            }
+        }
+    }
+    // normalise the centre (column 0) and store env k
+    double s2 = 0.0;
+    for (int t = threadIdx.x; t < 2 * pd[0] * pd[1]; t += blockDim.x) {
+        const int r = t / pd[1], b = t % pd[1];
+        s2 += PS[r * ld + b] * PS[r * ld + b];
+    }
+    s2 = tn_block_sum(s2, red);
+    const double nrm0 = sqrt(s2);
+    const double inv = nrm0 > 0.0 ? 1.0 / nrm0 : 0.0;
+    double *Ek = dsc.env + (size_t)k * Lx * 2 * D * D;
+    for (size_t t = threadIdx.x; t < (size_t)Lx * 2 * D * D; t += blockDim.x) {
+        const int c = (int)(t / (2 * D * D));
+        const int rem = (int)(t % (2 * D * D));
+        const int a = rem / (2 * D), u = (rem / D) & 1, b = rem % D;
+        double v = 0.0;
+        if (a < pd[c] && b < pd[c + 1]) v = PS[c * box + (a * 2 + u) * ld + b] * (c == 0 ? inv : 1.0);
+        Ek[t] = v;
+    }
+    for (int c = threadIdx.x; c <= Lx; c += blockDim.x) dsc.dims[k * (Lx + 1) + c] = c < Lx ? pd[c] : 1;
+    if (threadIdx.x == 0) {
+        dsc.ell[k] = lnqr + log(nrm0);
+        dsc.cst[k] = -1;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_env_fit(const tn_env_desc *__restrict__ descs, int step) {
+    extern __shared__ double lds[];
+    const tn_env_desc dsc = descs[blockIdx.x];
+    const int k = dsc.Ly - 1 - step;
+    if (k < 1 || dsc.fit <= 0) return;
+    fit_row(dsc, k, lds);
 }
 
 // Row step `step` of every instance (row k = Ly - 1 - step; the instances
@@ -778,7 +1063,7 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
     };
     std::vector<tn_env_desc> ds(n);
     int maxLy = 1, maxD = 1;
-    size_t lds_tiny = 0, lds_small = 0, lds_big = 0;   // doubles
+    size_t lds_tiny = 0, lds_small = 0, lds_big = 0, lds_fit = 0;   // doubles
     for (int i = 0; i < n; ++i) {
         tn_ctx *ctx = ctxs[i];
         const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
@@ -793,11 +1078,19 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
             hipMalloc((void **)&ctx->xdims, 2 * (4 * TN_MAX_D + 1) * sizeof(int) +
                                                 2 * 1024 * sizeof(int)) != hipSuccess)
             return fail(TN_ENOMEM, "hipMalloc failed");
+        if (ctx->fit_sweeps > 0) {
+            if (D > 32) return fail(TN_EINVAL, "the variational sweeps support D up to 32");
+            if ((rc = tn_ensure(ctx, (void **)&ctx->fbuf, &ctx->fbuf_cap,
+                                fit_layout(Lx, D).total * sizeof(double))))
+                return fail(rc, ctx->err);
+            lds_fit = 2 * tn_svd_area(D) > lds_fit ? 2 * tn_svd_area(D) : lds_fit;
+        }
         tn_env_desc &d = ds[i];
         d.Lx = Lx;
         d.Ly = Ly;
         d.D = D;
-        d.pad = 0;
+        d.fit = ctx->fit_sweeps;
+        d.fbuf = ctx->fbuf;
         d.beta = ctx->beta;
         d.Jh = ctx->Jh;
         d.Jv = ctx->Jv;
@@ -831,6 +1124,7 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
     plan->n = n;
     plan->maxLy = maxLy;
     plan->lds_tiny = lds_tiny * sizeof(double);
+    plan->lds_fit = lds_fit * sizeof(double);
     plan->lds_small = lds_small * sizeof(double);
     plan->lds_big = lds_big * sizeof(double);
     plan->dd = dd;
@@ -850,7 +1144,9 @@ int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, 
                                                 (int)plan->lds_small) != hipSuccess) ||
         (plan->lds_big && hipFuncSetAttribute((const void *)k_env_row<1024>,
                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)plan->lds_big) != hipSuccess)) {
+                                              (int)plan->lds_big) != hipSuccess) ||
+        (plan->lds_fit && hipFuncSetAttribute((const void *)k_env_fit, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)plan->lds_fit) != hipSuccess)) {
         if (err) *err = "LDS size not accepted";
         return TN_EHIP;
     }
@@ -864,6 +1160,8 @@ int tn_env_build_steps(tn_build_plan *plan, int s0, int s1, hipStream_t stream, 
         if (plan->lds_big)
             hipLaunchKernelGGL(k_env_row<1024>, dim3(plan->n), dim3(1024), plan->lds_big, stream,
                                plan->dd, step);
+        if (plan->lds_fit)
+            hipLaunchKernelGGL(k_env_fit, dim3(plan->n), dim3(256), plan->lds_fit, stream, plan->dd, step);
         if (hipGetLastError() != hipSuccess) {
             if (err) *err = "row kernel launch failed";
             return TN_EHIP;

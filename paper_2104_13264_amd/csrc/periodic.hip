@@ -370,6 +370,7 @@ int tn_periodic_setup(tn_ctx *ctx, int Lx, int Ly, int wrap_x, int wrap_y, int D
             k->Dp = Dp;
             k->beta = inst[m].beta;
             k->prec = prec;
+            k->fit_sweeps = ctx->fit_sweeps;
             k->inst = m;
             k->Jh = pd[m].Jho;
             k->Jv = pd[m].Jvo;

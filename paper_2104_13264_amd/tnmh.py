@@ -65,6 +65,7 @@ def lib():
         "tn_get_env": (i, [vp, vp, vp, vp, ctypes.POINTER(d)]),
         "tn_set_precision": (i, [vp, i]),
         "tn_set_instance": (i, [vp, i]),
+        "tn_set_compression": (i, [vp, i]),
         "tn_sample": (i, [vp, i, u64, u64, u64, vp, vp, vp]),
         "tn_eval_logq": (i, [vp, i, vp, vp, vp]),
         "tn_mh_step": (i, [vp, i, u64, u64, vp, vp, vp, vp]),
@@ -107,7 +108,8 @@ def exported_symbols():
             "tn_build_env_multi", "tn_mh_step_multi", "tn_multi_instance", "tn_graph_begin",
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
             "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
-            "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap"]
+            "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap",
+            "tn_set_compression"]
 
 
 def _ptr(t):
@@ -210,6 +212,11 @@ class Sampler:
 
     def set_instance(self, inst):
         self._check(lib().tn_set_instance(self._ctx, int(inst)))
+
+    def set_compression(self, fit_sweeps):
+        """0: successive SVD; n > 0: successive SVD then n two-site variational
+        sweeps, for the builds that follow (tn_set_compression)."""
+        self._check(lib().tn_set_compression(self._ctx, int(fit_sweeps)))
 
     # -- sampling -----------------------------------------------------------
     def empty_batch(self, batch):

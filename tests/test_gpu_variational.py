@@ -1,0 +1,142 @@
+"""Two-site variational compression on the GPU (tn_set_compression) against
+the oracle (oracle/bmps.py: compress_variational).
+
+ln Z~ of fitted builds within 1e-9 relative of the oracle's fitted builds
+(single, incremental and batched builds; 1 and 3 sweeps; bond dimensions of
+every kernel class up to 32), FP64 proposals on fitted environments bitwise
+with the oracle's sampler on its own fitted environments (draws nearer than
+1e-6 to a threshold excluded), ln q to 1e-9 |ln Z~| absolute; a periodic
+FP64 chain on fitted
+builds follows the oracle; the frozen derivative is refused after a fitted
+build while the two-sided estimate runs; D > 32 and sweep counts outside
+0..16 are refused.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bmps, sampler, periodic
+from workloads import random_instance, ferro, ea_pm, ea_gauss, fully_frustrated, periodic_couplings
+from bridge import model_of, TOL_LOGZ_FP64, NEAR_FP64
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+CASES = [  # (name, instance, D, sweeps)
+    ("random 7x9 D3 field", lambda: random_instance(7, 9, 0.9, 3, seed=31, field_scale=0.3), 3, 1),
+    ("ea 10 D8 beta2", lambda: ea_pm(10, 2.0, 8, seed=32), 8, 3),
+    ("ferro 12x14 D4", lambda: ferro(12, 0.4407, 4, Lx=14), 4, 2),
+    ("frustrated 8 D6", lambda: fully_frustrated(8, 1.0, 6), 6, 1),
+    ("gauss 9x16 D24", lambda: random_instance(9, 16, 1.5, 24, seed=33), 24, 1),
+    ("gauss 8x12 D32", lambda: random_instance(8, 12, 2.0, 32, seed=34), 32, 1),
+    ("strip 1x9", lambda: random_instance(1, 9, 0.8, 4, seed=35), 4, 2),
+    ("column 7x1", lambda: random_instance(7, 1, 0.8, 2, seed=36), 2, 2),
+    ("two columns 6x2 D1", lambda: random_instance(6, 2, 0.8, 1, seed=37), 1, 2),
+    # the size of the equilibration workload: Gaussian 32x32 at T = 0.212, D = 16
+    ("gauss 32 T0.212 D16", lambda: ea_gauss(32, 1 / 0.212, 16, seed=39), 16, 1),
+]
+
+
+@pytest.mark.parametrize("name,mk,D,sw", CASES, ids=[c[0] for c in CASES])
+def test_fitted_logZ_and_sampler_match_oracle(name, mk, D, sw):
+    from paper_2104_13264_amd import Sampler
+    inst = mk()
+    log(f"[fit] {name} Ly={inst.Ly} Lx={inst.Lx} D={D} sweeps={sw}")
+    m = model_of(inst)
+    ref = bmps.build_envs(m, D, fit_sweeps=sw)
+    s = Sampler()
+    s.set_compression(sw)
+    lz = s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, D, FP64)
+    assert abs(lz - ref["logZ"]) <= TOL_LOGZ_FP64 * abs(ref["logZ"]) + 1e-12
+    assert s.stats()["clamps"] == 0
+    B, seed, step = 29, 4242, 3
+    want = sampler.sample(m, ref, B, seed, step=step)
+    sp, lq, E = s.sample(B, seed, step=step)
+    sp, lq = sp.cpu().numpy(), lq.cpu().numpy()
+    ok = want["min_gap"] >= NEAR_FP64
+    assert np.array_equal(sp[ok], want["spins"][ok])
+    # q is a ratio of contractions of the environments whose ln Z~ agrees to
+    # 1e-9 relative: ln q is held to that absolute error (the fit iterates on
+    # near-degenerate cuts at low temperature, e.g. 2.5e-7 on |ln q| ~ 36 at
+    # 32x32, T = 0.212, where ln Z~ = 6178)
+    tol = TOL_LOGZ_FP64 * max(abs(ref["logZ"]), 1.0)
+    assert np.all(np.abs(lq[ok] - want["logq"][ok]) <= tol)
+    s.close()
+
+
+def test_fit_changes_the_svd_result_and_incremental_build_agrees():
+    from paper_2104_13264_amd import Sampler
+    inst = random_instance(10, 12, 1.2, 4, seed=38, field_scale=0.2)
+    m = model_of(inst)
+    a = Sampler()
+    lz0 = a.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 4, FP64)
+    a.set_compression(2)
+    lz2 = a.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 4, FP64)
+    lz2i = a.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 4, FP64, progress=lambda d, t: None, rows_per_call=3)
+    assert lz2 == lz2i
+    assert abs(lz0 - bmps.build_envs(m, 4)["logZ"]) <= TOL_LOGZ_FP64 * abs(lz0)
+    ref2 = bmps.build_envs(m, 4, fit_sweeps=2)["logZ"]
+    assert abs(lz2 - ref2) <= TOL_LOGZ_FP64 * abs(ref2)
+    # the fit moves ln Z~ here by far more than the tolerance, as in the oracle
+    ref0 = bmps.build_envs(m, 4)["logZ"]
+    assert abs(lz2 - lz0) > 10 * TOL_LOGZ_FP64 * abs(lz0)
+    assert abs((lz2 - lz0) - (ref2 - ref0)) <= 2 * TOL_LOGZ_FP64 * abs(lz0)
+    a.close()
+
+
+def test_batched_fitted_builds():
+    from paper_2104_13264_amd import Sampler
+    items = [(random_instance(6, 9, 0.7, 8, seed=41, field_scale=0.2), 8),
+             (ea_pm(10, 1.0, 12, seed=42), 12),
+             (random_instance(9, 7, 0.5, 24, seed=43), 24),
+             (ea_pm(12, 2.0, 32, seed=44), 32)]
+    s = Sampler()
+    s.set_compression(1)
+    lz = s.build_env_multi([dict(Jh=i.Jh, Jv=i.Jv, h=i.h, beta=i.beta, D=D, chains=4) for i, D in items], FP32)
+    for (inst, D), got in zip(items, lz):
+        ref = bmps.build_envs(model_of(inst), D, fit_sweeps=1)["logZ"]
+        assert abs(got - ref) <= TOL_LOGZ_FP64 * abs(ref) + 1e-12
+    s.close()
+
+
+def test_periodic_fp64_chain_on_fitted_builds():
+    from paper_2104_13264_amd import Sampler
+    Ly, Lx, D = 7, 8, 3
+    inst = [dict(periodic_couplings(Ly, Lx, True, True, 50, field_scale=0.3), beta=1.1, chains=6)]
+    rng = np.random.default_rng(5)
+    s0 = rng.choice(np.array([-1, 1], dtype=np.int8), size=(6, Ly, Lx))
+    s = Sampler()
+    s.set_compression(1)
+    s.periodic_setup(inst, Lx, Ly, True, True, D, FP64)
+    spins = torch.as_tensor(s0, device=s.device).contiguous()
+    ref = s0.copy()
+    for t in range(3):
+        cr, cc = (2 * t + 1) % Ly, (3 * t) % Lx
+        E, acc = s.periodic_step(spins, 19, t, cr, cc)
+        ref, Eref, accref = periodic.step(inst, ref, 19, t, cr, cc, D, True, True, fit_sweeps=1)
+        np.testing.assert_array_equal(acc.cpu().numpy().astype(bool), accref)
+        np.testing.assert_array_equal(spins.cpu().numpy(), ref)
+    s.close()
+
+
+def test_derivatives_and_errors():
+    from paper_2104_13264_amd import Sampler, TNError
+    inst = fully_frustrated(6, 1.0, 4, Lx=8)
+    s = Sampler()
+    with pytest.raises(TNError):
+        s.set_compression(17)
+    s.set_compression(1)
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 4, FP64)
+    with pytest.raises(TNError):
+        s.grad()
+    dJh, dJv, db = s.grad(two_sided=True)
+    assert torch.isfinite(dJh).all() and torch.isfinite(dJv).all() and np.isfinite(db)
+    with pytest.raises(TNError):
+        s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 40, FP64)
+    s.close()
