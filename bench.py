@@ -370,14 +370,17 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     return out
 
 
-def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("tnmh+metropolis", 1))):
+def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("tnmh+metropolis", 1)),
+              fit_sweeps=0):
     """Equilibration test of Sec. 3, Eq. (Delta), on Gaussian spin glasses in
     the setting of the paper's Fig. hb b: n_inst 32x32 open instances at
     T = 0.212, D = 16, 30 chains each (15 replica pairs), from uniform random
     configurations; MH steps of all instances together (`modes`: name and
     Metropolis sweeps after each step).  Delta(t) is the disorder average
     over the instances of <H>/|V| + beta (|E| - link overlap)/|V| with the
-    thermal averages over each instance's chains and replica pairs."""
+    thermal averages over each instance's chains and replica pairs.
+    fit_sweeps > 0: environments by successive SVD and that many two-site
+    variational sweeps (the compression App. A names for these runs)."""
     import numpy as np
     import torch
     from paper_2104_13264_amd import Sampler, FP32
@@ -388,13 +391,14 @@ def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("t
     nV, nE = L * L, 2 * L * (L - 1)
     beta = insts[0].beta
     s = Sampler()
+    s.set_compression(fit_sweeps)
     t0 = time.perf_counter()
     s.build_env_multi([dict(Jh=i.Jh, Jv=i.Jv, h=None, beta=i.beta, D=i.D, chains=i.chains) for i in insts], prec)
     build_s = time.perf_counter() - t0
     log(f"[bench] delta: {n_inst} Gaussian instances built in {build_s:.2f} s")
     subs = [s.instance(k) for k in range(n_inst)]
     out = {"workload": "delta_ea_gauss32_T0.212_D16", "instances": n_inst, "chains": chains,
-           "steps": steps, "env_build_s": build_s}
+           "steps": steps, "env_build_s": build_s, "fit_sweeps": fit_sweeps}
     thresholds = (0.25, 0.15, 0.05, 0.025)
     for mode, nsw in modes:
         states = [sub.init_state(chains, torch.as_tensor(random_spins(chains, L, L, SEED + 77 + k)))
@@ -608,6 +612,8 @@ def main():
                     help="MH steps per sampler launch (default: enough for two four-wave teams per CU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--fit-sweeps", type=int, default=0,
+                    help="delta workload: also run with this many two-site variational sweeps")
     ap.add_argument("--periodic-steps", type=int, default=60,
                     help="TNMH steps of the periodic workload")
     ap.add_argument("--periodic-cuts", default="random", choices=["random", "opposite"],
@@ -631,6 +637,9 @@ def main():
         elif args.workload == "delta":
             from paper_2104_13264_amd import FP64, FP32
             out = {"fp32": run_delta(prec=FP32), "fp64": run_delta(prec=FP64)}
+            if args.fit_sweeps:
+                out["fp32_fit"] = run_delta(prec=FP32, fit_sweeps=args.fit_sweeps, modes=(("tnmh", 0),))
+                out["fp64_fit"] = run_delta(prec=FP64, fit_sweeps=args.fit_sweeps)
         elif args.workload == "periodic":
             out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts)
         else:
