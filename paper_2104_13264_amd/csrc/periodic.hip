@@ -445,10 +445,13 @@ int tn_periodic_step(tn_ctx *ctx, uint64_t seed, uint64_t step, int cut_row, int
         if (!P->descs_ready && (rc = make_descs(ctx, P))) return rc;
     } else {
         if (!P->descs_ready && (rc = make_descs(ctx, P))) return rc;
+        // one proposal per chain: the one-set-per-wave variant, whose second
+        // team of a chain has no proposal and leaves at once
         const int NT = ((P->D + 15) / 16);
         const bool bf = P->prec == TN_BF16;
-        if ((rc = tn_run_mfma_multi(ctx, NT, bf, 0, P->sd_eval, T, 8 * T, P->Lxo, 0, 0, true))) return rc;
-        if ((rc = tn_run_mfma_multi(ctx, NT, bf, 0, P->sd_samp, T, 8 * T, P->Lxo, seed, step, false))) return rc;
+        const int v = tn_team_variants(NT) > 1 ? 1 : 0;
+        if ((rc = tn_run_mfma_multi(ctx, NT, bf, v, P->sd_eval, T, 8 * T, P->Lxo, 0, 0, true))) return rc;
+        if ((rc = tn_run_mfma_multi(ctx, NT, bf, v, P->sd_samp, T, 8 * T, P->Lxo, seed, step, false))) return rc;
     }
     if ((rc = tn_launch_accept_multi(ctx, P->ad, P->nacc, T, seed, step))) return rc;
     hipLaunchKernelGGL(k_uncut, dim3(T), dim3(PT_THREADS), (size_t)P->Lx * P->Ly, ctx->stream, P->pd, P->inst_of,

@@ -266,6 +266,7 @@ __device__ __forceinline__ void lds_tiles(ATiles<NT, BF16> &a, const unsigned ch
 template <int NT, bool BF16, int V>
 __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0, const int eval,
                                           const uint32_t k0, const uint32_t k1, const uint64_t step0) {
+    if (unit0 * 16 >= A.B) return;   // a team with no proposal of its instance (uniform)
     using AT = ATiles<NT, BF16>;
     using CF = TeamCfg<NT, BF16, V>;
     constexpr int TL = CF::TL, SE = CF::SETS, PT = CF::PT;
