@@ -44,6 +44,13 @@ Readings adopted:
 Chains of one instance whose frozen lines agree share one environment build
 (the open model depends on the frozen spins only).
 
+Single-spin-flip Metropolis sweeps (Sec. 3) on the identified lattice follow
+oracle.metropolis with the wrapping neighbours: checkerboard order (r + c
+even first), which needs an even length along a wrapped direction so that
+same-colour sites share no bond; local field h + left + right + up + down in
+that order; flip iff u < exp(-(beta 2 s F)); u from Philox stream 2 at counter
+(sweep * 2^14 + i // 4, chain j, step, m << 2 | 2), word i % 4.
+
 Test infrastructure only (see the package docstring).
 """
 import numpy as np
@@ -52,6 +59,7 @@ from .ising import Model
 from .bmps import build_envs
 from .sampler import sample, eval_logq
 from .mh import accept_uniforms, mh_decide
+from .metropolis import sweep_uniforms
 
 
 def check_shapes(Lx, Ly, Jh, Jv, h, wrap_x, wrap_y):
@@ -178,3 +186,53 @@ def step(instances, spins, seed, t, cut_row, cut_col, D, wrap_x, wrap_y, fit_swe
         E[g0:g0 + C] = energy(out[g0:g0 + C], it["Jh"], it["Jv"], it.get("h"), wrap_x, wrap_y)
         g0 += C
     return out, E, acc
+
+
+def local_field(s, Jh, Jv, h, wrap_x, wrap_y):
+    """F[..., r, c] = h + J_left s_left + J_right s_right + J_up s_up + J_down s_down
+    on the identified lattice, added in this order (0 for a missing neighbour)."""
+    s = np.asarray(s, dtype=np.float64)
+    Ly, Lx = s.shape[-2:]
+    Jh = np.asarray(Jh, dtype=np.float64)
+    Jv = np.asarray(Jv, dtype=np.float64)
+    left = np.zeros(s.shape)
+    right = np.zeros(s.shape)
+    up = np.zeros(s.shape)
+    down = np.zeros(s.shape)
+    for c in range(Lx):
+        if c > 0 or wrap_x:
+            left[..., :, c] = Jh[:, (c - 1) % Lx] * s[..., :, (c - 1) % Lx]
+        if c < Lx - 1 or wrap_x:
+            right[..., :, c] = Jh[:, c] * s[..., :, (c + 1) % Lx]
+    for r in range(Ly):
+        if r > 0 or wrap_y:
+            up[..., r, :] = Jv[(r - 1) % Ly, :] * s[..., (r - 1) % Ly, :]
+        if r < Ly - 1 or wrap_y:
+            down[..., r, :] = Jv[r, :] * s[..., (r + 1) % Ly, :]
+    F = np.zeros(s.shape) if h is None else np.broadcast_to(np.asarray(h, dtype=np.float64), s.shape).copy()
+    return (((F + left) + right) + up) + down
+
+
+def sweeps(instances, spins, seed, step, nsweeps, wrap_x, wrap_y):
+    """nsweeps checkerboard Metropolis sweeps of every chain on the identified
+    lattice (new array) and the accepted flips per chain."""
+    s = np.array(spins, dtype=np.float64)
+    T, Ly, Lx = s.shape
+    assert not (wrap_x and Lx % 2) and not (wrap_y and Ly % 2), "checkerboard needs even wrapped lengths"
+    rr, cc = np.meshgrid(np.arange(Ly), np.arange(Lx), indexing="ij")
+    colour = (rr + cc) & 1
+    flips = np.zeros(T, dtype=np.int64)
+    g0 = 0
+    for m, it in enumerate(instances):
+        C = it["chains"]
+        x = s[g0:g0 + C]
+        for k in range(nsweeps):
+            u = sweep_uniforms(C, Ly * Lx, seed, step, k, inst=m).reshape(C, Ly, Lx)
+            for col in (0, 1):
+                F = local_field(x, it["Jh"], it["Jv"], it.get("h"), wrap_x, wrap_y)
+                flip = (u < np.exp(-(it["beta"] * ((2.0 * x) * F)))) & (colour == col)[None]
+                x = np.where(flip, -x, x)
+                flips[g0:g0 + C] += flip.sum(axis=(1, 2))
+        s[g0:g0 + C] = x
+        g0 += C
+    return s.astype(np.int8), flips

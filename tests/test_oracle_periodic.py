@@ -214,3 +214,75 @@ def test_link_overlap_counts(wrap):
     b = a.copy()
     b[2, 3] = -b[2, 3]
     assert periodic.link_overlap(a, b, wx, wy) == nb - 8
+
+
+def exact_sweep_matrix(Jh, Jv, h, beta, Ly, Lx, wx, wy):
+    """One checkerboard Metropolis sweep on the identified lattice, from the
+    rule min(1, exp(-beta dE)) with dE from the periodic energy directly."""
+    cf = all_configs(Ly, Lx)
+    index = {c.tobytes(): k for k, c in enumerate(cf)}
+    n = len(cf)
+
+    def half(P, colour):
+        out = np.zeros((n, n))
+        for a in range(n):
+            for k0 in np.nonzero(P[a])[0]:
+                s = cf[k0]
+                sites = [(r, c) for r in range(Ly) for c in range(Lx) if (r + c) % 2 == colour]
+                e0 = periodic.energy(s, Jh, Jv, h, wx, wy)
+                probs = []
+                for (r, c) in sites:
+                    t = s.copy()
+                    t[r, c] = -t[r, c]
+                    probs.append(min(1.0, np.exp(-beta * (periodic.energy(t, Jh, Jv, h, wx, wy) - e0))))
+                for pattern in itertools.product([0, 1], repeat=len(sites)):
+                    t = s.copy()
+                    w = P[a, k0]
+                    for f, (r, c), p in zip(pattern, sites, probs):
+                        w *= p if f else 1.0 - p
+                        if f:
+                            t[r, c] = -t[r, c]
+                    out[a, index[t.tobytes()]] += w
+        return out
+
+    return half(half(np.eye(n), 0), 1), cf
+
+
+def test_periodic_sweep_matrix_and_oracle_frequencies():
+    # 2x4 cylinder along x: 256 states, the wrapping bonds in every sweep
+    rng = np.random.default_rng(12)
+    Ly, Lx, beta = 2, 4, 0.7
+    Jh, Jv, h = couplings(rng, Ly, Lx, True, False, field=0.3)
+    P, cf = exact_sweep_matrix(Jh, Jv, h, beta, Ly, Lx, True, False)
+    _, p = boltzmann(Jh, Jv, h, beta, Ly, Lx, True, False)
+    np.testing.assert_allclose(p @ P, p, atol=1e-13)
+    index = {c.tobytes(): k for k, c in enumerate(cf)}
+    N = 3000
+    inst = [dict(Jh=Jh, Jv=Jv, h=h, beta=beta, chains=N)]
+    for a in range(0, len(cf), 17):
+        out, _ = periodic.sweeps(inst, np.broadcast_to(cf[a], (N, Ly, Lx)), seed=4, step=a, nsweeps=1,
+                                 wrap_x=True, wrap_y=False)
+        freq = np.bincount([index[o.tobytes()] for o in out], minlength=len(cf)) / N
+        sigma = np.sqrt(P[a] * (1.0 - P[a]) / N)
+        assert np.all(np.abs(freq - P[a]) <= 5.0 * sigma + 2e-3), a
+
+
+def test_periodic_sweeps_keep_the_torus_energy_law():
+    rng = np.random.default_rng(8)
+    Ly, Lx, beta, N = 4, 4, 1.0, 20000
+    Jh, Jv, h = couplings(rng, Ly, Lx, True, True, field=0.4)
+    cf, p = boltzmann(Jh, Jv, h, beta, Ly, Lx, True, True)
+    Ecf = periodic.energy(cf, Jh, Jv, h, True, True)
+    s = cf[rng.choice(len(cf), size=N, p=p)]
+    out, flips = periodic.sweeps([dict(Jh=Jh, Jv=Jv, h=h, beta=beta, chains=N)], s, seed=6, step=0, nsweeps=2,
+                                 wrap_x=True, wrap_y=True)
+    assert flips.sum() > 0
+    assert energy_chi2_pvalue(periodic.energy(out, Jh, Jv, h, True, True), Ecf, p) > 1e-4
+    # the local field against energy differences of single flips
+    F = periodic.local_field(s[:50], Jh, Jv, h, True, True)
+    E0 = periodic.energy(s[:50], Jh, Jv, h, True, True)
+    for (r, c) in [(0, 0), (3, 3), (1, 2)]:
+        t = s[:50].copy()
+        t[:, r, c] = -t[:, r, c]
+        dE = periodic.energy(t, Jh, Jv, h, True, True) - E0
+        np.testing.assert_allclose(dE, 2.0 * s[:50, r, c] * F[:, r, c], atol=1e-12)
