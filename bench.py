@@ -436,7 +436,7 @@ def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("t
     return out
 
 
-def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None, cuts="random"):
+def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None, cuts="random", sweeps=0):
     """Equilibration test of Eq. (Delta) with periodic boundaries (Section
     "Arbitrary boundary conditions", table of TNMH iterations on periodic
     Gaussian spin glasses): n_inst 32x32 tori at T = 0.212, D = 16, 30 chains
@@ -446,7 +446,8 @@ def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None, cuts="random")
     run_delta with the 2 L^2 bonds of the torus.  cuts: "opposite" alternates
     between two opposite crosses, (k, k) and (k + L/2, k + L/2) with k = t // 2
     (the torus analogue of the paper's alternating opposite lines, shifted so
-    that no site stays frozen), "random" draws a uniform cross per step."""
+    that no site stays frozen), "random" draws a uniform cross per step.
+    sweeps: Metropolis sweeps on the torus after every TNMH step."""
     import numpy as np
     import torch
     from paper_2104_13264_amd import Sampler, FP32
@@ -484,6 +485,8 @@ def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None, cuts="random")
     for t in range(steps):
         ts = time.perf_counter()
         E, acc = s.periodic_step(spins, SEED, t, int(cut[t, 0]), int(cut[t, 1]))
+        if sweeps:
+            E = s.periodic_sweeps(spins, sweeps, SEED, t)
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - ts) * 1e3)
         series.append(delta_now(E))
@@ -497,6 +500,7 @@ def run_periodic(steps=60, n_inst=64, chains=30, D=16, prec=None, cuts="random")
     out = {"workload": f"periodic_ea_gauss_torus{L}_T0.212_D{D}", "instances": n_inst, "chains": chains,
            "chains_total": T, "steps": steps, "setup_s": setup_s,
            "cuts": "uniform random cross per step" if cuts == "random" else "alternating opposite crosses",
+           "metropolis_sweeps_per_step": sweeps,
            "delta": series, "steps_to_reach": first,
            "acceptance": st["accepted"] / max(st["proposed"], 1),
            "ms_per_step": wall * 1e3 / steps, "ms_per_step_median": float(np.median(step_ms)),
@@ -616,6 +620,8 @@ def main():
                     help="delta workload: also run with this many two-site variational sweeps")
     ap.add_argument("--periodic-steps", type=int, default=60,
                     help="TNMH steps of the periodic workload")
+    ap.add_argument("--periodic-sweeps", type=int, default=0,
+                    help="Metropolis sweeps after every TNMH step of the periodic workload")
     ap.add_argument("--periodic-cuts", default="random", choices=["random", "opposite"],
                     help="cut schedule of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
@@ -641,7 +647,7 @@ def main():
                 out["fp32_fit"] = run_delta(prec=FP32, fit_sweeps=args.fit_sweeps, modes=(("tnmh", 0),))
                 out["fp64_fit"] = run_delta(prec=FP64, fit_sweeps=args.fit_sweeps)
         elif args.workload == "periodic":
-            out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts)
+            out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts, sweeps=args.periodic_sweeps)
         else:
             out = run_frustrated128()
         print(json.dumps(out), flush=True)

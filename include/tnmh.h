@@ -401,6 +401,18 @@ int tn_periodic_setup(tn_ctx *ctx, int Lx, int Ly, int wrap_x, int wrap_y, int D
 int tn_periodic_step(tn_ctx *ctx, uint64_t seed, uint64_t step, int cut_row, int cut_col, int8_t *spins,
                      double *energy, uint8_t *accepted);
 
+/* nsweeps checkerboard single-spin-flip Metropolis sweeps of every chain on
+ * the periodic lattice (Sec. 3 interleaves such sweeps with TNMH steps), in
+ * place, then the periodic energies into energy (dev, fp64 [total chains]).
+ * Site order r + c even first; local field h + left + right + up + down with
+ * the wrapping neighbours, in that order; flip iff u < exp(-(beta 2 s F)),
+ * u = word i % 4 of Philox4x32-10 at counter (sweep * 2^14 + i / 4, chain j,
+ * step, instance m << 2 | 2).  Flips are counted in tn_stats.  Errors:
+ * TN_ESTATE before tn_periodic_setup; TN_EINVAL for an odd length along a
+ * wrapped direction (same-colour sites would share a bond) or nsweeps
+ * outside 0..2^18-1. */
+int tn_periodic_sweeps(tn_ctx *ctx, int nsweeps, uint64_t seed, uint64_t step, int8_t *spins, double *energy);
+
 /* Periodic energies of given states (dev, int8 [total chains][Ly][Lx]) into
  * energy (dev, fp64 [total chains]).  TN_ESTATE before tn_periodic_setup. */
 int tn_periodic_energy(tn_ctx *ctx, const int8_t *spins, double *energy);

@@ -34,6 +34,7 @@ struct tn_per_desc {
     const double *Jh, *Jv, *h;   // periodic couplings and field (h may be NULL)
     double *Jho, *Jvo;           // open couplings under the current cut
     int first, chains;
+    double beta;
 };
 
 struct tn_periodic {
@@ -140,6 +141,61 @@ k_uncut(const tn_per_desc *__restrict__ pd, const int *__restrict__ inst_of, int
         energy[g] = e;
         if (acc) accepted[g] = acc[g];
     }
+}
+
+// Checkerboard Metropolis sweeps on the identified lattice (Sec. 3: single
+// spin flips between TNMH steps), one workgroup per chain with its spins in
+// LDS.  Local field h + left + right + up + down with the wrapping
+// neighbours, in that order; flip iff u < exp(-(beta 2 s F)); u is word i % 4
+// of Philox stream 2 at counter (sweep * 2^14 + i / 4, chain j, step,
+// instance m << 2 | 2).  Wrapped lengths are even, so same-colour sites share
+// no bond.
+__global__ void __launch_bounds__(PT_THREADS)
+k_per_metropolis(const tn_per_desc *__restrict__ pd, const int *__restrict__ inst_of, int Lx, int Ly, int wx,
+                 int wy, int nsweeps, int8_t *__restrict__ S, uint32_t k0, uint32_t k1, uint32_t step,
+                 unsigned long long *__restrict__ counters) {
+    extern __shared__ int8_t sp[];   // [Ly][Lx]
+    const int g = blockIdx.x;
+    const int m = inst_of[g];
+    const tn_per_desc P = pd[m];
+    const uint32_t j = (uint32_t)(g - P.first);
+    const int N = Lx * Ly, JhW = wx ? Lx : Lx - 1;
+    int8_t *s = S + (size_t)g * N;
+    for (int i = threadIdx.x; i < N; i += PT_THREADS) sp[i] = s[i];
+    __syncthreads();
+    uint32_t flips = 0;
+    const int nblk = (N + 3) >> 2;
+    for (int k = 0; k < nsweeps; ++k) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int b = threadIdx.x; b < nblk; b += PT_THREADS) {
+                const uint4 w = tn_philox(make_uint4(((uint32_t)k << 14) | (uint32_t)b, j, step,
+                                                     ((uint32_t)m << 2) | 2u),
+                                          k0, k1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 4 * b + q;
+                    if (i >= N) break;
+                    const int r = i / Lx, c = i - r * Lx;
+                    if (((r + c) & 1) != colour) continue;
+                    const int cl = c > 0 ? c - 1 : Lx - 1, cr = c + 1 < Lx ? c + 1 : 0;
+                    const int ru = r > 0 ? r - 1 : Ly - 1, rd = r + 1 < Ly ? r + 1 : 0;
+                    double F = P.h ? P.h[i] : 0.0;
+                    if (c > 0 || wx) F = F + P.Jh[r * JhW + cl] * (double)sp[r * Lx + cl];
+                    if (c + 1 < Lx || wx) F = F + P.Jh[r * JhW + c] * (double)sp[r * Lx + cr];
+                    if (r > 0 || wy) F = F + P.Jv[ru * Lx + c] * (double)sp[ru * Lx + c];
+                    if (r + 1 < Ly || wy) F = F + P.Jv[r * Lx + c] * (double)sp[rd * Lx + c];
+                    const double dE = (2.0 * (double)sp[i]) * F;
+                    if (tn_u01(tn_word(w, q)) < exp(-(P.beta * dE))) {
+                        sp[i] = (int8_t)(-sp[i]);
+                        ++flips;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < N; i += PT_THREADS) s[i] = sp[i];
+    if (flips) atomicAdd(&counters[CNT_FLIPS], (unsigned long long)flips);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -345,6 +401,7 @@ int tn_periodic_setup(tn_ctx *ctx, int Lx, int Ly, int wrap_x, int wrap_y, int D
         pd[m].Jvo = pd[m].Jho + nho;
         pd[m].first = g;
         pd[m].chains = inst[m].chains;
+        pd[m].beta = inst[m].beta;
         P->first[m] = g;
         P->chains[m] = inst[m].chains;
         P->beta[m] = inst[m].beta;
@@ -458,6 +515,24 @@ int tn_periodic_step(tn_ctx *ctx, uint64_t seed, uint64_t step, int cut_row, int
                        P->Lx, P->Ly, P->wx, P->wy, P->Lxo, P->Lyo, cr, cc, P->os, spins, energy, P->acc, accepted);
     TN_HIP(ctx, hipGetLastError());
     return TN_OK;
+}
+
+int tn_periodic_sweeps(tn_ctx *ctx, int nsweeps, uint64_t seed, uint64_t step, int8_t *spins, double *energy) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_periodic(ctx))) return rc;
+    tn_periodic *P = per_of(ctx);
+    if (!spins || !energy) return tn_fail(ctx, TN_EINVAL, "NULL buffer");
+    if (nsweeps < 0 || nsweeps >= (1 << 18)) return tn_fail(ctx, TN_EINVAL, "nsweeps must be in 0..2^18-1");
+    if ((P->wx && (P->Lx & 1)) || (P->wy && (P->Ly & 1)))
+        return tn_fail(ctx, TN_EINVAL, "checkerboard sweeps need an even length along a wrapped direction");
+    if (nsweeps > 0) {
+        hipLaunchKernelGGL(k_per_metropolis, dim3(P->total), dim3(PT_THREADS), (size_t)P->Lx * P->Ly, ctx->stream,
+                           P->pd, P->inst_of, P->Lx, P->Ly, P->wx, P->wy, nsweeps, spins, (uint32_t)seed,
+                           (uint32_t)(seed >> 32), (uint32_t)step, ctx->counters);
+        TN_HIP(ctx, hipGetLastError());
+    }
+    return tn_periodic_energy(ctx, spins, energy);
 }
 
 int tn_periodic_energy(tn_ctx *ctx, const int8_t *spins, double *energy) {

@@ -90,6 +90,7 @@ def lib():
         "tn_periodic_setup": (i, [vp, i, i, i, i, i, i, i, vp]),
         "tn_periodic_step": (i, [vp, u64, u64, i, i, vp, vp, vp]),
         "tn_periodic_energy": (i, [vp, vp, vp]),
+        "tn_periodic_sweeps": (i, [vp, i, u64, u64, vp, vp]),
         "tn_periodic_link_overlap": (i, [vp, i, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -109,7 +110,7 @@ def exported_symbols():
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
             "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
             "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap",
-            "tn_set_compression"]
+            "tn_set_compression", "tn_periodic_sweeps"]
 
 
 def _ptr(t):
@@ -372,6 +373,15 @@ class Sampler:
         self._check(lib().tn_periodic_step(self._ctx, int(seed), int(step), int(cut_row), int(cut_col),
                                            _ptr(spins), _ptr(energy), _ptr(accepted)))
         return energy, accepted
+
+    def periodic_sweeps(self, spins, nsweeps, seed, step):
+        """nsweeps Metropolis sweeps of every chain on the periodic lattice,
+        in place (tn_periodic_sweeps); returns the periodic energies."""
+        if spins.dtype != torch.int8 or not spins.is_contiguous() or spins.device != self.device:
+            raise ValueError("spins must be a contiguous int8 tensor on the context's device")
+        E = torch.empty(spins.shape[0], dtype=torch.float64, device=self.device)
+        self._check(lib().tn_periodic_sweeps(self._ctx, int(nsweeps), int(seed), int(step), _ptr(spins), _ptr(E)))
+        return E
 
     def periodic_energy(self, spins):
         spins = torch.as_tensor(spins, dtype=torch.int8, device=self.device).contiguous()

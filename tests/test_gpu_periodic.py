@@ -200,3 +200,40 @@ def test_errors():
         s.periodic_step(spins, 1, 0, 0, -1)
     s.periodic_step(spins, 1, 0, 3, 3)
     s.close()
+
+
+@pytest.mark.parametrize("wrap", [(True, True), (True, False), (False, True)], ids=["torus", "cyl_x", "cyl_y"])
+def test_periodic_sweeps_match_oracle(wrap):
+    from paper_2104_13264_amd import Sampler
+    wx, wy = wrap
+    Ly, Lx = 10, 12
+    inst = instances(Ly, Lx, wx, wy, (5, 8), seed=900, beta=(1.3, 0.6))
+    log(f"[periodic] sweeps {Ly}x{Lx} wrap=({wx},{wy})")
+    s = Sampler()
+    s.periodic_setup(inst, Lx, Ly, wx, wy, 4, FP32)
+    rng = np.random.default_rng(21)
+    s0 = rng.choice(np.array([-1, 1], dtype=np.int8), size=(13, Ly, Lx))
+    spins = torch.as_tensor(s0, device=s.device).contiguous()
+    s.stats(reset=True)
+    E = s.periodic_sweeps(spins, 3, 55, 7)
+    ref, flips = periodic.sweeps(inst, s0, 55, 7, 3, wx, wy)
+    np.testing.assert_array_equal(spins.cpu().numpy(), ref)
+    assert s.stats()["metropolis_flips"] == int(flips.sum())
+    g0 = 0
+    for it in inst:
+        C = it["chains"]
+        np.testing.assert_allclose(E.cpu().numpy()[g0:g0 + C],
+                                   periodic.energy(ref[g0:g0 + C], it["Jh"], it["Jv"], it.get("h"), wx, wy),
+                                   rtol=1e-13, atol=1e-12)
+        g0 += C
+    s.close()
+
+
+def test_periodic_sweeps_refuse_odd_wrapped_lengths():
+    from paper_2104_13264_amd import Sampler, TNError
+    s = Sampler()
+    s.periodic_setup(instances(6, 5, True, False, (2,), seed=3), 5, 6, True, False, 4, FP32)
+    spins = torch.ones((2, 6, 5), dtype=torch.int8, device=s.device)
+    with pytest.raises(TNError):
+        s.periodic_sweeps(spins, 1, 1, 0)
+    s.close()
