@@ -140,3 +140,20 @@ def test_derivatives_and_errors():
     with pytest.raises(TNError):
         s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 40, FP64)
     s.close()
+
+
+def test_fp32_sampler_on_fitted_environments():
+    from paper_2104_13264_amd import Sampler
+    from bridge import TOL_LOGQ_FP32
+    inst = random_instance(12, 13, 0.8, 16, seed=45, field_scale=0.2)
+    m = model_of(inst)
+    ref = bmps.build_envs(m, 16, fit_sweeps=2)
+    s = Sampler()
+    s.set_compression(2)
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 16, FP32)
+    sp, lq, E = s.sample(200, 77, step=1)
+    ev = sampler.eval_logq(m, ref, sp.cpu().numpy())
+    np.testing.assert_allclose(lq.cpu().numpy(), ev["logq"], rtol=TOL_LOGQ_FP32, atol=0)
+    lq2, _ = s.eval_logq(sp)
+    assert torch.equal(lq2, lq)
+    s.close()
