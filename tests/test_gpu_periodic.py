@@ -237,3 +237,41 @@ def test_periodic_sweeps_refuse_odd_wrapped_lengths():
     with pytest.raises(TNError):
         s.periodic_sweeps(spins, 1, 1, 0)
     s.close()
+
+
+EDGE_CASES = [  # (Ly, Lx, wrap_x, wrap_y, D, precision, chains per instance)
+    (3, 3, True, True, 2, FP64, (4, 0, 3)),      # smallest torus (open 2x2), an instance without chains
+    (5, 4, True, False, 2, FP64, (0, 5)),        # the first instance without chains
+    (2, 257, True, False, 4, FP32, (3,)),        # widest open lattice: 256 columns
+]
+
+
+@pytest.mark.parametrize("case", range(len(EDGE_CASES)))
+def test_edge_shapes(case):
+    from paper_2104_13264_amd import Sampler
+    Ly, Lx, wx, wy, D, prec, chains = EDGE_CASES[case]
+    log(f"[periodic] edge {Ly}x{Lx} wrap=({wx},{wy}) D={D} prec={prec} chains={chains}")
+    inst = instances(Ly, Lx, wx, wy, chains, seed=950 + case, beta=(1.1, 0.6))
+    T = sum(chains)
+    rng = np.random.default_rng(30 + case)
+    s0 = rng.choice(np.array([-1, 1], dtype=np.int8), size=(T, Ly, Lx))
+    s = Sampler()
+    s.periodic_setup(inst, Lx, Ly, wx, wy, D, prec)
+    spins = torch.as_tensor(s0, device=s.device).contiguous()
+    ref = s0.copy()
+    for t in range(2):
+        cr, cc = cuts(t, Ly, Lx)
+        before = spins.cpu().numpy()
+        E, acc = s.periodic_step(spins, 13, t, cr, cc)
+        got = spins.cpu().numpy()
+        if prec == FP64:
+            ref, Eref, accref = periodic.step(inst, ref, 13, t, cr, cc, D, wx, wy)
+            np.testing.assert_array_equal(got, ref)
+            np.testing.assert_array_equal(acc.cpu().numpy().astype(bool), accref)
+            np.testing.assert_allclose(E.cpu().numpy(), Eref, rtol=1e-13, atol=1e-12)
+        else:
+            for j in range(T):
+                want, ok = open_context_step(inst, before[j], 0, j, 13, t, cr, cc, D, prec, wx, wy)
+                assert bool(acc.cpu().numpy()[j]) == ok
+                np.testing.assert_array_equal(got[j], want)
+    s.close()
