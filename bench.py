@@ -322,6 +322,7 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     s.build_env(inst.Jh, inst.Jv, None, inst.beta, inst.D, FP32)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    degen = s.stats()["degenerate_cuts"]   # truncations at tied singular values
     out = {"workload": "hybrid_ea32_T0.212_D16", "chains": chains, "steps": steps, "env_build_s": build_s,
            "logZ": s.stats()["logZ"]}
     stream = torch.cuda.current_stream()
@@ -366,6 +367,19 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     out["eval_logq_ms"] = eval_ms
     out["sweep_kernel_ms_est"] = kern_ms
     out["site_updates_per_s_est"] = sweeps * chains * inst.Lx * inst.Ly / (kern_ms * 1e-3) if kern_ms > 0 else None
+    # the same environments with FP64 operands (plain path): how much of the
+    # FP32 acceptance is lost to the rounding of ln q
+    from paper_2104_13264_amd import FP64
+    s.set_precision(FP64)
+    state = s.init_state(chains)
+    s.stats(reset=True)
+    n64 = 60
+    for t in range(n64):
+        s.mh_step(state, SEED, t)
+    st = s.stats()
+    out["fp64_acceptance_60_steps"] = st["accepted"] / max(st["proposed"], 1)
+    out["degenerate_cuts"] = degen
+    log(f"[bench] hybrid tnmh, FP64 operands: acceptance {out['fp64_acceptance_60_steps']:.5f} over {n64} steps")
     s.close()
     return out
 
