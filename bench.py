@@ -384,6 +384,36 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     return out
 
 
+def run_precision(steps=40, chains=1024, temps=(1.0, 0.5, 0.3, 0.212)):
+    """Acceptance of the three sampler precisions on one environment build:
+    the +-J 32x32 instance of the hybrid workload, D = 16, from all-up, at
+    several temperatures (FP64 plain path, FP32 and BF16 batched path; the
+    operands of each are derived from the same FP64 environments)."""
+    import torch
+    from paper_2104_13264_amd import Sampler, FP64, FP32, BF16
+    from workloads import ea_pm, SEED
+    out = {"workload": "precision_ea32_D16", "chains": chains, "steps": steps, "rows": []}
+    for T in temps:
+        inst = ea_pm(32, 1.0 / T, 16, SEED + 7, chains=chains)
+        s = Sampler()
+        s.build_env(inst.Jh, inst.Jv, None, inst.beta, 16, FP64)
+        row = {"T": T, "degenerate_cuts": s.stats()["degenerate_cuts"]}
+        for name, prec in (("fp64", FP64), ("fp32", FP32), ("bf16", BF16)):
+            s.set_precision(prec)
+            state = s.init_state(chains)
+            s.stats(reset=True)
+            for t in range(steps):
+                s.mh_step(state, SEED, t)
+            st = s.stats()
+            row[name] = st["accepted"] / max(st["proposed"], 1)
+        torch.cuda.synchronize()
+        s.close()
+        out["rows"].append(row)
+        log(f"[bench] precision T={T}: acceptance fp64 {row['fp64']:.5f}, fp32 {row['fp32']:.5f}, "
+            f"bf16 {row['bf16']:.5f} (degenerate cuts {row['degenerate_cuts']})")
+    return out
+
+
 def run_delta(steps=40, n_inst=64, chains=30, prec=None, modes=(("tnmh", 0), ("tnmh+metropolis", 1)),
               fit_sweeps=0):
     """Equilibration test of Sec. 3, Eq. (Delta), on Gaussian spin glasses in
@@ -640,7 +670,7 @@ def main():
                     help="cut schedule of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
                     choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta",
-                             "periodic"],
+                             "periodic", "precision"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -660,6 +690,8 @@ def main():
             if args.fit_sweeps:
                 out["fp32_fit"] = run_delta(prec=FP32, fit_sweeps=args.fit_sweeps, modes=(("tnmh", 0),))
                 out["fp64_fit"] = run_delta(prec=FP64, fit_sweeps=args.fit_sweeps)
+        elif args.workload == "precision":
+            out = run_precision()
         elif args.workload == "periodic":
             out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts, sweeps=args.periodic_sweeps)
         else:
