@@ -675,7 +675,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler "
-              "shards by chains, see DESIGN.md", file=sys.stderr)
+              "shards by chains, one process per GPU, and only one GPU is measured here", file=sys.stderr)
         sys.exit(2)
     if args.workload != "ferro64":
         if args.workload == "ea_mix":
