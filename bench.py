@@ -384,6 +384,31 @@ def run_hybrid(steps=200, chains=1024, sweeps=1):
     return out
 
 
+def run_fitbuild(sweeps=(0, 1, 2), n_inst=64):
+    """Batched environment builds of the 64 Gaussian 32x32 instances of the
+    delta workload (T = 0.212, D = 16) by successive SVD and with 1 and 2
+    two-site variational sweeps per row: wall time and ln Z~ of instance 0."""
+    import torch
+    from paper_2104_13264_amd import Sampler, FP32
+    from workloads import ea_gauss_set
+    insts = ea_gauss_set(n=n_inst, chains=30)
+    out = {"workload": "fitbuild_ea_gauss32_T0.212_D16", "instances": n_inst, "rows": []}
+    for sw in sweeps:
+        s = Sampler()
+        s.set_compression(sw)
+        dicts = [dict(Jh=i.Jh, Jv=i.Jv, h=None, beta=i.beta, D=i.D, chains=i.chains) for i in insts]
+        s.build_env_multi(dicts, FP32)   # first build allocates
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lz = s.build_env_multi(dicts, FP32)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        out["rows"].append({"fit_sweeps": sw, "build_s": dt, "logZ_0": lz[0]})
+        log(f"[bench] fitbuild: {sw} sweeps, {n_inst} builds in {dt:.3f} s, ln Z~[0] = {lz[0]:.9f}")
+    return out
+
+
 def run_precision(steps=40, chains=1024, temps=(1.0, 0.5, 0.3, 0.212)):
     """Acceptance of the three sampler precisions on one environment build:
     the +-J 32x32 instance of the hybrid workload, D = 16, from all-up, at
@@ -670,7 +695,7 @@ def main():
                     help="cut schedule of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
                     choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta",
-                             "periodic", "precision"],
+                             "periodic", "precision", "fitbuild"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -690,6 +715,8 @@ def main():
             if args.fit_sweeps:
                 out["fp32_fit"] = run_delta(prec=FP32, fit_sweeps=args.fit_sweeps, modes=(("tnmh", 0),))
                 out["fp64_fit"] = run_delta(prec=FP64, fit_sweeps=args.fit_sweeps)
+        elif args.workload == "fitbuild":
+            out = run_fitbuild()
         elif args.workload == "precision":
             out = run_precision()
         elif args.workload == "periodic":
