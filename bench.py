@@ -116,19 +116,17 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1, tune_steps=0, tu
         t += mm
     s.stats(reset=True)
     E_series = torch.empty((steps, C), dtype=torch.float64, device=s.device)
-    nl = -(-steps // m)
+    # the timed steps in launches of m steps, the remainder in a last launch
+    launch_sizes = [m] * (steps // m) + ([steps % m] if steps % m else [])
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(nl)]
-    launch_sizes = []
+          for _ in launch_sizes]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     k = 0
-    for li in range(nl):
-        mm = min(m, steps - k)
+    for li, mm in enumerate(launch_sizes):
         ev[li][0].record(stream)
         block(warmup + k, mm)
         ev[li][1].record(stream)
-        launch_sizes.append(mm)
         for j in range(mm):
             accept(warmup + k, j)
             torch.mul(state["energy"], 1.0, out=E_series[k + j])   # an elementwise kernel, not a blit
@@ -136,15 +134,16 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1, tune_steps=0, tu
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     kern_ms = [a.elapsed_time(b) for a, b in ev]
-    full = [ms for ms, mm in zip(kern_ms, launch_sizes) if mm == m]
-    if full:
-        log(f"[bench] sampler launches: min {min(full):.3f} median {float(np.median(full)):.3f} "
-            f"max {max(full):.3f} ms ({len(full)} launches of {m} steps)")
+    for mm in sorted(set(launch_sizes), reverse=True):
+        ms = [t for t, z in zip(kern_ms, launch_sizes) if z == mm]
+        log(f"[bench] sampler launches of {mm} steps ({mm * C} proposals): {len(ms)} timed, "
+            f"min {min(ms):.3f} median {float(np.median(ms)):.3f} max {max(ms):.3f} ms")
     st = s.stats()
     E = E_series.cpu().numpy()
     s.close()
     return dict(wall=wall, accepted=st["accepted"], proposed=st["proposed"],
-                sampler_ms=float(np.mean(full if full else kern_ms)), steps_per_launch=m, variant=variant,
+                kern_ms=kern_ms, launch_sizes=launch_sizes,
+                sampler_ms=float(np.mean(kern_ms)), steps_per_launch=m, variant=variant,
                 build_s=build_s, logZ=logZ, E=E, near=st["near_threshold"],
                 clamps=st["clamps"]), env_state
 
@@ -742,11 +741,11 @@ def main():
 
     m = ahead_steps(C) if args.ahead is None else args.ahead
     res32, env_state = run_gpu(1, inst, args.steps, args.warmup, ahead=m,
-                               tune_steps=0 if args.ahead is not None else args.tune_steps,
+                               tune_steps=0 if args.ahead is not None else min(args.tune_steps, args.steps),
                                tune_cache=args.tune_cache)
     m = res32["steps_per_launch"]
     log(f"[bench] fp32 batched: {res32['wall']*1e3/args.steps:.3f} ms/step, "
-        f"sampler {res32['sampler_ms']:.3f} ms per launch of {m} steps, "
+        f"sampler launches of {res32['launch_sizes']} steps: {sum(res32['kern_ms']):.3f} ms in total, "
         f"acc {res32['accepted']}/{res32['proposed']}, env build {res32['build_s']:.2f} s")
     res64 = None
     if not args.no_plain:
@@ -756,13 +755,21 @@ def main():
 
     value = res32["accepted"] / res32["wall"]
     ms_per_step = res32["wall"] * 1e3 / args.steps
-    # algorithmic work of one sampler launch: per proposal and column, the
-    # right sweep multiplies the two D x D matrices G_c(+-1) into its vectors
-    # and the left sweep one D x D matrix: 3 * 2 D^2 flops; L^2 columns; a
-    # launch draws the proposals of `steps_per_launch` MH steps.
-    flops_launch = 6.0 * D * D * L * L * C * res32["steps_per_launch"]
-    achieved = flops_launch / (res32["sampler_ms"] * 1e-3)
-    traffic = measured_traffic(C * res32["steps_per_launch"], res32["variant"])
+    # Roofline of the sampler launches timed above (HIP events on the stream
+    # they run on), from the proposals they actually drew.  Algorithmic work
+    # per proposal, three counts:
+    #   12 D^2 L^2  the method's count: per site, the right environment with
+    #               its horizontal leg (8 D^2) and the drawing product (4 D^2)
+    #    6 D^2 L^2  the minimum: the horizontal bond contracted exactly, both
+    #               spins' right products (4 D^2) and the drawn spin's left
+    #               product (2 D^2)
+    #    8 D^2 L^2  what the kernel executes: both spins' left products
+    props = C * sum(res32["launch_sizes"])
+    kern_s = sum(res32["kern_ms"]) * 1e-3
+    flops = {k: f * D * D * L * L * props for k, f in (("12D2L2", 12.0), ("6D2L2", 6.0), ("8D2L2", 8.0))}
+    achieved = flops["12D2L2"] / kern_s
+    shapes = sorted(set(res32["launch_sizes"]))
+    traffic = measured_traffic(C * shapes[0], res32["variant"]) if len(shapes) == 1 else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -786,8 +793,12 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic,
                      "kernel": f"k_sampler_team<2,false,{res32['variant']}>",
-                     "flops_per_launch": flops_launch,
-                     "proposals_per_launch": C * res32["steps_per_launch"],
+                     "flop_count": "12 D^2 L^2 per proposal",
+                     "frac_6D2L2_minimum": flops["6D2L2"] / kern_s / PEAK_FP32_MFMA,
+                     "frac_8D2L2_executed": flops["8D2L2"] / kern_s / PEAK_FP32_MFMA,
+                     "launch_steps": res32["launch_sizes"],
+                     "proposals_timed": props,
+                     "kernel_ms_total": sum(res32["kern_ms"]),
                      "kernel_ms": res32["sampler_ms"]},
         "acceptance": res32["accepted"] / max(res32["proposed"], 1),
         "proposals_per_s": res32["proposed"] / res32["wall"],

@@ -14,6 +14,8 @@ int tn_fail(tn_ctx *ctx, int code, const std::string &msg) {
 
 int tn_ensure(tn_ctx *ctx, void **ptr, size_t *cap, size_t bytes) {
     if (bytes <= *cap && *ptr) return TN_OK;
+    if (ctx->capturing)   // no synchronisation or allocation inside a stream capture
+        return tn_fail(ctx, TN_ESTATE, "buffers not allocated: run the call once before capture");
     if (*ptr) {
         TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
         TN_HIP(ctx, hipFree(*ptr));
@@ -120,6 +122,7 @@ int check_prec(tn_ctx *ctx, int prec) {
 // Copy the couplings into context-owned buffers and record the instance.
 int set_instance(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                  const double *h, double beta, int D, int prec) {
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     ctx->building = false;   // a new instance abandons an open incremental build
     ++ctx->env_gen;
     if (Lx < 1 || Ly < 1) return tn_fail(ctx, TN_EINVAL, "Lx and Ly must be >= 1");
@@ -173,6 +176,17 @@ int need_env(tn_ctx *ctx) {
     if (!ctx) return TN_EINVAL;
     if (!ctx->has_env) return tn_fail(ctx, TN_ESTATE, "no environment: call tn_build_env first");
     return TN_OK;
+}
+
+// tn_sample after the common checks; tn_mh_step calls it while capturing
+int sample_impl(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
+                int8_t *spins, double *logq, double *energy) {
+    if (batch < 0) return tn_fail(ctx, TN_EINVAL, "batch < 0");
+    if (batch > 0 && (!spins || !logq || !energy))
+        return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
+    if (ctx->prec == TN_FP64)
+        return tn_run_fp64(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
+    return tn_run_mfma(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
 }
 
 }  // namespace
@@ -332,6 +346,7 @@ int tn_get_env(tn_ctx *ctx, double *env, int *dims, double *ell, double *logZ) {
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
     const size_t box = (size_t)2 * D * D;
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -355,6 +370,7 @@ int tn_set_precision(tn_ctx *ctx, int prec) {
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     if ((rc = check_prec(ctx, prec))) return rc;
     if ((rc = tn_make_operands(ctx, prec))) return rc;
     ctx->prec = prec;
@@ -383,12 +399,8 @@ int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t fir
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
-    if (batch < 0) return tn_fail(ctx, TN_EINVAL, "batch < 0");
-    if (batch > 0 && (!spins || !logq || !energy))
-        return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
-    if (ctx->prec == TN_FP64)
-        return tn_run_fp64(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
-    return tn_run_mfma(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
+    return sample_impl(ctx, batch, seed, step, first_id, spins, logq, energy);
 }
 
 int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, double *energy) {
@@ -396,6 +408,7 @@ int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, doub
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (batch < 0) return tn_fail(ctx, TN_EINVAL, "batch < 0");
     if (batch > 0 && (!spins || !logq || !energy))
         return tn_fail(ctx, TN_EINVAL, "NULL buffer");
@@ -403,6 +416,7 @@ int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, doub
     if (ctx->prec == TN_FP64) return tn_run_fp64(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
     return tn_run_mfma(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
 }
+
 
 int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *state_spins,
                double *state_logq, double *state_energy, uint8_t *accepted) {
@@ -426,7 +440,7 @@ int tn_mh_step(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step, int8_t *st
     }
     ctx->plogq = (double *)(ctx->pspins + spin_bytes);
     ctx->pE = ctx->plogq + chains;
-    if ((rc = tn_sample(ctx, chains, seed, step, 0, ctx->pspins, ctx->plogq, ctx->pE))) return rc;
+    if ((rc = sample_impl(ctx, chains, seed, step, 0, ctx->pspins, ctx->plogq, ctx->pE))) return rc;
     if ((rc = tn_launch_accept(ctx, chains, seed, step, ctx->pspins, ctx->plogq, ctx->pE,
                                state_spins, state_logq, state_energy, accepted)))
         return rc;
@@ -440,6 +454,7 @@ int tn_sample_steps(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (chains < 0 || nsteps < 1) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsteps < 1");
     if ((size_t)chains * nsteps > (size_t)INT32_MAX / 2)
         return tn_fail(ctx, TN_EINVAL, "chains * nsteps too large");
@@ -458,6 +473,7 @@ int tn_mh_run(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t step0
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (chains < 0 || nsteps < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsteps < 0");
     if (chains == 0 || nsteps == 0) return TN_OK;
     if (!state_spins || !state_logq || !state_energy || !accepted)
@@ -505,6 +521,7 @@ int tn_metropolis_sweeps(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, ui
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (chains < 0 || nsweeps < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsweeps < 0");
     if (nsweeps >= (1 << 18)) return tn_fail(ctx, TN_EINVAL, "nsweeps must be below 2^18");
     if ((long)ctx->Lx * ctx->Ly > 65536) return tn_fail(ctx, TN_EINVAL, "more than 65536 sites");
@@ -522,6 +539,7 @@ int tn_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (n < 0) return tn_fail(ctx, TN_EINVAL, "n < 0");
     if (n == 0) return TN_OK;
     if (!a || !b || !q) return tn_fail(ctx, TN_EINVAL, "NULL buffer");
@@ -536,6 +554,7 @@ int tn_mh_accept(tn_ctx *ctx, int chains, uint64_t seed, uint64_t step,
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (chains < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0");
     if (chains == 0) return TN_OK;
     if (!prop_spins || !prop_logq || !prop_energy || !state_spins || !state_logq ||
@@ -763,6 +782,7 @@ int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
     int rc;
     if ((rc = need_env(ctx))) return rc;
     ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     if ((ctx->Lx > 1 && !dJh) || (ctx->Ly > 1 && !dJv))
         return tn_fail(ctx, TN_EINVAL, "NULL gradient buffer");
     return tn_grad_device(ctx, nullptr, dJh, dJv, dbeta);
@@ -830,6 +850,7 @@ int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
 int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset) {
     (void)hipGetLastError();
     if (!ctx || !out) return TN_EINVAL;
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     unsigned long long c[CNT_N];
     TN_HIP(ctx, hipStreamSynchronize(ctx->stream));
     TN_HIP(ctx, hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));

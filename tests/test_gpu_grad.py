@@ -101,6 +101,14 @@ def test_autograd_function_matches_tn_grad_and_brute_force():
     # untruncated: d ln Z / d beta = -<E> exactly (brute force)
     cfg, E, _, lp = exact.brute_force(inst.Jh, inst.Jv, None, inst.beta)
     assert abs(float(gb) / 2.0 + float(np.dot(np.exp(lp), E))) < 1e-10
+    # the two-sided estimator behind the same function: tn_grad_two_sided
+    lz2 = log_z(Jh, Jv, beta, 8, estimator="two_sided")
+    tJh, tJv, tb = torch.autograd.grad(lz2, (Jh, Jv, beta))
+    eJh, eJv, eb = s.grad(two_sided=True)
+    assert torch.equal(tJh, eJh) and torch.equal(tJv, eJv) and float(tb) == eb
+    assert abs(float(tb) + float(np.dot(np.exp(lp), E))) < 1e-10
+    with pytest.raises(ValueError):
+        log_z(Jh, Jv, beta, 8, estimator="rebuilt")
     s.close()
 
 

@@ -140,3 +140,58 @@ def test_graph_capture_refuses_allocation():
     s.mh_step(a, 1, 0)   # eager works again
     stream.synchronize()
     s.close()
+
+
+def test_graph_capture_refuses_calls_other_than_mh_steps():
+    # Only MH steps may be captured: the other calls' random streams would not
+    # follow the replays' step shift, or they synchronise or allocate.  Each
+    # is refused (TN_ESTATE) without enqueuing work, and the captured steps
+    # still replay bitwise like the eager ones.  The calls go straight to the
+    # C ABI with buffers allocated before the capture.
+    import ctypes
+    from paper_2104_13264_amd import Sampler
+    from paper_2104_13264_amd.tnmh import lib, _ptr, _Stats
+    TN_ESTATE = -6
+    inst = random_instance(6, 7, 0.6, 4, seed=67)
+    stream = torch.cuda.Stream()
+    s = Sampler(stream=stream)
+    s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 4, FP32)
+    C = 24
+    with torch.cuda.stream(stream):
+        a = s.init_state(C)
+        b = clone(a)
+        sp, lq, E = s.empty_batch(2 * C)
+        q = torch.empty(C, dtype=torch.int32, device=s.device)
+        acc = torch.empty(2 * C, dtype=torch.uint8, device=s.device)
+        dJh = torch.empty((inst.Ly, inst.Lx - 1), dtype=torch.float64, device=s.device)
+        dJv = torch.empty((inst.Ly - 1, inst.Lx), dtype=torch.float64, device=s.device)
+    stream.synchronize()
+    s.mh_step(a, 5, 0)
+    s.mh_step(b, 5, 0)
+    L, ctx = lib(), s._ctx
+    st = (_ptr(b["spins"]), _ptr(b["logq"]), _ptr(b["energy"]))
+    db = ctypes.c_double()
+    stats = _Stats()
+    refused = {
+        "tn_sample": lambda: L.tn_sample(ctx, C, 5, 9, 0, _ptr(sp), _ptr(lq), _ptr(E)),
+        "tn_sample_steps": lambda: L.tn_sample_steps(ctx, C, 2, 5, 9, 0, _ptr(sp), _ptr(lq), _ptr(E)),
+        "tn_eval_logq": lambda: L.tn_eval_logq(ctx, C, _ptr(a["spins"]), _ptr(lq), _ptr(E)),
+        "tn_mh_accept": lambda: L.tn_mh_accept(ctx, C, 5, 9, _ptr(sp), _ptr(lq), _ptr(E), *st, _ptr(acc)),
+        "tn_mh_run": lambda: L.tn_mh_run(ctx, C, 2, 5, 9, *st, _ptr(acc), None),
+        "tn_metropolis_sweeps": lambda: L.tn_metropolis_sweeps(ctx, C, 1, 5, 9, *st),
+        "tn_link_overlap": lambda: L.tn_link_overlap(ctx, C, _ptr(a["spins"]), _ptr(b["spins"]), _ptr(q)),
+        "tn_stats": lambda: L.tn_stats(ctx, ctypes.byref(stats), 0),
+        "tn_grad": lambda: L.tn_grad(ctx, _ptr(dJh), _ptr(dJv), ctypes.byref(db)),
+    }
+    s.graph_begin()
+    s.mh_step(a, 5, 1)
+    codes = {name: call() for name, call in refused.items()}
+    s.graph_end_and_replay(2)
+    log(f"[graph] return codes while capturing: {codes}")
+    assert all(rc == TN_ESTATE for rc in codes.values()), codes
+    for j in range(2):
+        s.mh_step(b, 5, 1 + j)
+    stream.synchronize()
+    for k in ("spins", "logq", "energy", "accepted"):
+        assert torch.equal(a[k], b[k])
+    s.close()
