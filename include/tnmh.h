@@ -448,7 +448,7 @@ typedef struct {
     uint64_t near_threshold;/* draws with |u - p+| < 1e-6 */
     uint64_t accepted;      /* accepted MH moves since the last reset */
     uint64_t proposed;      /* MH proposals since the last reset */
-    uint64_t degenerate_cuts;/* truncations with s_chi-1 - s_chi < 1e-12 s_0 */
+    uint64_t degenerate_cuts;/* cuts (successive SVD and two-site fit) with s_chi-1 - s_chi < 1e-12 s_0 */
     double   logZ;          /* ln Z~ of the current environment */
     double   env_build_ms;  /* wall time of the last tn_build_env */
     uint64_t metropolis_flips; /* spins flipped by tn_metropolis_sweeps */

@@ -80,12 +80,21 @@ def qr_sweep(X):
     return X, lognorm
 
 
-def compress(X, D):
+def degenerate_cut(S, chi):
+    """A truncation that keeps chi of the descending singular values S is
+    degenerate when the last kept and the first dropped one are tied to
+    1e-12 of the largest: which vectors are kept is then decided by rounding
+    (reading: parity is not defined for such a cut; it is counted)."""
+    return chi < S.shape[0] and (S[chi - 1] - S[chi]) < 1e-12 * S[0]
+
+
+def compress(X, D, degen=None):
     """Successive-SVD compression of an MPS to bond D (App. A; reading above).
 
     Returns (tensors, ln of the removed norm, list of truncated bonds).  A bond
     c (between columns c-1 and c) is "truncated" when chi < min(rows, cols) of
-    the SVD taken at column c.
+    the SVD taken at column c.  degen (a list, optional) receives one entry per
+    degenerate cut.
     """
     X, lognorm = qr_sweep(X)
     Lx = len(X)
@@ -97,6 +106,8 @@ def compress(X, D):
         chi = min(D, S.shape[0])
         if chi < S.shape[0]:
             truncated.append(c)
+        if degen is not None and degenerate_cut(S, chi):
+            degen.append(c)
         X[c] = Vt[:chi].reshape(chi, u, b)
         X[c - 1] = np.einsum('aub,bk->auk', X[c - 1], U[:, :chi] * S[:chi])
     m = np.linalg.norm(X[0])
@@ -104,26 +115,27 @@ def compress(X, D):
     return X, lognorm + np.log(m), truncated
 
 
-def fit_two_site(Xh, psi, D, sweeps):
+def fit_two_site(Xh, psi, D, sweeps, degen=None):
     """Two-site variational sweeps fitting psi (right-canonical, centre at
     column 0) to Xh; returns the fitted, unnormalised psi (right-canonical,
-    centre at column 0)."""
+    centre at column 0).  degen (a list, optional) receives one entry per
+    degenerate two-site cut."""
     Lx = len(Xh)
     psi = [p.copy() for p in psi]
     if Lx == 1:                       # one site: the fit is Xh itself
         return [Xh[0].copy()]
     one = np.ones((1, 1))
 
+    # Each contraction is written as the one sum it defines; numpy picks the
+    # order in which its pairs are multiplied (optimize=True).
     def right_env(c, R):              # R_c[b_psi, B] from R_{c+1}
-        return np.einsum('aub,Aub->aA', psi[c], np.einsum('AuB,bB->Aub', Xh[c], R))
+        return np.einsum('aub,AuB,bB->aA', psi[c], Xh[c], R, optimize=True)
 
     def left_env(c, L):               # L_{c+1}[a_psi, A] from L_c
-        return np.einsum('aub,auB->bB', psi[c], np.einsum('aA,AuB->auB', L, Xh[c]))
+        return np.einsum('aub,aA,AuB->bB', psi[c], L, Xh[c], optimize=True)
 
-    def theta(L, c, R):               # Theta[a, u, b, v] = L X^_c X^_{c+1} R, pair by pair
-        t = np.einsum('aA,AuM->auM', L, Xh[c])
-        t = np.einsum('auM,MvB->auvB', t, Xh[c + 1])
-        return np.einsum('auvB,bB->aubv', t, R)
+    def theta(L, c, R):               # Theta[a, u, b, v] = L X^_c X^_{c+1} R
+        return np.einsum('aA,AuM,MvB,bB->aubv', L, Xh[c], Xh[c + 1], R, optimize=True)
 
     for _ in range(sweeps):
         R = [None] * (Lx + 1)
@@ -136,6 +148,8 @@ def fit_two_site(Xh, psi, D, sweeps):
             a, u, b, v = Th.shape
             U, S, Vt = np.linalg.svd(Th.transpose(0, 1, 3, 2).reshape(a * u, v * b), full_matrices=False)
             chi = min(D, S.shape[0])
+            if degen is not None and degenerate_cut(S, chi):
+                degen.append(c)
             psi[c] = U[:, :chi].reshape(a, u, chi)
             psi[c + 1] = (S[:chi, None] * Vt[:chi]).reshape(chi, v, b)
             L = left_env(c, L)
@@ -149,20 +163,22 @@ def fit_two_site(Xh, psi, D, sweeps):
             a, u, b, v = Th.shape
             U, S, Vt = np.linalg.svd(Th.transpose(0, 1, 3, 2).reshape(a * u, v * b), full_matrices=False)
             chi = min(D, S.shape[0])
+            if degen is not None and degenerate_cut(S, chi):
+                degen.append(c)
             psi[c + 1] = Vt[:chi].reshape(chi, v, b)
             psi[c] = (U[:, :chi] * S[:chi]).reshape(a, u, chi)
             R = right_env(c + 1, R)
     return psi
 
 
-def compress_variational(X, D, sweeps):
+def compress_variational(X, D, sweeps, degen=None):
     """Successive SVD followed by `sweeps` two-site variational sweeps (reading
     above).  Returns (tensors, ln of the removed norm, truncated bonds of the
-    successive-SVD start)."""
+    successive-SVD start).  degen as in compress, for every cut taken."""
     Xh, lognorm = qr_sweep(X)
-    psi, lm, truncated = compress(Xh, D)
+    psi, lm, truncated = compress(Xh, D, degen)
     psi[0] = psi[0] * np.exp(lm)      # Xh ~ psi with the norm in the centre
-    psi = fit_two_site(Xh, psi, D, sweeps)
+    psi = fit_two_site(Xh, psi, D, sweeps, degen)
     m = np.linalg.norm(psi[0])
     psi[0] = psi[0] / m
     return psi, lognorm + np.log(m), truncated
@@ -199,13 +215,14 @@ def build_envs(model, D, fit_sweeps=0):
     env = [None] * (Ly + 1)
     ell = np.zeros(Ly + 1)
     trunc = [[] for _ in range(Ly + 1)]
+    degen = [[] for _ in range(Ly + 1)]
     env[Ly] = trivial_env(Lx)
     for k in range(Ly - 1, 0, -1):
         X = apply_row(model, k, env[k + 1])
         if fit_sweeps > 0:
-            env[k], ell[k], trunc[k] = compress_variational(X, D, fit_sweeps)
+            env[k], ell[k], trunc[k] = compress_variational(X, D, fit_sweeps, degen[k])
         else:
-            env[k], ell[k], trunc[k] = compress(X, D)
+            env[k], ell[k], trunc[k] = compress(X, D, degen[k])
     lo, sign = row_overlap(model, 0, env[1])
     return dict(env=env, ell=ell, trunc=trunc, logZ=ell.sum() + lo, sign=sign,
-                D=D)
+                D=D, degenerate=[len(d) for d in degen])

@@ -757,6 +757,10 @@ __device__ int fit_split(const double *th, int ca, int cb, bool lr, double *W, d
     }
     __syncthreads();
     const int chi = min(D, min(rows, len));
+    // a cut tied to 1e-12 of the largest singular value is counted (rounding
+    // decides which vectors are kept), as in the successive-SVD sweep
+    if (threadIdx.x == 0 && chi < min(rows, len) && sv[idx[chi - 1]] - sv[idx[chi]] < 1e-12 * sv[idx[0]])
+        atomicAdd(&counters[CNT_DEGEN], 1ull);
     // orthonormal factor O[k][e] = W'[idx k][e] / s_k (length len); coefficients
     // C[i][k] = sum_e Wo[i][e] O[k][e] (rows x chi)
     for (int t = threadIdx.x; t < chi * len; t += blockDim.x) {

@@ -3,13 +3,18 @@ the oracle (oracle/bmps.py: compress_variational).
 
 ln Z~ of fitted builds within 1e-9 relative of the oracle's fitted builds
 (single, incremental and batched builds; 1 and 3 sweeps; bond dimensions of
-every kernel class up to 32), FP64 proposals on fitted environments bitwise
+every kernel class up to 32); FP64 proposals on fitted environments bitwise
 with the oracle's sampler on its own fitted environments (draws nearer than
-1e-6 to a threshold excluded), ln q to 1e-9 |ln Z~| absolute; a periodic
-FP64 chain on fitted
-builds follows the oracle; the frozen derivative is refused after a fitted
-build while the two-sided estimate runs; D > 32 and sweep counts outside
-0..16 are refused.
+1e-6 to a threshold excluded; 1e-4 on builds with degenerate cuts) and their
+ln q within 1e-9 relative.  A build
+with degenerate cuts (the last kept and first dropped singular values tied to
+1e-12 of the largest; the oracle and the GPU count them) has no defined
+parity, since rounding picks the kept vectors: its proposals are held instead
+to ten times the change of the oracle's own ln q under a one-ulp change of
+every coupling (the instance's conditioning), with 1e-9 relative as the floor.
+A periodic FP64 chain on fitted builds follows the oracle; the frozen
+derivative is refused after a fitted build while the two-sided estimate
+runs; D > 32 and sweep counts outside 0..16 are refused.
 """
 import numpy as np
 import pytest
@@ -43,6 +48,18 @@ CASES = [  # (name, instance, D, sweeps)
 ]
 
 
+def ulp_spread(inst, D, sw, spins, logq):
+    """|change of the oracle's ln q| of the given configurations when every
+    coupling moves by one ulp up, and one ulp down (the larger of the two)."""
+    out = np.zeros(len(logq))
+    for f in (1.0 + 2.0 ** -52, 1.0 - 2.0 ** -53):
+        m = model_of(inst)
+        m2 = type(m)(inst.Jh * f, inst.Jv * f, inst.h, inst.beta)
+        ev = sampler.eval_logq(m2, bmps.build_envs(m2, D, fit_sweeps=sw), spins)
+        out = np.maximum(out, np.abs(ev["logq"] - logq))
+    return out
+
+
 @pytest.mark.parametrize("name,mk,D,sw", CASES, ids=[c[0] for c in CASES])
 def test_fitted_logZ_and_sampler_match_oracle(name, mk, D, sw):
     from paper_2104_13264_amd import Sampler
@@ -53,20 +70,30 @@ def test_fitted_logZ_and_sampler_match_oracle(name, mk, D, sw):
     s = Sampler()
     s.set_compression(sw)
     lz = s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, D, FP64)
-    assert abs(lz - ref["logZ"]) <= TOL_LOGZ_FP64 * abs(ref["logZ"]) + 1e-12
-    assert s.stats()["clamps"] == 0
+    st = s.stats()
+    degen_gpu, degen_ref = st["degenerate_cuts"], sum(ref["degenerate"])
+    assert st["clamps"] == 0
     B, seed, step = 29, 4242, 3
     want = sampler.sample(m, ref, B, seed, step=step)
     sp, lq, E = s.sample(B, seed, step=step)
     sp, lq = sp.cpu().numpy(), lq.cpu().numpy()
-    ok = want["min_gap"] >= NEAR_FP64
+    # with degenerate cuts the conditionals themselves are defined only to the
+    # instance's conditioning: spins are compared where the draw was farther
+    # than 1e-4 from its threshold
+    degenerate = bool(degen_gpu or degen_ref)
+    ok = want["min_gap"] >= (1e-4 if degenerate else NEAR_FP64)
     assert np.array_equal(sp[ok], want["spins"][ok])
-    # q is a ratio of contractions of the environments whose ln Z~ agrees to
-    # 1e-9 relative: ln q is held to that absolute error (the fit iterates on
-    # near-degenerate cuts at low temperature, e.g. 2.5e-7 on |ln q| ~ 36 at
-    # 32x32, T = 0.212, where ln Z~ = 6178)
-    tol = TOL_LOGZ_FP64 * max(abs(ref["logZ"]), 1.0)
-    assert np.all(np.abs(lq[ok] - want["logq"][ok]) <= tol)
+    dev = np.abs(lq[ok] - want["logq"][ok])
+    tol = TOL_LOGZ_FP64 * np.abs(want["logq"][ok])
+    if degenerate:
+        # no defined parity for these rows: the instance's own conditioning
+        tol = np.maximum(tol, 10.0 * ulp_spread(inst, D, sw, want["spins"][ok], want["logq"][ok]))
+    log(f"[fit] {name}: degenerate cuts gpu {degen_gpu} oracle {degen_ref}; "
+        f"ln Z~ rel {abs(lz - ref['logZ']) / abs(ref['logZ']):.2e}; ln q rel max "
+        f"{np.max(dev / np.abs(want['logq'][ok])):.2e}, bound rel max {np.max(tol / np.abs(want['logq'][ok])):.2e}, "
+        f"{int(ok.sum())}/{B} proposals compared")
+    assert abs(lz - ref["logZ"]) <= TOL_LOGZ_FP64 * abs(ref["logZ"]) + 1e-12
+    assert np.all(dev <= tol)
     s.close()
 
 
