@@ -153,6 +153,27 @@ int tn_set_compression(tn_ctx *ctx, int fit_sweeps);
 int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
               int8_t *spins, double *logq, double *energy);
 
+/* tn_sample for callers that cannot allocate device memory: code under HIP
+ * graph capture of their own, tight serving loops, harnesses that forbid
+ * hipMalloc.  Arguments, proposals (bitwise those of tn_sample with the same
+ * arguments), errors and ownership as in tn_sample; the call allocates and
+ * frees nothing (no hipMalloc, hipFree or allocating library routine).  The
+ * sampler's scratch (the per-proposal right-environment tiles of the rows in
+ * flight) comes from a fixed 64 MiB device array inside the library instead
+ * of a context allocation; each GPU the library runs on holds its own copy
+ * until the process ends.  Need: FP32/BF16 32 * Lx * Dp * (batch rounded up
+ * to 128) bytes (Dp = D rounded up to 16), FP64 16 * Lx * D * batch bytes;
+ * e.g. 4096 proposals of a 64-wide lattice at D = 32 in FP32.  A larger batch
+ * fails with TN_EINVAL and a message giving both sizes.  Every call on a GPU
+ * shares that GPU's array and leaves its contents there; nothing in it needs
+ * to start at zero (a call reads only what it wrote).  Calls that overlap in
+ * time on one GPU (on different streams, or from different contexts) race on
+ * the array: the caller serialises them.  The context's device must be
+ * current (TN_EINVAL otherwise); TN_EHIP if the array's address could not be
+ * taken when the context was created. */
+int tn_sample_noalloc(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
+                      int8_t *spins, double *logq, double *energy);
+
 /* ln q(s) and H(s) of given configurations by exactly the arithmetic of
  * tn_sample (the forced-spin mode of the same kernels).
  *   spins (dev, int8 [batch][Ly][Lx]), logq, energy (dev, fp64 [batch]) */

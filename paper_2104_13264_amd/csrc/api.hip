@@ -4,8 +4,45 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
+
+// Scratch of tn_sample_noalloc: a fixed device array of the library (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never uses the array's name as an address: tn_create takes the address of
+// the current device's copy once per device (hipGetSymbolAddress) and every
+// later use goes through that pointer.
+constexpr size_t TN_NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[TN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int TN_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[TN_MAX_DEVICES] = {};
+hipError_t g_scratch_err[TN_MAX_DEVICES] = {};
+bool g_scratch_done[TN_MAX_DEVICES] = {};
+
+// The address of the current device's scratch copy, looked up on the first
+// call for that device; nullptr (and the lookup's error) if it failed.
+void *noalloc_scratch(int device, hipError_t *err) {
+    if (device < 0 || device >= TN_MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_done[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_err[device] = e;
+        g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+        if (e != hipSuccess) (void)hipGetLastError();
+        g_scratch_done[device] = true;
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 int tn_fail(tn_ctx *ctx, int code, const std::string &msg) {
     if (ctx) ctx->err = msg;
@@ -211,6 +248,12 @@ int tn_create(tn_ctx **out, void *hip_stream) {
         delete ctx;
         return TN_EHIP;
     }
+    // the no-allocation sampler's scratch on this device (looked up once per
+    // device, with the device current); a failed lookup only disables
+    // tn_sample_noalloc, which reports it
+    hipError_t se = hipSuccess;
+    ctx->noalloc_scr = noalloc_scratch(ctx->device, &se);
+    ctx->noalloc_err = (int)se;
     *out = ctx;
     return TN_OK;
 }
@@ -403,6 +446,36 @@ int tn_sample(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t fir
     return sample_impl(ctx, batch, seed, step, first_id, spins, logq, energy);
 }
 
+int tn_sample_noalloc(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t first_id,
+                      int8_t *spins, double *logq, double *energy) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
+    if (batch < 0) return tn_fail(ctx, TN_EINVAL, "batch < 0");
+    if (batch == 0) return TN_OK;
+    if (!spins || !logq || !energy) return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
+    if (!ctx->noalloc_scr)
+        return tn_fail(ctx, TN_EHIP, std::string("address of the fixed scratch not available: ") +
+                                         hipGetErrorString((hipError_t)ctx->noalloc_err));
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+        return tn_fail(ctx, TN_EINVAL, "the context's device must be current");
+    const size_t need = ctx->prec == TN_FP64 ? tn_fp64_scratch_bytes(ctx, batch)
+                                             : tn_mfma_scratch_bytes(ctx, batch);
+    if (need > TN_NOALLOC_SCRATCH_BYTES)
+        return tn_fail(ctx, TN_EINVAL, "tn_sample_noalloc: " + std::to_string(batch) +
+                                           " proposals need " + std::to_string(need) +
+                                           " bytes of scratch, above its fixed " +
+                                           std::to_string(TN_NOALLOC_SCRATCH_BYTES) + " bytes");
+    if (ctx->prec == TN_FP64)
+        return tn_run_fp64(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy,
+                           ctx->noalloc_scr);
+    return tn_run_mfma(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy, -1,
+                       ctx->noalloc_scr);
+}
+
 int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, double *energy) {
     (void)hipGetLastError();
     int rc;
@@ -589,6 +662,8 @@ int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, do
         k->device = ctx->device;
         k->dstep = ctx->dstep;   // the instances follow the batched context's step base
         k->own_dstep = false;
+        k->noalloc_scr = ctx->noalloc_scr;   // same device, same fixed scratch
+        k->noalloc_err = ctx->noalloc_err;
         ctx->kids.push_back(k);
         if (hipMalloc((void **)&k->counters, CNT_N * sizeof(unsigned long long)) != hipSuccess ||
             hipMalloc((void **)&k->scal, 16 * sizeof(double)) != hipSuccess ||

@@ -86,6 +86,8 @@ struct tn_ctx {
     double *wbuf = nullptr;   // global work buffers when LDS is too small
     double *scal = nullptr;   // small device scalars (top overlap result ...)
     uint64_t *dstep = nullptr;  // device step base added to every MH step (graph replays)
+    void *noalloc_scr = nullptr; // this device's fixed scratch of tn_sample_noalloc (not owned)
+    int noalloc_err = 0;         // hipError_t of its address lookup
     bool own_dstep = true;      // false for the instances of a batched context
 
     // batched uneven instances (tn_build_env_multi): one child context each
@@ -264,6 +266,11 @@ inline size_t tn_mfma_scratch_bytes(const tn_ctx *ctx, int batch) {
     const int units = ((batch + 127) / 128) * 8;
     return (size_t)units * ctx->Lx * 2 * (size_t)ctx->Dp * 16 * sizeof(float);
 }
+// Scratch bytes of the plain fp64 sampler: per proposal both spins' right
+// environments of every column of the row in flight.
+inline size_t tn_fp64_scratch_bytes(const tn_ctx *ctx, int batch) {
+    return (size_t)batch * ctx->Lx * 2 * ctx->D * sizeof(double);
+}
 // Launch variants of the batched sampler for bond class NT = Dp / 16 (same
 // arithmetic, different launch shape; sampler_mfma.hip).
 constexpr int tn_team_variants(int NT) { return NT <= 2 ? 3 : 1; }
@@ -291,13 +298,16 @@ void tn_multi_groups(tn_ctx *ctx, std::vector<tn_samp_desc> &sd, std::vector<tn_
 
 // Samplers: proposal j of a launch has id first_id + j % per_step and MH step
 // step0 + j / per_step.
+// scr: the sampler's scratch (at least tn_fp64_scratch_bytes or
+// tn_mfma_scratch_bytes), or nullptr for the context's own buffer, allocated
+// or grown as needed.
 int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
-                double *energy);
+                double *energy, void *scr = nullptr);
 // variant: launch variant of the batched sampler, -1 for the context's
 int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
-                double *energy, int variant = -1);
+                double *energy, int variant = -1, void *scr = nullptr);
 
 // Metropolis sweeps of `chains` states in place (metropolis.hip)
 int tn_launch_metropolis(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step, int8_t *spins);

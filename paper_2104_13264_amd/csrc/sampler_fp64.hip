@@ -216,13 +216,16 @@ int launch_rows(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 }  // namespace
 
 int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
-                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy) {
+                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy,
+                void *scr) {
     if (batch == 0) return TN_OK;
     if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
-    const size_t need = (size_t)batch * ctx->Lx * 2 * ctx->D * sizeof(double);
     int rc;
-    if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, need))) return rc;
-    double *g = (double *)ctx->gscr;
+    if (!scr) {
+        if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, tn_fp64_scratch_bytes(ctx, batch)))) return rc;
+        scr = ctx->gscr;
+    }
+    double *g = (double *)scr;
     int T = 1;
     while (T < ctx->D) T <<= 1;
     switch (T) {

@@ -697,15 +697,19 @@ int dispatch_nt(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq, d
 }  // namespace
 
 int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
-                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy, int variant) {
+                uint64_t first_id, int8_t *spins, bool eval, double *logq, double *energy, int variant,
+                void *scr) {
     if (batch == 0) return TN_OK;
     if (ctx->Lx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
     if (variant < 0) variant = tn_ctx_variant(ctx);
     if (variant >= tn_team_variants(ctx->Dp / 16)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     int rc;
-    if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, tn_mfma_scratch_bytes(ctx, batch)))) return rc;
-    float *g = (float *)ctx->gscr;
+    if (!scr) {
+        if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, tn_mfma_scratch_bytes(ctx, batch)))) return rc;
+        scr = ctx->gscr;
+    }
+    float *g = (float *)scr;
     if (ctx->prec == TN_BF16)
         return dispatch_nt<true>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
     return dispatch_nt<false>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);

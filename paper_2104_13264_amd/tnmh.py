@@ -67,6 +67,7 @@ def lib():
         "tn_set_instance": (i, [vp, i]),
         "tn_set_compression": (i, [vp, i]),
         "tn_sample": (i, [vp, i, u64, u64, u64, vp, vp, vp]),
+        "tn_sample_noalloc": (i, [vp, i, u64, u64, u64, vp, vp, vp]),
         "tn_eval_logq": (i, [vp, i, vp, vp, vp]),
         "tn_mh_step": (i, [vp, i, u64, u64, vp, vp, vp, vp]),
         "tn_sample_steps": (i, [vp, i, i, u64, u64, u64, vp, vp, vp]),
@@ -110,7 +111,7 @@ def exported_symbols():
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
             "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
             "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap",
-            "tn_set_compression", "tn_periodic_sweeps"]
+            "tn_set_compression", "tn_periodic_sweeps", "tn_sample_noalloc"]
 
 
 def _ptr(t):
@@ -229,6 +230,14 @@ class Sampler:
         s, lq, E = out if out is not None else self.empty_batch(batch)
         self._check(lib().tn_sample(self._ctx, int(batch), int(seed), int(step), int(first_id),
                                     _ptr(s), _ptr(lq), _ptr(E)))
+        return s, lq, E
+
+    def sample_noalloc(self, batch, seed, step=0, first_id=0, out=None):
+        """sample() through tn_sample_noalloc: the library allocates nothing
+        (the caller passes the output buffers in `out`)."""
+        s, lq, E = out if out is not None else self.empty_batch(batch)
+        self._check(lib().tn_sample_noalloc(self._ctx, int(batch), int(seed), int(step), int(first_id),
+                                            _ptr(s), _ptr(lq), _ptr(E)))
         return s, lq, E
 
     def sample_steps(self, chains, nsteps, seed, step0=0, first_id=0, out=None):
