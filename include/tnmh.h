@@ -326,6 +326,30 @@ int tn_graph_end_and_replay(tn_ctx *ctx, int n_replays);
  * buffers or beta*J = 0 on a bond.  Synchronises the stream. */
 int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
 
+/* The frozen contraction whose derivative tn_grad takes, evaluated at other
+ * couplings, so that tn_grad can be checked by central finite differences
+ * (Sec. 4 derives energies from derivatives of the approximate
+ * contraction): ln Z~_frozen(J', h', beta') =
+ * ln <top| P_1 TM_1 P_2 TM_2 ... P_{Ly-1} TM_{Ly-1} |.>, the transfer
+ * matrices TM_k built from the given couplings and each P_k the orthogonal
+ * projector onto the span the current build kept at its leftmost truncated
+ * column (the identity where it truncated nothing).  At the build's own
+ * couplings it equals ln Z~.  n coupling sets are evaluated as one batched
+ * build (one workgroup per set and row), each an exact recompression of the
+ * projected product (no further truncation).
+ *   Jh, Jv, h: host arrays of n device pointers (fp64, layouts of
+ *     tn_build_env on this context's lattice); h may be NULL, as may its
+ *     entries (zero field)
+ *   beta (host, fp64 [n]); logZ_out (host, fp64 [n]) receives the values
+ * The context keeps one environment stack per set between calls (about
+ * Ly * Lx * 2 D^2 doubles each).  Errors: TN_ESTATE without an environment
+ * built by tn_build_env with successive SVD (tn_set_env and fitted builds
+ * have no recorded cuts) or while capturing; TN_EINVAL for n < 1, NULL
+ * arrays or a non-finite beta; TN_ENONPOS if a value is not positive.
+ * Synchronises the stream. */
+int tn_logz_frozen(tn_ctx *ctx, int n, const double *const *Jh, const double *const *Jv,
+                   const double *const *h, const double *beta, double *logZ_out);
+
 /* Two-sided estimate of d ln Z / dJ and d ln Z / d beta, i.e. of beta times
  * the bond correlations and of minus the mean energy (Sec. 4 compares energies
  * from derivatives of the approximate contraction with sampled ones).  Every

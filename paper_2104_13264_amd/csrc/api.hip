@@ -130,10 +130,15 @@ void free_all(tn_ctx *ctx) {
         ctx->flip = nullptr;
     }
     ctx->kids.clear();
+    for (tn_ctx *k : ctx->fkids) {
+        free_all(k);
+        delete k;
+    }
+    ctx->fkids.clear();
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
                     ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters,
-                    ctx->cst,   ctx->gradscr, ctx->descs, ctx->fbuf,
+                    ctx->cst,   ctx->gradscr, ctx->descs, ctx->fbuf, ctx->pscr,
                     ctx->own_dstep ? (void *)ctx->dstep : nullptr};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
@@ -920,6 +925,57 @@ int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
         ctx->flip_gen = ctx->env_gen;
     }
     return tn_grad_device(ctx, ctx->flip, dJh, dJv, dbeta);
+}
+
+int tn_logz_frozen(tn_ctx *ctx, int n, const double *const *Jh, const double *const *Jv,
+                   const double *const *h, const double *beta, double *logZ_out) {
+    (void)hipGetLastError();
+    int rc;
+    if ((rc = need_env(ctx))) return rc;
+    ctx->err.clear();
+    if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
+    if (!ctx->has_cst)
+        return tn_fail(ctx, TN_ESTATE, "the frozen contraction needs an environment built by tn_build_env "
+                                       "with successive SVD");
+    if (n < 1 || !beta || !logZ_out) return tn_fail(ctx, TN_EINVAL, "need n >= 1, beta and logZ_out");
+    const int Lx = ctx->Lx, Ly = ctx->Ly;
+    if ((Lx > 1 && !Jh) || (Ly > 1 && !Jv)) return tn_fail(ctx, TN_EINVAL, "Jh or Jv is NULL");
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(beta[i])) return tn_fail(ctx, TN_EINVAL, "beta must be finite");
+        if ((Lx > 1 && !Jh[i]) || (Ly > 1 && !Jv[i]))
+            return tn_fail(ctx, TN_EINVAL, "coupling set " + std::to_string(i) + " has a NULL array");
+    }
+    // one context per evaluation (kept for later calls), built together with
+    // the projectors of this context's build
+    while ((int)ctx->fkids.size() < n) {
+        tn_ctx *k = new (std::nothrow) tn_ctx();
+        if (!k) return tn_fail(ctx, TN_ENOMEM, "out of host memory");
+        k->stream = ctx->stream;
+        k->device = ctx->device;
+        ctx->fkids.push_back(k);
+        if (hipMalloc((void **)&k->counters, CNT_N * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc((void **)&k->scal, 16 * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&k->dstep, sizeof(uint64_t)) != hipSuccess ||
+            hipMalloc((void **)&k->xdims, 4096 * sizeof(int)) != hipSuccess ||
+            hipMemsetAsync(k->counters, 0, CNT_N * sizeof(unsigned long long), ctx->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return tn_fail(ctx, TN_ENOMEM, "allocation for the frozen evaluations failed");
+        }
+    }
+    std::vector<tn_ctx *> ks(ctx->fkids.begin(), ctx->fkids.begin() + n);
+    for (int i = 0; i < n; ++i) {
+        tn_ctx *k = ks[i];
+        k->err.clear();
+        k->fit_sweeps = 0;
+        k->proj_src = ctx;
+        if ((rc = set_instance(k, Lx, Ly, Lx > 1 ? Jh[i] : nullptr, Ly > 1 ? Jv[i] : nullptr,
+                               h ? h[i] : nullptr, beta[i], ctx->D, TN_FP64)))
+            return tn_fail(ctx, rc, "coupling set " + std::to_string(i) + ": " + k->err);
+    }
+    std::string e;
+    if ((rc = tn_env_build_many(ks.data(), n, ctx->stream, &e))) return tn_fail(ctx, rc, e);
+    for (int i = 0; i < n; ++i) logZ_out[i] = ks[i]->logZ;
+    return TN_OK;
 }
 
 int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset) {

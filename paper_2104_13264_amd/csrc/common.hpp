@@ -87,6 +87,10 @@ struct tn_ctx {
     double *scal = nullptr;   // small device scalars (top overlap result ...)
     uint64_t *dstep = nullptr;  // device step base added to every MH step (graph replays)
     void *noalloc_scr = nullptr; // this device's fixed scratch of tn_sample_noalloc (not owned)
+    const tn_ctx *proj_src = nullptr; // frozen evaluation: the build whose projectors it applies
+    double *pscr = nullptr;     // its projection scratch (8 D^2 doubles)
+    size_t pscr_cap = 0;
+    std::vector<tn_ctx *> fkids;     // contexts of tn_logz_frozen's evaluations
     int noalloc_err = 0;         // hipError_t of its address lookup
     bool own_dstep = true;      // false for the instances of a batched context
 
@@ -171,6 +175,14 @@ struct tn_env_desc {
     double *scal;
     unsigned long long *counters;
     double *fbuf;         // the variational sweeps' scratch (fit > 0)
+    // frozen contraction (tn_logz_frozen): after the MPO-MPS product of row
+    // k, project onto the span the build of penv kept at its leftmost
+    // truncated column pcst[k] (nothing where pcst[k] < 0); pscr: 8 D^2
+    // doubles of scratch.  penv == nullptr: an ordinary build.
+    const double *penv;
+    const int *pdims;
+    const int *pcst;
+    double *pscr;
 };
 // Builds the environments of n instances together (one workgroup per
 // instance and row step); fills each ctx's logZ.  ctxs[i] must have its

@@ -465,7 +465,7 @@ constexpr int FIT_DIMS = 1024;
 // later Z = U S and Y = X_{c-1} Z.  QLDS: QA and QB in LDS (D <= 32);
 // otherwise they are in global `gwork` and only W sits in LDS.
 template <bool QLDS>
-__device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
+__device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds, double lognorm0) {
     const int Lx = dsc.Lx, D = dsc.D;
     double *xbox = dsc.xbox, *env = dsc.env, *ell = dsc.ell, *gwork = dsc.wbuf;
     int *xdims = dsc.xdims, *dims = dsc.dims, *cst = dsc.cst;
@@ -500,7 +500,7 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds) {
     // ---- left-to-right QR sweep: X_c <- Q, X_{c+1} <- R X_{c+1} / |X_c|.
     // The carried factor is kept at unit norm and its norm logged: a row's
     // weight can pass the fp64 range before the sweep ends.
-    double lognorm = 0.0;
+    double lognorm = lognorm0;
     for (int c = 0; c + 1 < Lx; ++c) {
         double *X = xbox + c * box, *Xn = xbox + (c + 1) * box;
         const int m = 2 * mX[c], n = nX[c], n1 = nX[c + 1];
@@ -944,6 +944,94 @@ __global__ void __launch_bounds__(256) k_env_fit(const tn_env_desc *__restrict__
 // together; they need no spills for that.  D <= 16 takes 256 threads: its
 // Jacobi rounds have at most 16 row pairs, one per 16-lane row, and four of
 // its workgroups fit a compute unit's LDS.
+// Frozen truncation of row k (the contraction whose derivative tn_grad
+// takes): the MPO-MPS product X in xbox is replaced by P X, P the orthogonal
+// projector onto span{|columns 0..c*-1> x |columns c*.. of the frozen env k>},
+// c* = pcst[k] the leftmost column whose left bond that build truncated.  The
+// overlap O of X's columns c*.. with the frozen env's (right-orthonormal)
+// columns is carried right to left, rescaled by its largest entry at every
+// column, and absorbed into column c*-1; columns c*.. become the frozen env's.
+// Returns ln of the removed scale.  Scratch (pscr, 8 D^2 doubles):
+// O [2D][D], T [2D][2][D], On [2D][D].
+__device__ double project_row(const tn_env_desc &dsc, int k) {
+    const int c0 = dsc.pcst[k];
+    if (c0 < 1) return 0.0;   // nothing was truncated: the identity
+    const int Lx = dsc.Lx, D = dsc.D, ld = 2 * D;
+    const size_t box = (size_t)8 * D * D, ebox = (size_t)2 * D * D;
+    double *xbox = dsc.xbox;
+    int *xdims = dsc.xdims;
+    const int *pd = dsc.pdims + (size_t)k * (Lx + 1);
+    const double *Ek = dsc.penv + (size_t)k * Lx * ebox;
+    double *O = dsc.pscr, *T = O + 2 * D * D, *On = T + 4 * D * D;
+    __shared__ double red[16];
+    __shared__ int om;   // rows of O (the left bond of X at the current column)
+    if (threadIdx.x == 0) {
+        O[0] = 1.0;
+        om = 1;
+    }
+    __syncthreads();
+    double logscale = 0.0;
+    for (int c = Lx - 1; c >= c0; --c) {
+        const double *X = xbox + c * box;
+        const double *E = Ek + c * ebox;
+        const int m = xdims[c], n = xdims[Lx + 1 + c], pl = pd[c], pr = pd[c + 1];
+        // T[a][u][d] = sum_b X_c[a][u][b] O[b][d]   (b < n = rows of O)
+        for (int t = threadIdx.x; t < m * 2 * pr; t += blockDim.x) {
+            const int a = t / (2 * pr), u = (t / pr) & 1, d = t % pr;
+            double acc = 0.0;
+            for (int b = 0; b < n; ++b) acc += X[(a * 2 + u) * ld + b] * O[b * D + d];
+            T[(a * 2 + u) * D + d] = acc;
+        }
+        __syncthreads();
+        // On[a][e] = sum_{u,d} T[a][u][d] E_c[e][u][d]
+        double mx = 0.0;
+        for (int t = threadIdx.x; t < m * pl; t += blockDim.x) {
+            const int a = t / pl, e = t % pl;
+            double acc = 0.0;
+            for (int u = 0; u < 2; ++u)
+                for (int d = 0; d < pr; ++d) acc += T[(a * 2 + u) * D + d] * E[e * 2 * D + u * D + d];
+            On[a * D + e] = acc;
+            mx = fmax(mx, fabs(acc));
+        }
+        mx = tn_block_max(mx, red);
+        const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+        if (mx > 0.0) logscale += log(mx);
+        for (int t = threadIdx.x; t < m * pl; t += blockDim.x) O[(t / pl) * D + t % pl] = On[(t / pl) * D + t % pl] * inv;
+        if (threadIdx.x == 0) om = m;
+        __syncthreads();
+    }
+    // X_{c*-1}[a][u][e] = sum_b X_{c*-1}[a][u][b] O[b][e]
+    {
+        double *X = xbox + (c0 - 1) * box;
+        const int m1 = xdims[c0 - 1], n1 = om, pe = pd[c0];
+        for (int t = threadIdx.x; t < m1 * 2 * pe; t += blockDim.x) {
+            const int r = t / pe, e = t % pe;
+            double acc = 0.0;
+            for (int b = 0; b < n1; ++b) acc += X[r * ld + b] * O[b * D + e];
+            T[r * D + e] = acc;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < m1 * 2 * pe; t += blockDim.x) X[(t / pe) * ld + t % pe] = T[(t / pe) * D + t % pe];
+        if (threadIdx.x == 0) xdims[Lx + 1 + c0 - 1] = pe;
+    }
+    // columns c*.. of the frozen env
+    for (int c = c0; c < Lx; ++c) {
+        double *X = xbox + c * box;
+        const double *E = Ek + c * ebox;
+        const int pl = pd[c], pr = pd[c + 1];
+        for (int t = threadIdx.x; t < pl * 2 * pr; t += blockDim.x) {
+            const int e = t / (2 * pr), u = (t / pr) & 1, d = t % pr;
+            X[(e * 2 + u) * ld + d] = E[e * 2 * D + u * D + d];
+        }
+        if (threadIdx.x == 0) {
+            xdims[c] = pl;
+            xdims[Lx + 1 + c] = pr;
+        }
+    }
+    __syncthreads();
+    return logscale;
+}
+
 template <int NTH>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 1024 ? 1 : 4, 8)))
 k_env_row(const tn_env_desc *__restrict__ descs, int step) {
@@ -954,7 +1042,8 @@ k_env_row(const tn_env_desc *__restrict__ descs, int step) {
     if (step == 0)   // trivial env below the last row: bond 1 everywhere
         for (int c = threadIdx.x; c <= dsc.Lx; c += blockDim.x) dsc.dims[(size_t)dsc.Ly * (dsc.Lx + 1) + c] = 1;
     mpo_apply_row(dsc, k);
-    truncate_row<NTH < 1024>(dsc, k, lds);
+    const double lp = dsc.penv ? project_row(dsc, k) : 0.0;
+    truncate_row<NTH < 1024>(dsc, k, lds, lp);
 }
 
 // ln <top|env_1>: row 0 (no up legs) contracted with env 1 left to right,
@@ -1111,6 +1200,20 @@ int tn_env_build_prepare(tn_ctx *const *ctxs, int n, hipStream_t stream, std::st
         d.xbox = ctx->xbox;
         d.xdims = ctx->xdims;
         d.wbuf = ctx->wbuf;
+        d.penv = nullptr;
+        d.pdims = nullptr;
+        d.pcst = nullptr;
+        d.pscr = nullptr;
+        if (const tn_ctx *src = ctx->proj_src) {
+            if (src->D != D || src->Lx != Lx || src->Ly != Ly || !src->has_cst)
+                return fail(TN_EINVAL, "frozen evaluation: the projector build does not match");
+            if ((rc = tn_ensure(ctx, (void **)&ctx->pscr, &ctx->pscr_cap, (size_t)8 * D * D * sizeof(double))))
+                return fail(rc, ctx->err);
+            d.penv = src->env;
+            d.pdims = src->dims;
+            d.pcst = src->cst;
+            d.pscr = ctx->pscr;
+        }
         d.scal = ctx->scal;
         d.counters = ctx->counters;
         maxLy = Ly > maxLy ? Ly : maxLy;

@@ -83,6 +83,7 @@ def lib():
         "tn_mh_accept": (i, [vp, i, u64, u64, vp, vp, vp, vp, vp, vp, vp]),
         "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_grad_two_sided": (i, [vp, vp, vp, ctypes.POINTER(d)]),
+        "tn_logz_frozen": (i, [vp, i, vp, vp, vp, vp, vp]),
         "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
         "tn_autotune": (i, [vp, i, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "tn_autotune_multi": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i)]),
@@ -111,7 +112,7 @@ def exported_symbols():
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
             "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
             "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap",
-            "tn_set_compression", "tn_periodic_sweeps", "tn_sample_noalloc"]
+            "tn_set_compression", "tn_periodic_sweeps", "tn_sample_noalloc", "tn_logz_frozen"]
 
 
 def _ptr(t):
@@ -424,6 +425,26 @@ class Sampler:
         fn = lib().tn_grad_two_sided if two_sided else lib().tn_grad
         self._check(fn(self._ctx, _ptr(dJh), _ptr(dJv), ctypes.byref(db)))
         return dJh, dJv, db.value
+
+    def logz_frozen(self, sets):
+        """ln Z~_frozen (tn_logz_frozen) for every (Jh, Jv, h, beta) in `sets`
+        with the projectors of the current build.  Returns a list of floats."""
+        n = len(sets)
+        keep = []
+        pj = (ctypes.c_void_p * n)()
+        pv = (ctypes.c_void_p * n)()
+        ph = (ctypes.c_void_p * n)()
+        b = (ctypes.c_double * n)()
+        for k, (Jh, Jv, h, beta) in enumerate(sets):
+            tJh, tJv = _dev64(Jh, self.device), _dev64(Jv, self.device)
+            th = None if h is None else _dev64(h, self.device)
+            keep += [tJh, tJv, th]
+            pj[k], pv[k] = tJh.data_ptr(), tJv.data_ptr()
+            ph[k] = None if th is None else th.data_ptr()
+            b[k] = float(beta)
+        out = (ctypes.c_double * n)()
+        self._check(lib().tn_logz_frozen(self._ctx, n, pj, pv, ph, b, out))
+        return list(out)
 
     def autotune(self, chains, max_steps=16, cache=None):
         """Pick the batched sampler's launch variant and the MH steps per
