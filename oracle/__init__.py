@@ -24,6 +24,8 @@ Modules
     metropolis  single-spin-flip sweeps interleaved with TNMH steps
     periodic periodic boundaries by alternately frozen lines (Sec.
              "Arbitrary boundary conditions")
+    potts    q-state Potts models, general local dimension d (App. A
+             Eqs. pf_bond_description, tensor-general; Sec. 2)
 
 Parity status: every function is pinned by the CPU tests (tests/test_oracle_*.py)
 against brute force, exact transfer matrices, closed forms, invariants or an
