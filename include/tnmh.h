@@ -94,6 +94,36 @@ int tn_build_env_begin(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const doub
 int tn_build_env_rows(tn_ctx *ctx, int nrows, int *rows_left);
 int tn_build_env_end(tn_ctx *ctx, double *logZ_out);
 
+/* q-state Potts models: the method for a general local dimension d (App. A
+ * writes any nearest-neighbour model whose variables take d values through
+ * d x d bond matrices, Eq. pf_bond_description, split into site tensors,
+ * Eq. tensor-general; Sec. 2 notes that the sampler carries over to the
+ * Potts model).  Energy H(s) = - sum_<ij> J_ij delta(s_i, s_j)
+ * - sum_i h_i(s_i), values s in 0..d-1 stored as int8.  The bond matrix
+ * exp(beta J delta) is split through its eigenbasis (the uniform vector and
+ * Helmert's orthonormal basis of its complement, lambda_0 = e^K - 1 + d,
+ * lambda_mu = e^K - 1): P(s, mu) = e_mu(s) sqrt|lambda_mu|, Q(mu, s) =
+ * sign(lambda_mu) sqrt|lambda_mu| e_mu(s).  The environments are built as
+ * for Ising (bottom-up, QR sweep and successive SVD to D, fp64).
+ *   d          number of values, 2..6
+ *   Jh, Jv     (dev, fp64) couplings as in tn_build_env
+ *   h          (dev, fp64 [Ly][Lx][d], or NULL for 0) field of every value
+ *   D          bond dimension, 1..32
+ *   logZ_out   (host, may be NULL) ln Z~
+ * Afterwards the context is a Potts context until the next build: tn_sample,
+ * tn_sample_noalloc, tn_sample_steps, tn_eval_logq, tn_mh_step, tn_mh_accept
+ * and tn_mh_run work on value configurations (int8 [.][Ly][Lx], values
+ * 0..d-1) with the plain fp64 sampler: snake order, each conditional the
+ * categorical law of the d weights contracted from the same env, the draw
+ * the smallest value k with u (w_0 + .. + w_{d-1}) < w_0 + .. + w_k (u as for
+ * Ising); the Ising-only calls (tn_set_precision, tn_get_env, tn_grad,
+ * tn_grad_two_sided, tn_logz_frozen, tn_metropolis_sweeps, tn_link_overlap,
+ * tn_autotune) return TN_EINVAL.  Errors: TN_EINVAL for arguments out of
+ * range, fitted compression (tn_set_compression > 0); TN_ENOCONV, TN_ENONPOS
+ * as for tn_build_env.  Synchronises the stream. */
+int tn_potts_build_env(tn_ctx *ctx, int Lx, int Ly, int d, const double *Jh, const double *Jv,
+                       const double *h, double beta, int D, double *logZ_out);
+
 /* Install an environment computed elsewhere (or saved by tn_get_env) instead
  * of building it.  Couplings as in tn_build_env (dev).  Host arrays:
  *   env   [(Ly-1)][Lx][D][2][D] fp64: env k=1..Ly-1, tensor E[a][u][b] of column

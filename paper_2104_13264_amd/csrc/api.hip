@@ -139,6 +139,7 @@ void free_all(tn_ctx *ctx) {
                     ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
                     ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters,
                     ctx->cst,   ctx->gradscr, ctx->descs, ctx->fbuf, ctx->pscr,
+                    ctx->pq,    ctx->pG,   ctx->pw,
                     ctx->own_dstep ? (void *)ctx->dstep : nullptr};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
@@ -165,6 +166,7 @@ int check_prec(tn_ctx *ctx, int prec) {
 int set_instance(tn_ctx *ctx, int Lx, int Ly, const double *Jh, const double *Jv,
                  const double *h, double beta, int D, int prec) {
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
+    ctx->qd = 0;             // an Ising instance
     ctx->building = false;   // a new instance abandons an open incremental build
     ++ctx->env_gen;
     if (Lx < 1 || Ly < 1) return tn_fail(ctx, TN_EINVAL, "Lx and Ly must be >= 1");
@@ -226,9 +228,16 @@ int sample_impl(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint64_t f
     if (batch < 0) return tn_fail(ctx, TN_EINVAL, "batch < 0");
     if (batch > 0 && (!spins || !logq || !energy))
         return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
+    if (ctx->qd) return tn_run_potts(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
     if (ctx->prec == TN_FP64)
         return tn_run_fp64(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
     return tn_run_mfma(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy);
+}
+
+// calls defined for Ising contexts only
+int not_potts(tn_ctx *ctx) {
+    if (ctx->qd) return tn_fail(ctx, TN_EINVAL, "not available for a Potts context (tn_potts_build_env)");
+    return TN_OK;
 }
 
 }  // namespace
@@ -394,6 +403,7 @@ int tn_get_env(tn_ctx *ctx, double *env, int *dims, double *ell, double *logZ) {
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     const int Lx = ctx->Lx, Ly = ctx->Ly, D = ctx->D;
     const size_t box = (size_t)2 * D * D;
@@ -418,6 +428,7 @@ int tn_set_precision(tn_ctx *ctx, int prec) {
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     if ((rc = check_prec(ctx, prec))) return rc;
     if ((rc = tn_make_operands(ctx, prec))) return rc;
@@ -467,13 +478,17 @@ int tn_sample_noalloc(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step, uint
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
         return tn_fail(ctx, TN_EINVAL, "the context's device must be current");
-    const size_t need = ctx->prec == TN_FP64 ? tn_fp64_scratch_bytes(ctx, batch)
-                                             : tn_mfma_scratch_bytes(ctx, batch);
+    const size_t need = ctx->qd ? tn_potts_scratch_bytes(ctx, batch)
+                                : (ctx->prec == TN_FP64 ? tn_fp64_scratch_bytes(ctx, batch)
+                                                        : tn_mfma_scratch_bytes(ctx, batch));
     if (need > TN_NOALLOC_SCRATCH_BYTES)
         return tn_fail(ctx, TN_EINVAL, "tn_sample_noalloc: " + std::to_string(batch) +
                                            " proposals need " + std::to_string(need) +
                                            " bytes of scratch, above its fixed " +
                                            std::to_string(TN_NOALLOC_SCRATCH_BYTES) + " bytes");
+    if (ctx->qd)
+        return tn_run_potts(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy,
+                            ctx->noalloc_scr);
     if (ctx->prec == TN_FP64)
         return tn_run_fp64(ctx, batch, seed, step, batch, first_id, spins, false, logq, energy,
                            ctx->noalloc_scr);
@@ -491,6 +506,7 @@ int tn_eval_logq(tn_ctx *ctx, int batch, const int8_t *spins, double *logq, doub
     if (batch > 0 && (!spins || !logq || !energy))
         return tn_fail(ctx, TN_EINVAL, "NULL buffer");
     int8_t *s = const_cast<int8_t *>(spins);   // read-only in eval mode
+    if (ctx->qd) return tn_run_potts(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
     if (ctx->prec == TN_FP64) return tn_run_fp64(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
     return tn_run_mfma(ctx, batch, 0, 0, batch, 0, s, true, logq, energy);
 }
@@ -539,6 +555,7 @@ int tn_sample_steps(tn_ctx *ctx, int chains, int nsteps, uint64_t seed, uint64_t
     if (chains == 0) return TN_OK;
     if (!spins || !logq || !energy) return tn_fail(ctx, TN_EINVAL, "NULL output buffer");
     const int batch = chains * nsteps;
+    if (ctx->qd) return tn_run_potts(ctx, batch, seed, step0, chains, first_id, spins, false, logq, energy);
     if (ctx->prec == TN_FP64)
         return tn_run_fp64(ctx, batch, seed, step0, chains, first_id, spins, false, logq, energy);
     return tn_run_mfma(ctx, batch, seed, step0, chains, first_id, spins, false, logq, energy);
@@ -598,6 +615,7 @@ int tn_metropolis_sweeps(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, ui
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     ctx->err.clear();
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (chains < 0 || nsweeps < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0 or nsweeps < 0");
@@ -616,6 +634,7 @@ int tn_link_overlap(tn_ctx *ctx, int n, const int8_t *a, const int8_t *b, int32_
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     ctx->err.clear();
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "only MH steps may be captured");
     if (n < 0) return tn_fail(ctx, TN_EINVAL, "n < 0");
@@ -861,6 +880,7 @@ int tn_grad(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     ctx->err.clear();
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     if ((ctx->Lx > 1 && !dJh) || (ctx->Ly > 1 && !dJv))
@@ -872,6 +892,7 @@ int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta) {
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     ctx->err.clear();
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     if ((ctx->Lx > 1 && !dJh) || (ctx->Ly > 1 && !dJv))
@@ -932,6 +953,7 @@ int tn_logz_frozen(tn_ctx *ctx, int n, const double *const *Jh, const double *co
     (void)hipGetLastError();
     int rc;
     if ((rc = need_env(ctx))) return rc;
+    if ((rc = not_potts(ctx))) return rc;
     ctx->err.clear();
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "not allowed while capturing a graph");
     if (!ctx->has_cst)

@@ -139,6 +139,7 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
     ctx->err.clear();
     if (!ctx->has_env) return tn_fail(ctx, TN_ESTATE, "no environment: build or set one first");
     if (ctx->capturing) return tn_fail(ctx, TN_ESTATE, "cannot time kernels during graph capture");
+    if (ctx->qd) return tn_fail(ctx, TN_EINVAL, "not available for a Potts context (tn_potts_build_env)");
     if (chains < 1 || max_steps < 1) return tn_fail(ctx, TN_EINVAL, "chains < 1 or max_steps < 1");
     if (max_steps > 64) max_steps = 64;
     const int NT = ctx->Dp / 16;

@@ -140,6 +140,13 @@ struct tn_ctx {
 
     // periodic lattices (tn_periodic_setup): tn_periodic, owned
     void *per = nullptr;
+
+    // q-state Potts models (tn_potts_build_env, potts.hip): qd = d > 0 marks
+    // a Potts context (env boxes D x d x D, h [Ly][Lx][d]); its factor
+    // tables, sampler operands (both layouts) and build work area
+    int qd = 0;
+    double *pq = nullptr, *pG = nullptr, *pw = nullptr;
+    size_t pq_cap = 0, pG_cap = 0, pw_cap = 0;
 };
 
 int tn_fail(tn_ctx *ctx, int code, const std::string &msg);
@@ -320,6 +327,15 @@ int tn_run_fp64(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
 int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
                 uint64_t first_id, int8_t *spins, bool eval, double *logq,
                 double *energy, int variant = -1, void *scr = nullptr);
+
+// q-state Potts sampler (potts.hip): the plain fp64 draw with d-way
+// conditionals; scr as for tn_run_fp64 (tn_potts_scratch_bytes)
+int tn_run_potts(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_step,
+                 uint64_t first_id, int8_t *states, bool eval, double *logq, double *energy,
+                 void *scr = nullptr);
+inline size_t tn_potts_scratch_bytes(const tn_ctx *ctx, int batch) {
+    return (size_t)batch * ctx->Lx * ctx->qd * ctx->D * sizeof(double);
+}
 
 // Metropolis sweeps of `chains` states in place (metropolis.hip)
 int tn_launch_metropolis(tn_ctx *ctx, int chains, int nsweeps, uint64_t seed, uint64_t step, int8_t *spins);

@@ -84,6 +84,7 @@ def lib():
         "tn_grad": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_grad_two_sided": (i, [vp, vp, vp, ctypes.POINTER(d)]),
         "tn_logz_frozen": (i, [vp, i, vp, vp, vp, vp, vp]),
+        "tn_potts_build_env": (i, [vp, i, i, i, vp, vp, vp, d, i, ctypes.POINTER(d)]),
         "tn_stats": (i, [vp, ctypes.POINTER(_Stats), i]),
         "tn_autotune": (i, [vp, i, i, ctypes.c_char_p, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "tn_autotune_multi": (i, [vp, ctypes.c_char_p, ctypes.POINTER(i)]),
@@ -112,7 +113,8 @@ def exported_symbols():
             "tn_graph_end_and_replay", "tn_grad", "tn_grad_two_sided", "tn_stats",
             "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
             "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap",
-            "tn_set_compression", "tn_periodic_sweeps", "tn_sample_noalloc", "tn_logz_frozen"]
+            "tn_set_compression", "tn_periodic_sweeps", "tn_sample_noalloc", "tn_logz_frozen",
+            "tn_potts_build_env"]
 
 
 def _ptr(t):
@@ -140,6 +142,7 @@ class Sampler:
                                         ctypes.c_void_p(self.stream.cuda_stream)))
         self.Lx = self.Ly = self.D = None
         self.beta = None
+        self.d = None   # number of values of a Potts context
 
     # -- plumbing -----------------------------------------------------------
     def _check(self, rc):
@@ -180,6 +183,20 @@ class Sampler:
                 progress(Ly - 1 - left.value, Ly - 1)
             self._check(lib().tn_build_env_end(self._ctx, ctypes.byref(logZ)))
         self.Lx, self.Ly, self.D, self.beta = Lx, Ly, int(D), float(beta)
+        self.d = None
+        return logZ.value
+
+    def potts_build_env(self, Jh, Jv, h, beta, D, d):
+        """Environments of a q-state Potts model with d values
+        (tn_potts_build_env; h: [Ly][Lx][d] or None); returns ln Z~.  The
+        sampling calls then draw value configurations 0..d-1."""
+        Jh, Jv, h = (_dev64(x, self.device) for x in (Jh, Jv, h))
+        Ly, Lx = Jv.shape[0] + 1, Jh.shape[1] + 1
+        self._keep = (Jh, Jv, h)
+        logZ = ctypes.c_double()
+        self._check(lib().tn_potts_build_env(self._ctx, Lx, Ly, int(d), _ptr(Jh), _ptr(Jv), _ptr(h),
+                                             float(beta), int(D), ctypes.byref(logZ)))
+        self.Lx, self.Ly, self.D, self.beta, self.d = Lx, Ly, int(D), float(beta), int(d)
         return logZ.value
 
     def set_env(self, Jh, Jv, h, beta, D, env, dims, ell, logZ, prec=FP64):
@@ -196,6 +213,7 @@ class Sampler:
                                      dims.ctypes.data_as(ctypes.c_void_p),
                                      ell.ctypes.data_as(ctypes.c_void_p), float(logZ)))
         self.Lx, self.Ly, self.D, self.beta = Lx, Ly, int(D), float(beta)
+        self.d = None
 
     def get_env(self):
         """Return (env [(Ly-1)][Lx][D][2][D], dims [(Ly-1)][Lx+1], ell, logZ)."""
@@ -262,8 +280,11 @@ class Sampler:
         return lq, E
 
     def init_state(self, chains, spins=None):
+        """Chains in the given configurations, by default all up (Ising) or
+        all value 0 (Potts), with ln q and H from tn_eval_logq."""
         if spins is None:
-            spins = torch.ones((chains, self.Ly, self.Lx), dtype=torch.int8, device=self.device)
+            fill = torch.zeros if self.d else torch.ones
+            spins = fill((chains, self.Ly, self.Lx), dtype=torch.int8, device=self.device)
         spins = torch.as_tensor(spins, dtype=torch.int8, device=self.device).contiguous().clone()
         lq, E = self.eval_logq(spins)
         acc = torch.zeros(spins.shape[0], dtype=torch.uint8, device=self.device)
