@@ -120,6 +120,9 @@ def run_gpu(prec, inst, steps, warmup, env_state=None, ahead=1, tune_steps=0, tu
     launch_sizes = [m] * (steps // m) + ([steps % m] if steps % m else [])
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in launch_sizes]
+    # the elementwise kernel that records the energy series runs once before
+    # the timed region (its first launch loads the kernel)
+    torch.mul(state["energy"], 1.0, out=E_series[0])
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     k = 0
@@ -228,7 +231,8 @@ def run_ea_mix(steps, warmup):
                                             for (b, nt), v in sorted(variants.items())}},
             "acceptance": acc / max(prop, 1),
             "acceptance_by_L": {str(L): a[0] / max(a[1], 1) for L, a in sorted(by_L.items())},
-            "achieved_tflops_algorithmic": flops_step * steps / wall / 1e12,
+            "achieved_tflops_6D2L2_minimum": flops_step * steps / wall / 1e12,
+            "achieved_tflops_12D2L2": 2.0 * flops_step * steps / wall / 1e12,
             "env_build_s": build_s, "logZ_first": lz[0]}
 
 
@@ -286,7 +290,7 @@ def run_antiferro256(steps, warmup, n_eval=2048):
         dev[name] = dict(max=float(d.max()), mean=float(d.mean()),
                          rel_max=float((d / lq64.abs().cpu().numpy()).max()))
     s.close()
-    flops = 6.0 * inst.D ** 2 * inst.Lx * inst.Ly * C
+    flops = 12.0 * inst.D ** 2 * inst.Lx * inst.Ly * C   # the method's count per proposal, 12 D^2 L^2
     return {"metric": "accepted MH proposals/s, 2D Ising L=256 D=64: batched BF16 (and FP32)",
             "value": out["bf16"]["value"], "unit": UNIT, "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": out["bf16"]["ms_per_step"], "higher_is_better": True,
@@ -298,10 +302,91 @@ def run_antiferro256(steps, warmup, n_eval=2048):
                          "peak": 2500.0, "unit": "TFLOP/s",
                          "frac": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
                          "traffic": None, "kernel": "k_sampler_team<4,true,0>",
+                         "flop_count": "12 D^2 L^2 per proposal",
+                         "frac_6D2L2_minimum": flops / 2 / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
                          "kernel_ms": out["bf16"]["sampler_ms"]},
             "fp32": {k: v for k, v in out["fp32"].items() if k not in ("spins", "logq")},
             "abs_logq_minus_fp64": dev, "n_eval": n_eval,
             "env_build_s": build_s, "logZ": lz}
+
+
+def run_potts(steps, warmup, L=32, d=3, D=16, chains=8192):
+    """q-state Potts ferromagnet (general local dimension d, App. A), L x L
+    open boundaries, J = 1, h = 0, at the critical coupling of the square
+    lattice, beta = ln(1 + sqrt(d)); plain fp64 sampler with d-way
+    conditionals, one MH step of `chains` chains per step from all value 0.
+    The roofline is that of the row-sampler kernel (fp64 vector work): per
+    site the environment sweep's d products with D x D matrices, the drawing
+    product and the d weights, (d + 1) 2 D^2 + 2 d D flops."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2104_13264_amd import Sampler
+    from workloads import SEED
+    beta = math.log(1.0 + math.sqrt(d))
+    Jh, Jv = np.ones((L, L - 1)), np.ones((L - 1, L))
+    s = Sampler()
+    t0 = time.perf_counter()
+    lz = s.potts_build_env(Jh, Jv, None, beta, D, d)
+    build_s = time.perf_counter() - t0
+    log(f"[bench] potts {L}x{L} d={d} D={D}: build {build_s:.2f} s, ln Z~ {lz:.6f}")
+    state = s.init_state(chains)
+    prop = s.empty_batch(chains)
+    for t in range(warmup):
+        s.sample(chains, SEED, step=t, out=prop)
+        s.mh_accept(prop, state, SEED, t)
+    s.stats(reset=True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    E_series = torch.empty((steps, chains), dtype=torch.float64, device=s.device)
+    torch.mul(state["energy"], 1.0, out=E_series[0])   # loads the kernel before the timed region
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        s.sample(chains, SEED, step=warmup + k, out=prop)
+        ev[k][1].record(stream)
+        s.mh_accept(prop, state, SEED, warmup + k)
+        torch.mul(state["energy"], 1.0, out=E_series[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    st = s.stats()
+    kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    s.close()
+    flops = ((d + 1) * 2.0 * D * D + 2.0 * d * D) * L * L * chains
+    achieved = flops / (kms * 1e-3)
+    # the oracle on the host cores, a bounded sample of the same workload
+    from oracle import potts as opotts
+    m = opotts.PottsModel(Jh, Jv, None, beta, d)
+    envs = opotts.build_envs(m, D)
+    ost = opotts.init_state(m, envs, 64)
+    n, acc_o, tc = 0, 0, time.perf_counter()
+    while n < 20 and time.perf_counter() - tc < 10.0:
+        acc_o += int(opotts.mh_step(m, envs, ost, SEED, n).sum())
+        n += 1
+    dt = time.perf_counter() - tc
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return {"metric": "accepted MH proposals/s, 3-state Potts L=32 D=16 at beta_c: plain FP64 (d-way draw)",
+            "value": st["accepted"] / wall, "unit": UNIT, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"potts{d}_{L}x{L}_D{D}: {d}-state Potts ferromagnet J=1, h=0, "
+                                   f"beta=ln(1+sqrt({d}))={beta:.6f}, open boundaries, {chains} chains "
+                                   "from all value 0, one proposal per chain per step"},
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": achieved / 78.6e12, "traffic": None,
+                         "kernel": f"k_potts_rows<{1 << (D - 1).bit_length()},{d}> (one launch per row)",
+                         "flop_count": "((d+1) 2 D^2 + 2 d D) L^2 per proposal",
+                         "kernel_ms_per_step": kms},
+            "acceptance": st["accepted"] / max(st["proposed"], 1),
+            "tau_int_mean_energy": tau_int(E_series.cpu().numpy()),
+            "near_threshold_draws": st["near_threshold"], "clamps": st["clamps"],
+            "env_build_s": build_s, "logZ": lz,
+            "cpu_baseline": {"value": acc_o / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+                             "sample": f"{n} MH steps x 64 chains of the same workload (numpy fp64, {dt:.1f} s)"}}
 
 
 def run_hybrid(steps=200, chains=1024, sweeps=1):
@@ -694,7 +779,7 @@ def main():
                     help="cut schedule of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
                     choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta",
-                             "periodic", "precision", "fitbuild"],
+                             "periodic", "precision", "fitbuild", "potts"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -718,6 +803,8 @@ def main():
             out = run_fitbuild()
         elif args.workload == "precision":
             out = run_precision()
+        elif args.workload == "potts":
+            out = run_potts(args.steps, args.warmup)
         elif args.workload == "periodic":
             out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts, sweeps=args.periodic_sweeps)
         else:

@@ -411,9 +411,13 @@ int tn_grad_two_sided(tn_ctx *ctx, double *dJh, double *dJv, double *dbeta);
  * through a temporary file renamed over it.  Both calls synchronise the
  * stream and are refused while capturing (TN_ESTATE). */
 
-/* Tune this context's instance for tn_mh_run with `chains` chains: every
- * variant and every count of MH steps per sampler launch among 1, 2, 4, ...,
- * max_steps (capped at 64 and by a quarter of the free device memory).  The
+/* Tune this context's instance for tn_mh_run with `chains` chains and runs
+ * of max_steps MH steps: every variant and every count m of MH steps per
+ * sampler launch among 1, 2, 4, ..., max_steps (capped at 64 and by a
+ * quarter of the free device memory), ranked by the time of max_steps steps
+ * drawn in launches of m steps and one launch of the remainder (so a count
+ * that leaves a small, poorly filled last launch can lose to one that does
+ * not).  The
  * choice applies to tn_sample, tn_sample_steps, tn_eval_logq, tn_mh_step and
  * tn_mh_run while the lattice size, the bond dimension rounded up to 16 and
  * the precision stay those tuned (a new build with other couplings keeps it);

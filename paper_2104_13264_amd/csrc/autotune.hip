@@ -5,10 +5,14 @@
 // proposals per wavefront, wavefronts per SIMD; sampler_mfma.hip).  Which one
 // is fastest depends on the lattice, D, the precision and how many proposals
 // one launch draws, so it is measured: every candidate is launched on the
-// context's own instance and timed with HIP events, and the fastest time per
-// proposal wins.  For tn_mh_run the count of MH steps whose proposals share a
-// launch is tuned along with it (proposals do not depend on the chains' state,
-// Sec. 2, so drawing several steps ahead leaves the chains unchanged).
+// context's own instance and timed with HIP events.  For tn_mh_run the count
+// of MH steps whose proposals share a launch is tuned along with it
+// (proposals do not depend on the chains' state, Sec. 2, so drawing several
+// steps ahead leaves the chains unchanged): the pair that runs the caller's
+// max_steps steps fastest wins, launches of m steps plus one of the remainder
+// (a launch that fills only part of the chip's team slots costs nearly as
+// much as a full one).  tn_autotune_multi tunes the variant of each group's
+// one-step launch by its time.
 //
 // Choices persist in a JSON file: one object whose members are keyed by the
 // device architecture and the problem, one member per line,
@@ -173,6 +177,13 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
             if ((size_t)m * chains <= (size_t)INT32_MAX / 2 && (size_t)m * chains * per_prop <= free_b / 4)
                 fit.push_back(m);
         if (fit.empty()) return tn_fail(ctx, TN_ENOMEM, "not enough device memory for one step's proposals");
+        // the launches timed: every candidate count and the remainder it
+        // leaves of max_steps (the last launch of a run of max_steps steps)
+        std::vector<int> timed(fit);
+        for (int m : fit)
+            if (max_steps % m) timed.push_back(max_steps % m);
+        std::sort(timed.begin(), timed.end());
+        timed.erase(std::unique(timed.begin(), timed.end()), timed.end());
         const int mmax = fit.back();
         const size_t spin_bytes = (((size_t)mmax * chains * nsite + 255) / 256) * 256;
         const size_t need = spin_bytes + 2 * (size_t)mmax * chains * sizeof(double);
@@ -186,8 +197,8 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
         double *lq = (double *)(ctx->pspins + spin_bytes);
         double *E = lq + (size_t)mmax * chains;
         CounterGuard guard(ctx);
-        best.ns = -1.0;
-        for (int m : fit)
+        std::map<std::pair<int, int>, double> T;   // (variant, steps per launch) -> ms per launch
+        for (int m : timed)
             for (int v = 0; v < nvar; ++v) {
                 const int batch = m * chains;
                 double ms = 0.0;
@@ -199,10 +210,19 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
                     (void)guard.restore();
                     return rc;
                 }
-                const double ns = ms * 1e6 / batch;
+                T[{v, m}] = ms;
+            }
+        // the fastest run of max_steps steps: launches of m steps and one of
+        // the remainder, all in the same variant (as tn_mh_run draws them)
+        best.ns = -1.0;
+        for (int m : fit)
+            for (int v = 0; v < nvar; ++v) {
+                const int q = max_steps / m, r = max_steps % m;
+                const double total = q * T[{v, m}] + (r ? T[{v, r}] : 0.0);
+                const double ns = total * 1e6 / ((double)max_steps * chains);
                 if (best.ns < 0.0 || better(ns, best.ns)) {
                     best.variant = v;
-                    best.proposals = (long)batch;
+                    best.proposals = (long)m * chains;
                     best.ns = ns;
                 }
             }

@@ -500,6 +500,7 @@ class _BorrowedSampler(Sampler):
         self._ctx = ctypes.c_void_p(ptr)
         self._parent = parent
         self.Lx, self.Ly, self.D, self.beta = Lx, Ly, D, beta
+        self.d = None
 
     def close(self):
         self._ctx = ctypes.c_void_p()
