@@ -51,11 +51,19 @@ enum tn_status {
 
 /* Arithmetic of the sampler.  The environment build (QR/SVD truncation and
  * log-normalisers) is float64 in every case.
- *   TN_FP64  plain path: float64 vector arithmetic, one launch per row
- *   TN_FP32  batched path: float32 MFMA contractions (fp32 accumulate),
- *            persistent kernel over all rows, p and ln q in float64
- *   TN_BF16  batched path with bf16 operands and fp32 accumulation          */
-enum tn_prec { TN_FP64 = 0, TN_FP32 = 1, TN_BF16 = 2 };
+ *   TN_FP64       plain path: float64 vector arithmetic, one launch per row
+ *   TN_FP32       batched path: float32 MFMA contractions (fp32 accumulate),
+ *                 persistent kernel over all rows, p and ln q in float64
+ *   TN_BF16       batched path with bf16 operands and fp32 accumulation
+ *   TN_FP64_MFMA  batched path with float64 operands and vectors on the
+ *                 fp64 matrix cores (D <= 32): the conditionals of the plain
+ *                 path at batched cost, for low temperatures, where the small
+ *                 conditional weights come out of cancelling inner products
+ *                 that float32 cannot resolve.  Negative weights are clamped
+ *                 to 0 as in TN_FP64.  Single instances only (the batched
+ *                 uneven-instance and periodic calls take TN_FP64, TN_FP32 or
+ *                 TN_BF16).                                                  */
+enum tn_prec { TN_FP64 = 0, TN_FP32 = 1, TN_BF16 = 2, TN_FP64_MFMA = 3 };
 
 /* Create a context bound to `hip_stream` (a hipStream_t, or NULL for the
  * null stream) on the current device.  *out receives the handle. */

@@ -136,7 +136,7 @@ void free_all(tn_ctx *ctx) {
     }
     ctx->fkids.clear();
     void *bufs[] = {ctx->Jh,    ctx->Jv,   ctx->h,    ctx->env,  ctx->dims,   ctx->ell,
-                    ctx->G64r,  ctx->G32R, ctx->G16R, ctx->fac,  ctx->xbox,   ctx->wbuf,
+                    ctx->G64r,  ctx->G32R, ctx->G16R, ctx->G64MR, ctx->fac,  ctx->xbox,   ctx->wbuf,
                     ctx->scal,  ctx->xdims, ctx->gscr, ctx->pspins, ctx->counters,
                     ctx->cst,   ctx->gradscr, ctx->descs, ctx->fbuf, ctx->pscr,
                     ctx->pq,    ctx->pG,   ctx->pw,
@@ -157,8 +157,8 @@ void tn_free_ctx(tn_ctx *ctx) { free_all(ctx); }
 namespace {
 
 int check_prec(tn_ctx *ctx, int prec) {
-    if (prec != TN_FP64 && prec != TN_FP32 && prec != TN_BF16)
-        return tn_fail(ctx, TN_EINVAL, "prec must be TN_FP64, TN_FP32 or TN_BF16");
+    if (prec != TN_FP64 && prec != TN_FP32 && prec != TN_BF16 && prec != TN_FP64_MFMA)
+        return tn_fail(ctx, TN_EINVAL, "prec must be TN_FP64, TN_FP32, TN_BF16 or TN_FP64_MFMA");
     return TN_OK;
 }
 
@@ -671,6 +671,8 @@ int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, do
     if (n < 1 || !inst) return tn_fail(ctx, TN_EINVAL, "need n >= 1 instances");
     int rc;
     if ((rc = check_prec(ctx, prec))) return rc;
+    if (prec == TN_FP64_MFMA)
+        return tn_fail(ctx, TN_EINVAL, "batched instances take TN_FP64, TN_FP32 or TN_BF16");
     for (int i = 0; i < n; ++i)
         if (inst[i].chains < 0) return tn_fail(ctx, TN_EINVAL, "chains < 0");
     while ((int)ctx->kids.size() > n) {

@@ -156,7 +156,7 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
     if (cache_path) cache = read_cache(cache_path);
     Choice best;
     auto hit = cache.find(key);
-    const int nvar = plain ? 1 : tn_team_variants(NT);
+    const int nvar = (plain || ctx->prec == TN_FP64_MFMA) ? 1 : tn_team_variants(NT);
     if (hit != cache.end() && hit->second.variant >= 0 && hit->second.variant < nvar &&
         hit->second.proposals >= 1) {
         best = hit->second;

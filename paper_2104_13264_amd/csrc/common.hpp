@@ -65,10 +65,12 @@ struct tn_ctx {
     //   G64c[r][c][s][b][a]  = G_c(s)[a][b]  (column-major, fp64)
     //   G32R / G32L          MFMA A-operand tiles of G and G^T (fp32)
     //   G16R / G16L          the same in bf16
+    //   G64MR / G64ML        the same in fp64 (the batched fp64 path)
     double *G64r = nullptr, *G64c = nullptr;
     float *G32R = nullptr, *G32L = nullptr;
     uint16_t *G16R = nullptr, *G16L = nullptr;
-    size_t ops_cap64 = 0, ops_cap32 = 0, ops_cap16 = 0;
+    double *G64MR = nullptr, *G64ML = nullptr;
+    size_t ops_cap64 = 0, ops_cap32 = 0, ops_cap16 = 0, ops_cap64m = 0;
 
     // Boltzmann factors per site: exp(+-beta h), exp(+-beta Jv above),
     // exp(+-beta Jh left), [Ly][Lx][6] fp64
@@ -231,6 +233,7 @@ struct tn_ops_desc {
     double *fac, *G64r, *G64c;
     float *G32R, *G32L;
     uint16_t *G16R, *G16L;
+    double *G64MR, *G64ML;
 };
 // after tn_make_operands has allocated the context's operand buffers
 tn_ops_desc tn_ops_desc_of(const tn_ctx *ctx, int prec);
@@ -266,8 +269,9 @@ inline tn_samp_desc tn_samp_desc_of(tn_ctx *ctx, int B, int8_t *S, double *logq,
     A.h = ctx->h;
     A.fac = ctx->fac;
     const bool bf16 = ctx->prec == TN_BF16;
-    A.GR = bf16 ? (const void *)ctx->G16R : (const void *)ctx->G32R;
-    A.GL = bf16 ? (const void *)ctx->G16L : (const void *)ctx->G32L;
+    const bool f64 = ctx->prec == TN_FP64_MFMA;
+    A.GR = bf16 ? (const void *)ctx->G16R : (f64 ? (const void *)ctx->G64MR : (const void *)ctx->G32R);
+    A.GL = bf16 ? (const void *)ctx->G16L : (f64 ? (const void *)ctx->G64ML : (const void *)ctx->G32L);
     A.S = S;
     A.logq = logq;
     A.energy = energy;
@@ -283,7 +287,8 @@ inline tn_samp_desc tn_samp_desc_of(tn_ctx *ctx, int B, int8_t *S, double *logq,
 // whole teams (up to eight units).
 inline size_t tn_mfma_scratch_bytes(const tn_ctx *ctx, int batch) {
     const int units = ((batch + 127) / 128) * 8;
-    return (size_t)units * ctx->Lx * 2 * (size_t)ctx->Dp * 16 * sizeof(float);
+    const size_t elem = ctx->prec == TN_FP64_MFMA ? sizeof(double) : sizeof(float);
+    return (size_t)units * ctx->Lx * 2 * (size_t)ctx->Dp * 16 * elem;
 }
 // Scratch bytes of the plain fp64 sampler: per proposal both spins' right
 // environments of every column of the row in flight.

@@ -18,6 +18,11 @@
 // four chunks of one (mo, mt) are 16 contiguous bytes (one load).
 // The bf16 tiles (v_mfma_f32_16x16x16_bf16) use chunk q = mt, lane -> row
 // 16*mo + lane%16, cols 16*mt + 4*(lane/16) + i for i = 0..3 packed in 8 bytes.
+// The fp64 tiles (v_mfma_f64_16x16x4f64) follow that instruction's output
+// layout, where register i of lane l holds row (l/16) + 4 i of the tile: chunk
+// q = 4*mt + i covers rows 16*mt + 4*i .. 16*mt + 4*i + 3 of the next
+// product's input, so lane -> row 16*mo + lane%16, col 16*mt + 4*i + lane/16,
+// a lane's four chunks of one (mo, mt) in 32 contiguous bytes.
 //
 // Boltzmann factors, per (r, c):  fac[r][c][0..5] =
 //   exp(+-beta h_rc), exp(+-beta Jv_{r-1,c}), exp(+-beta Jh_{r,c-1})
@@ -73,6 +78,15 @@ __device__ void ops_site(const tn_ops_desc &O, int r, int c, double *gsh) {
             const int row = 16 * mo + (lane & 15), col = 16 * mt + 4 * (lane >> 4) + i;
             O.G32R[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + row) * Dp + col];
             O.G32L[site * 2 * Dp * Dp + t] = (float)gsh[(s * Dp + col) * Dp + row];
+        }
+    }
+    if (O.G64MR) {
+        for (int t = threadIdx.x; t < 2 * Dp * Dp; t += blockDim.x) {
+            const int i = t & 3, lane = (t >> 2) & 63, mt = (t >> 8) % NT, mo = (t >> 8) / NT % NT;
+            const int s = t / (Dp * Dp);
+            const int row = 16 * mo + (lane & 15), col = 16 * mt + 4 * i + (lane >> 4);
+            O.G64MR[site * 2 * Dp * Dp + t] = gsh[(s * Dp + row) * Dp + col];
+            O.G64ML[site * 2 * Dp * Dp + t] = gsh[(s * Dp + col) * Dp + row];
         }
     }
     if (O.G16R) {
@@ -149,6 +163,8 @@ tn_ops_desc tn_ops_desc_of(const tn_ctx *ctx, int prec) {
     O.G32L = prec == TN_FP32 ? ctx->G32L : nullptr;
     O.G16R = prec == TN_BF16 ? ctx->G16R : nullptr;
     O.G16L = prec == TN_BF16 ? ctx->G16L : nullptr;
+    O.G64MR = prec == TN_FP64_MFMA ? ctx->G64MR : nullptr;
+    O.G64ML = prec == TN_FP64_MFMA ? ctx->G64ML : nullptr;
     return O;
 }
 
@@ -170,6 +186,12 @@ int tn_make_operands(tn_ctx *ctx, int prec) {
         if ((rc = tn_ensure(ctx, (void **)&ctx->G32R, &ctx->ops_cap32, 2 * n * sizeof(float))))
             return rc;
         ctx->G32L = ctx->G32R + n;
+    } else if (prec == TN_FP64_MFMA) {
+        if (Dp > 32) return tn_fail(ctx, TN_EINVAL, "the batched fp64 sampler supports D <= 32");
+        const size_t n = sites * 2 * Dp * Dp;
+        if ((rc = tn_ensure(ctx, (void **)&ctx->G64MR, &ctx->ops_cap64m, 2 * n * sizeof(double))))
+            return rc;
+        ctx->G64ML = ctx->G64MR + n;
     } else {
         const size_t n = sites * 2 * Dp * Dp;
         if ((rc = tn_ensure(ctx, (void **)&ctx->G16R, &ctx->ops_cap16, 2 * n * sizeof(uint16_t))))

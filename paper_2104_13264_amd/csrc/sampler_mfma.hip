@@ -1,7 +1,9 @@
 // Batched sampler on the matrix cores: the same sequential draw and the same
 // conditionals as the plain path (Sec. 2 Eqs. bayes, pi-approx; App. A
 // Eq. proba-ratio-apx), with the per-column products run as 16x16 MFMA tiles
-// (FP32 16x16x4, or BF16 16x16x16 with FP32 accumulation).
+// (FP32 16x16x4, BF16 16x16x16 with FP32 accumulation, or FP64 16x16x4).
+// The precision mode PM selects the operands and the vector arithmetic: FP32
+// and BF16 vectors are fp32, FP64 vectors are fp64.
 //
 // Each wavefront owns 16 proposals (the N dimension of every tile) for the
 // whole lattice.  Per row, in snake order (row r drawn left to right when r is
@@ -22,8 +24,9 @@
 // all tiles); powers of two are exact, so this equals rescaling the input first.
 // ln q is accumulated as two fp64 products, of the drawn weights and of the
 // weight totals, each with a separate binary exponent, and evaluated once at
-// the end; the spin is +1 iff u * (w+ + w-) < w+.  Weights below 2^-24 of
-// |w+| + |w-| are raised to that floor.
+// the end; the spin is +1 iff u * (w+ + w-) < w+.  In FP32 and BF16, weights
+// below 2^-24 of |w+| + |w-| are raised to that floor; in FP64, negative
+// weights are clamped to 0, as in the plain path.
 //
 // Proposal j of the launch has id first_id + j % per_step and MH step
 // step0 + j / per_step (several steps' proposals may share a launch; the
@@ -39,8 +42,24 @@
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
+
+// Precision modes of the team kernel.
+constexpr int PM_F32 = 0, PM_BF16 = 1, PM_F64 = 2;
+template <int PM>
+struct Arith {   // fp32 vectors (FP32 and BF16 operands)
+    using E = float;
+    using V4 = floatx4;
+};
+template <>
+struct Arith<PM_F64> {
+    using E = double;
+    using V4 = doublex4;
+};
+constexpr int team_variants(int NT, int PM) { return PM == PM_F64 ? 1 : tn_team_variants(NT); }
 
 #define TN_MAX_LX 256
 
@@ -49,6 +68,13 @@ __device__ __forceinline__ int pow2_exponent_f(float m) {
     if (m > 0.0f && m <= 3.0e38f) frexpf(m, &e);
     return e;
 }
+__device__ __forceinline__ int pow2_exponent_f(double m) {
+    int e = 0;
+    if (m > 0.0 && m <= 1.79e308) frexp(m, &e);
+    return e;
+}
+__device__ __forceinline__ float fma_e(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_e(double a, double b, double c) { return fma(a, b, c); }
 
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -80,23 +106,28 @@ __device__ __forceinline__ const char *uniform_ptr(const void *p) {
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // A operands of one spin's product for one column, per lane: every 16-row
-// output block mo = 0..NT-1 with the 4 NT k-chunks of the fp32 16x16x4 product
-// or the NT chunks of the bf16 16x16x16 product.  Tile layout per site:
-// [s][mo][mt][64 lanes][4 chunks] (fp32: 16 bytes per lane; bf16: 8).
-template <int NT, bool BF16>
-struct ATiles;
-
-template <int NT>
-struct ATiles<NT, false> {
+// output block mo = 0..NT-1 with the 4 NT k-chunks of the fp32 or fp64
+// 16x16x4 product or the NT chunks of the bf16 16x16x16 product.  Tile layout
+// per site: [s][mo][mt][64 lanes][4 chunks] (fp32: 16 bytes per lane; bf16: 8;
+// fp64: 32).
+template <int NT, int PM>
+struct ATiles {
     static constexpr int NQ = 4 * NT;
     static constexpr size_t SITE_BYTES = (size_t)2 * NT * NQ * 64 * 4;
     float a[NT][NQ];
 };
 
 template <int NT>
-struct ATiles<NT, true> {
+struct ATiles<NT, PM_BF16> {
     static constexpr size_t SITE_BYTES = (size_t)2 * NT * NT * 64 * 8;
     shortx4 a[NT][NT];
+};
+
+template <int NT>
+struct ATiles<NT, PM_F64> {
+    static constexpr int NQ = 4 * NT;
+    static constexpr size_t SITE_BYTES = (size_t)2 * NT * NQ * 64 * 8;
+    double a[NT][NQ];
 };
 
 // Sum (or max) over the four 16-lane rows of a wavefront, the same result in
@@ -120,20 +151,61 @@ __device__ __forceinline__ void rows4_sum2(float &a, float &b) {
     b = __uint_as_float(z[1]);
 }
 
+// The same for fp64 values: the swaps move the two 32-bit halves.
+__device__ __forceinline__ void swap32_pair(double v0, double v1, double &r0, double &r1) {
+    auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)__double2loint(v0), (uint32_t)__double2loint(v1), false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)__double2hiint(v0), (uint32_t)__double2hiint(v1), false, false);
+    r0 = __hiloint2double((int)hi[0], (int)lo[0]);
+    r1 = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16_pair(double v0, double v1, double &r0, double &r1) {
+    auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)__double2loint(v0), (uint32_t)__double2loint(v1), false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)__double2hiint(v0), (uint32_t)__double2hiint(v1), false, false);
+    r0 = __hiloint2double((int)hi[0], (int)lo[0]);
+    r1 = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double rows4_max(double v) {
+    double a, b;
+    swap32_pair(v, v, a, b);
+    v = fmax(a, b);
+    swap16_pair(v, v, a, b);
+    return fmax(a, b);
+}
+__device__ __forceinline__ void rows4_sum2(double &a, double &b) {
+    double r0, r1;
+    swap32_pair(a, b, r0, r1);
+    double v = r0 + r1;
+    swap16_pair(v, v, r0, r1);
+    v = r0 + r1;
+    swap32_pair(v, v, r0, r1);
+    a = r0;
+    b = r1;
+}
+
 // LDS arrays indexed by proposal keep the proposal index innermost, so the 16
 // proposals of a wavefront touch 16 consecutive entries (no bank conflicts).
 constexpr int RS = 4;   // rescale (and ln q renormalisation) period in columns
 
 // Products of both spins' tiles, the four (2 NT) accumulation chains
 // interleaved: acc[s] = A[s] x[s].
-template <int NT, bool BF16>
-__device__ __forceinline__ void mul_both(const ATiles<NT, BF16> (&a)[2], const floatx4 (&x0)[NT],
-                                         const floatx4 (&x1)[NT], floatx4 (&acc)[2][NT]) {
+template <int NT, int PM>
+__device__ __forceinline__ void mul_both(const ATiles<NT, PM> (&a)[2], const typename Arith<PM>::V4 (&x0)[NT],
+                                         const typename Arith<PM>::V4 (&x1)[NT],
+                                         typename Arith<PM>::V4 (&acc)[2][NT]) {
+    using V4 = typename Arith<PM>::V4;
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-        for (int mo = 0; mo < NT; ++mo) acc[sp][mo] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    if constexpr (BF16) {
+        for (int mo = 0; mo < NT; ++mo) acc[sp][mo] = V4{0, 0, 0, 0};
+    if constexpr (PM == PM_F64) {
+#pragma unroll
+        for (int q = 0; q < 4 * NT; ++q)
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo) {
+                acc[0][mo] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0].a[mo][q], x0[q >> 2][q & 3], acc[0][mo], 0, 0, 0);
+                acc[1][mo] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1].a[mo][q], x1[q >> 2][q & 3], acc[1][mo], 0, 0, 0);
+            }
+    } else if constexpr (PM == PM_BF16) {
         shortx4 b0[NT], b1[NT];
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) {
@@ -192,17 +264,18 @@ constexpr int TW = 4;   // waves per team
 //   V = 0  two sets per wave, two waves per SIMD (D 33-64: one set, one wave)
 //   V = 1  one set per wave, two waves per SIMD (half the LDS per team)
 //   V = 2  one set per wave, three waves per SIMD
-template <int NT, bool BF16, int V>
+template <int NT, int PM, int V>
 struct TeamCfg {
-    static_assert(V >= 0 && V < tn_team_variants(NT), "no such variant for this bond class");
-    static constexpr uint32_t STAGE = (uint32_t)ATiles<NT, BF16>::SITE_BYTES;   // both spins
+    static_assert(V >= 0 && V < team_variants(NT, PM), "no such variant for this bond class");
+    static constexpr bool BF16 = PM == PM_BF16, F64 = PM == PM_F64;
+    static constexpr uint32_t STAGE = (uint32_t)ATiles<NT, PM>::SITE_BYTES;   // both spins
     static constexpr uint32_t LANE = STAGE % (TW * 64 * 16) == 0 ? 16 : 4;     // dwordx4 or dword fetches
     static constexpr int LOADS = (int)(STAGE / (TW * 64 * LANE));            // per wave per column
     static_assert(LOADS * TW * 64 * LANE == STAGE, "stage must split evenly");
     static constexpr int TL = NT <= 2 ? 4 : 2;
-    static constexpr int SETS = (NT <= 2 && V == 0) ? 2 : 1;
-    static constexpr int WPE = NT <= 2 ? (V == 2 ? 3 : 2) : 1;
-    static constexpr int ABUF = (BF16 || NT <= 2) ? 2 : 1;
+    static constexpr int SETS = (NT <= 2 && V == 0 && !F64) ? 2 : 1;
+    static constexpr int WPE = F64 ? (NT == 1 ? 2 : 1) : (NT <= 2 ? (V == 2 ? 3 : 2) : 1);
+    static constexpr int ABUF = F64 ? (NT == 1 ? 2 : 1) : ((BF16 || NT <= 2) ? 2 : 1);
     static constexpr int PT = TW * 16 * SETS;   // proposals per team
 };
 
@@ -243,9 +316,21 @@ __device__ __forceinline__ void team_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int NT, bool BF16>
-__device__ __forceinline__ void lds_tiles(ATiles<NT, BF16> &a, const unsigned char *st, int lane) {
-    if constexpr (BF16) {
+template <int NT, int PM>
+__device__ __forceinline__ void lds_tiles(ATiles<NT, PM> &a, const unsigned char *st, int lane) {
+    if constexpr (PM == PM_F64) {
+#pragma unroll
+        for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) {
+                const doublex2 v0 = *(const doublex2 *)(st + ((mo * NT + mt) * 64 + lane) * 32);
+                const doublex2 v1 = *(const doublex2 *)(st + ((mo * NT + mt) * 64 + lane) * 32 + 16);
+                a.a[mo][4 * mt + 0] = v0[0];
+                a.a[mo][4 * mt + 1] = v0[1];
+                a.a[mo][4 * mt + 2] = v1[0];
+                a.a[mo][4 * mt + 3] = v1[1];
+            }
+    } else if constexpr (PM == PM_BF16) {
 #pragma unroll
         for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
@@ -263,12 +348,16 @@ __device__ __forceinline__ void lds_tiles(ATiles<NT, BF16> &a, const unsigned ch
     }
 }
 
-template <int NT, bool BF16, int V>
+template <int NT, int PM, int V>
 __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0, const int eval,
                                           const uint32_t k0, const uint32_t k1, const uint64_t step0) {
     if (unit0 * 16 >= A.B) return;   // a team with no proposal of its instance (uniform)
-    using AT = ATiles<NT, BF16>;
-    using CF = TeamCfg<NT, BF16, V>;
+    using AT = ATiles<NT, PM>;
+    using CF = TeamCfg<NT, PM, V>;
+    using ET = typename Arith<PM>::E;
+    using V4 = typename Arith<PM>::V4;
+    constexpr bool F64 = PM == PM_F64;
+    constexpr uint32_t YB = sizeof(V4);   // bytes of one y tile per lane
     constexpr int TL = CF::TL, SE = CF::SETS, PT = CF::PT;
     constexpr int CG = 4 / SE;                 // column groups of a set's energy
     const int B = A.B, Lx = A.Lx, Ly = A.Ly, per_step = A.per_step;
@@ -299,7 +388,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
     double(*epart)[SE][4][16] = (double(*)[SE][4][16])(smem + L.epart);
     auto rowbuf = [&](int par) { return (int8_t(*)[PT])(smem + L.rows + par * Lx * PT); };
 
-    const uint32_t gstride = 2u * NT * 64 * 16;   // bytes of stored y tiles per column
+    const uint32_t gstride = 2u * NT * 64 * YB;   // bytes of stored y tiles per column
     __amdgpu_buffer_rsrc_t grs[SE];
 #pragma unroll
     for (int st = 0; st < SE; ++st)
@@ -359,73 +448,96 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             wait_vm<(TL - 2) * CF::LOADS>();   // own share of column 0 has landed
             __syncthreads();
             AT a[CF::ABUF][2];   // [set of registers][spin]
-            lds_tiles<NT, BF16>(a[0][0], ring, lane);
-            lds_tiles<NT, BF16>(a[0][1], ring + CF::STAGE / 2, lane);
+            lds_tiles<NT, PM>(a[0][0], ring, lane);
+            lds_tiles<NT, PM>(a[0][1], ring + CF::STAGE / 2, lane);
             if (sweep) {
-                floatx4 v0[SE][NT], v1[SE][NT];   // r_+ and r_- of every set
+                V4 v0[SE][NT], v1[SE][NT];   // r_+ and r_- of every set
 #pragma unroll
                 for (int st = 0; st < SE; ++st)
 #pragma unroll
-                    for (int mt = 0; mt < NT; ++mt) v0[st][mt] = v1[st][mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                    for (int mt = 0; mt < NT; ++mt) v0[st][mt] = v1[st][mt] = V4{0, 0, 0, 0};
                 if (grp == 0)
 #pragma unroll
-                    for (int st = 0; st < SE; ++st) v0[st][0][0] = v1[st][0][0] = 1.0f;
+                    for (int st = 0; st < SE; ++st) v0[st][0][0] = v1[st][0][0] = 1;
                 int e[SE];
 #pragma unroll
                 for (int st = 0; st < SE; ++st) e[st] = 0;
                 auto stepP = [&](int k, int t) {
                     const int c = colof(t);
-                    floatx4 acc[SE][2][NT];
+                    V4 acc[SE][2][NT];
 #pragma unroll
-                    for (int st = 0; st < SE; ++st) mul_both<NT, BF16>(a[k % CF::ABUF], v0[st], v1[st], acc[st]);
+                    for (int st = 0; st < SE; ++st) mul_both<NT, PM>(a[k % CF::ABUF], v0[st], v1[st], acc[st]);
                     issue(t + TL - 1);
 #pragma unroll
                     for (int st = 0; st < SE; ++st) {
                         const bool up_minus = r > 0 && prow[c][slot(st)] < 0;
-                        const floatx4 m = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
+                        ET m[4];   // the mixing weights W(s', s) v_c(s), fp32 (or fp64 in FP64 mode)
+                        if constexpr (F64) {
+                            const doublex2 m01 = *(const doublex2 *)&vS[c][up_minus ? 1 : 0][0][0];
+                            const doublex2 m23 = *(const doublex2 *)&vS[c][up_minus ? 1 : 0][1][0];
+                            m[0] = m01[0];
+                            m[1] = m01[1];
+                            m[2] = m23[0];
+                            m[3] = m23[1];
+                        } else {
+                            const floatx4 mf = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) m[i] = mf[i];
+                        }
                         if (t % RS == 0 && t > 0) {
 #pragma unroll
                             for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
                                 for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                                    for (int i = 0; i < 4; ++i) acc[st][sp][mo][i] = ldexpf(acc[st][sp][mo][i], -e[st]);
+                                    for (int i = 0; i < 4; ++i) acc[st][sp][mo][i] = ldexp(acc[st][sp][mo][i], -e[st]);
                         }
 #pragma unroll
                         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-                            for (int mo = 0; mo < NT; ++mo)
-                                __builtin_amdgcn_raw_buffer_store_b128(
-                                    __builtin_bit_cast(uintx4, acc[st][sp][mo]), grs[st],
-                                    (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
+                            for (int mo = 0; mo < NT; ++mo) {
+                                if constexpr (F64) {
+                                    const doublex2 lo = {acc[st][sp][mo][0], acc[st][sp][mo][1]};
+                                    const doublex2 hi = {acc[st][sp][mo][2], acc[st][sp][mo][3]};
+                                    const uint32_t off = (uint32_t)(((sp * NT + mo) * 64 + lane) * 32);
+                                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, lo), grs[st], off,
+                                                                           uniform_u32((uint32_t)c * gstride), 0);
+                                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, hi), grs[st], off + 16,
+                                                                           uniform_u32((uint32_t)c * gstride), 0);
+                                } else {
+                                    __builtin_amdgcn_raw_buffer_store_b128(
+                                        __builtin_bit_cast(uintx4, acc[st][sp][mo]), grs[st],
+                                        (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
+                                }
+                            }
 #pragma unroll
                         for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
-                                v0[st][mo][i] = fmaf(m[1], acc[st][1][mo][i], m[0] * acc[st][0][mo][i]);
-                                v1[st][mo][i] = fmaf(m[3], acc[st][1][mo][i], m[2] * acc[st][0][mo][i]);
+                                v0[st][mo][i] = fma_e(m[1], acc[st][1][mo][i], m[0] * acc[st][0][mo][i]);
+                                v1[st][mo][i] = fma_e(m[3], acc[st][1][mo][i], m[2] * acc[st][0][mo][i]);
                             }
                         if (t % RS == RS - 1) {
-                            float mx = 0.0f;
+                            ET mx = 0;
 #pragma unroll
                             for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
                                 for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                                    for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(acc[st][sp][mo][i]));
+                                    for (int i = 0; i < 4; ++i) mx = fmax(mx, fabs(acc[st][sp][mo][i]));
                             e[st] = pow2_exponent_f(rows4_max(mx));
                         }
                     }
                     // own fetch of column t + 1 has landed: at most the ops
                     // issued after it are in flight (fewer in the first steps,
                     // which follow the prologue's fetches)
-                    constexpr int ST = SE * 2 * NT;   // stores per step
+                    constexpr int ST = SE * 2 * NT * (F64 ? 2 : 1);   // stores per step
                     if (t >= TL - 2) wait_vm<ST + (TL - 2) * (CF::LOADS + ST)>();
                     else wait_vm<(TL - 2) * CF::LOADS + ST>();
                     team_barrier();
                     const unsigned char *stg = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
+                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
+                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
@@ -434,29 +546,39 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                 }
                 if (t < Lx) stepP(0, t);
             } else {
-                auto gload = [&](floatx4 (&gk)[SE][2][NT], int c) {
+                auto gload = [&](V4 (&gk)[SE][2][NT], int c) {
 #pragma unroll
                     for (int st = 0; st < SE; ++st)
 #pragma unroll
                         for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-                            for (int mo = 0; mo < NT; ++mo)
-                                gk[st][s2][mo] = __builtin_bit_cast(
-                                    floatx4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                 grs[st], (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
-                                                 uniform_u32((uint32_t)c * gstride), 0));
+                            for (int mo = 0; mo < NT; ++mo) {
+                                if constexpr (F64) {
+                                    const uint32_t off = (uint32_t)(((s2 * NT + mo) * 64 + lane) * 32);
+                                    const doublex2 lo = __builtin_bit_cast(
+                                        doublex2, __builtin_amdgcn_raw_buffer_load_b128(grs[st], off, uniform_u32((uint32_t)c * gstride), 0));
+                                    const doublex2 hi = __builtin_bit_cast(
+                                        doublex2, __builtin_amdgcn_raw_buffer_load_b128(grs[st], off + 16, uniform_u32((uint32_t)c * gstride), 0));
+                                    gk[st][s2][mo] = V4{lo[0], lo[1], hi[0], hi[1]};
+                                } else {
+                                    gk[st][s2][mo] = __builtin_bit_cast(
+                                        floatx4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                     grs[st], (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
+                                                     uniform_u32((uint32_t)c * gstride), 0));
+                                }
+                            }
                 };
-                floatx4 g[2][SE][2][NT];
+                V4 g[2][SE][2][NT];
                 gload(g[0], colof(0));
                 gload(g[1], colof(min(1, Lx - 1)));
-                floatx4 lam[SE][NT];
+                V4 lam[SE][NT];
 #pragma unroll
                 for (int st = 0; st < SE; ++st)
 #pragma unroll
-                    for (int mt = 0; mt < NT; ++mt) lam[st][mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                    for (int mt = 0; mt < NT; ++mt) lam[st][mt] = V4{0, 0, 0, 0};
                 if (grp == 0)
 #pragma unroll
-                    for (int st = 0; st < SE; ++st) lam[st][0][0] = 1.0f;
+                    for (int st = 0; st < SE; ++st) lam[st][0][0] = 1;
                 int sprev = 0;
                 uint4 words = make_uint4(0u, 0u, 0u, 0u);
                 int wblk = -1;
@@ -472,38 +594,46 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     const uint32_t word = tn_word(words, i & 3);
                     const bool up_minus = r > 0 && up < 0;
                     const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
-                    floatx4 acc[SE][2][NT];
+                    V4 acc[SE][2][NT];
 #pragma unroll
-                    for (int st = 0; st < SE; ++st) mul_both<NT, BF16>(a[k % CF::ABUF], lam[st], lam[st], acc[st]);
-                    float d0[SE], d1[SE];
+                    for (int st = 0; st < SE; ++st) mul_both<NT, PM>(a[k % CF::ABUF], lam[st], lam[st], acc[st]);
+                    ET d0[SE], d1[SE];
 #pragma unroll
                     for (int st = 0; st < SE; ++st) {
-                        d0[st] = 0.0f;
-                        d1[st] = 0.0f;
+                        d0[st] = 0;
+                        d1[st] = 0;
 #pragma unroll
                         for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                             for (int ii = 0; ii < 4; ++ii) {
-                                d0[st] = fmaf(lam[st][mo][ii], g[k][st][0][mo][ii], d0[st]);
-                                d1[st] = fmaf(lam[st][mo][ii], g[k][st][1][mo][ii], d1[st]);
+                                d0[st] = fma_e(lam[st][mo][ii], g[k][st][0][mo][ii], d0[st]);
+                                d1[st] = fma_e(lam[st][mo][ii], g[k][st][1][mo][ii], d1[st]);
                             }
                     }
                     issue(t + TL - 1);
                     gload(g[k], colof(min(t + 2, Lx - 1)));
 #pragma unroll
                     for (int st = 0; st < SE; ++st) rows4_sum2(d0[st], d1[st]);
-                    const float dd0 = (SE == 2 && ds) ? d0[SE - 1] : d0[0];
-                    const float dd1 = (SE == 2 && ds) ? d1[SE - 1] : d1[0];
+                    const ET dd0 = (SE == 2 && ds) ? d0[SE - 1] : d0[0];
+                    const ET dd1 = (SE == 2 && ds) ? d1[SE - 1] : d1[0];
                     double w0 = vv.x * (double)dd0;
                     double w1 = vv.y * (double)dd1;
-                    // a weight below the FP32 resolution of |w+| + |w-| (negative
-                    // ones included) is not resolved: it is raised to 2^-24 of
-                    // that sum (counted), so that every configuration keeps a
-                    // positive proposal probability and a finite ln q
-                    const double fl = 0x1p-24 * (fabs(w0) + fabs(w1));
-                    n_clamp += (w0 < fl) + (w1 < fl);
-                    w0 = fmax(w0, fl);
-                    w1 = fmax(w1, fl);
+                    if constexpr (F64) {
+                        // negative weights (ill-conditioning) clamped to 0 and
+                        // counted, as in the plain path
+                        n_clamp += (w0 < 0.0) + (w1 < 0.0);
+                        w0 = fmax(w0, 0.0);
+                        w1 = fmax(w1, 0.0);
+                    } else {
+                        // a weight below the FP32 resolution of |w+| + |w-| (negative
+                        // ones included) is not resolved: it is raised to 2^-24 of
+                        // that sum (counted), so that every configuration keeps a
+                        // positive proposal probability and a finite ln q
+                        const double fl = 0x1p-24 * (fabs(w0) + fabs(w1));
+                        n_clamp += (w0 < fl) + (w1 < fl);
+                        w0 = fmax(w0, fl);
+                        w1 = fmax(w1, fl);
+                    }
                     const double tot = w0 + w1;
                     const bool bad = !(tot > 0.0 && tot <= 1.79e308);
                     n_both += bad;
@@ -530,18 +660,18 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                         // entry) and renormalisation of the ln q products
 #pragma unroll
                         for (int st = 0; st < SE; ++st) {
-                            float mx = 0.0f;
+                            ET mx = 0;
 #pragma unroll
                             for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                                for (int ii = 0; ii < 4; ++ii) mx = fmaxf(mx, fabsf(lam[st][mo][ii]));
+                                for (int ii = 0; ii < 4; ++ii) mx = fmax(mx, fabs(lam[st][mo][ii]));
                             const int ee = pow2_exponent_f(rows4_max(mx));
 #pragma unroll
                             for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
                                 for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
-                                    for (int ii = 0; ii < 4; ++ii) acc[st][sp][mo][ii] = ldexpf(acc[st][sp][mo][ii], -ee);
+                                    for (int ii = 0; ii < 4; ++ii) acc[st][sp][mo][ii] = ldexp(acc[st][sp][mo][ii], -ee);
                         }
                         int e1, e2;
                         num = frexp(num, &e1);
@@ -555,12 +685,12 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     // own fetch of column t + 1 has landed (ops issued after it:
                     // the y loads of its step and TL - 2 steps of fetches and y
                     // loads; more in the first steps)
-                    constexpr int GL = SE * 2 * NT;   // y loads per step
+                    constexpr int GL = SE * 2 * NT * (F64 ? 2 : 1);   // y loads per step
                     wait_vm<GL + (TL - 2) * (CF::LOADS + GL)>();
                     team_barrier();
                     const unsigned char *stg = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
-                    lds_tiles<NT, BF16>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
+                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
+                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
@@ -605,18 +735,18 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
     }
 }
 
-template <int NT, bool BF16, int V>
-__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16, V>::WPE, 8)))
+template <int NT, int PM, int V>
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, PM, V>::WPE, 8)))
 k_sampler_team(tn_samp_desc A, int eval, uint32_t k0, uint32_t k1, uint64_t step0,
                const uint64_t *__restrict__ step_base) {
-    team_body<NT, BF16, V>(A, blockIdx.x * TW * TeamCfg<NT, BF16, V>::SETS, eval, k0, k1, step0 + *step_base);
+    team_body<NT, PM, V>(A, blockIdx.x * TW * TeamCfg<NT, PM, V>::SETS, eval, k0, k1, step0 + *step_base);
 }
 
-template <int NT, bool BF16, int V>
-__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, BF16, V>::WPE, 8)))
+template <int NT, int PM, int V>
+__global__ void __launch_bounds__(TW * 64) __attribute__((amdgpu_waves_per_eu(TeamCfg<NT, PM, V>::WPE, 8)))
 k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, int eval, uint32_t k0, uint32_t k1,
                      uint64_t step0, const uint64_t *__restrict__ step_base) {
-    const int u0 = (int)blockIdx.x * TW * TeamCfg<NT, BF16, V>::SETS;
+    const int u0 = (int)blockIdx.x * TW * TeamCfg<NT, PM, V>::SETS;
     int lo = 0, hi = n - 1;
     while (lo < hi) {   // last instance whose first unit is <= u0
         const int mid = (lo + hi + 1) >> 1;
@@ -624,15 +754,15 @@ k_sampler_team_multi(const tn_samp_desc *__restrict__ descs, int n, int eval, ui
         else hi = mid - 1;
     }
     const tn_samp_desc A = descs[lo];
-    team_body<NT, BF16, V>(A, u0 - A.blk0, eval, k0, k1, step0 + *step_base);
+    team_body<NT, PM, V>(A, u0 - A.blk0, eval, k0, k1, step0 + *step_base);
 }
 
-template <int NT, bool BF16, int V>
+template <int NT, int PM, int V>
 int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
-    using CF = TeamCfg<NT, BF16, V>;
+    using CF = TeamCfg<NT, PM, V>;
     const TeamSmem T(ctx->Lx, CF::STAGE, CF::TL, CF::PT);
-    auto kern = k_sampler_team<NT, BF16, V>;
+    auto kern = k_sampler_team<NT, PM, V>;
     if (T.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
@@ -644,13 +774,13 @@ int launch_mfma(tn_ctx *ctx, int B, int8_t *S, bool eval, double *logq, double *
 }
 
 // blocks counts 16-proposal units, a whole number of teams per instance
-template <int NT, bool BF16, int V>
+template <int NT, int PM, int V>
 int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks, int maxLx,
                       uint64_t seed, uint64_t step0, int eval) {
-    using CF = TeamCfg<NT, BF16, V>;
+    using CF = TeamCfg<NT, PM, V>;
     static_assert(8 % (TW * CF::SETS) == 0, "an instance's eight-unit blocks must split into teams");
     const TeamSmem T(maxLx, CF::STAGE, CF::TL, CF::PT);
-    auto kern = k_sampler_team_multi<NT, BF16, V>;
+    auto kern = k_sampler_team_multi<NT, PM, V>;
     if (T.total > 65536)
         TN_HIP(ctx, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         T.total));
@@ -661,37 +791,46 @@ int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks,
     return TN_OK;
 }
 
-// D <= 32 classes: the three launch variants; D 33-64: variant 0 only
-template <int NT, bool BF16>
+// D <= 32 classes: the three launch variants; D 33-64: variant 0 only; FP64
+// (D <= 32): variant 0 only
+template <int NT, int PM>
 int launch_variant(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq, double *energy,
                    float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
-    if constexpr (NT <= 2) {
-        if (V == 1) return launch_mfma<NT, BF16, 1>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-        if (V == 2) return launch_mfma<NT, BF16, 2>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    if constexpr (NT <= 2 && PM != PM_F64) {
+        if (V == 1) return launch_mfma<NT, PM, 1>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+        if (V == 2) return launch_mfma<NT, PM, 2>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
     }
-    return launch_mfma<NT, BF16, 0>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    return launch_mfma<NT, PM, 0>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
 }
 
-template <int NT, bool BF16>
+template <int NT, int PM>
 int launch_variant_multi(tn_ctx *ctx, int V, const tn_samp_desc *descs, int n, int blocks, int maxLx,
                          uint64_t seed, uint64_t step0, int eval) {
     if constexpr (NT <= 2) {
-        if (V == 1) return launch_mfma_multi<NT, BF16, 1>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
-        if (V == 2) return launch_mfma_multi<NT, BF16, 2>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
+        if (V == 1) return launch_mfma_multi<NT, PM, 1>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
+        if (V == 2) return launch_mfma_multi<NT, PM, 2>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
     }
-    return launch_mfma_multi<NT, BF16, 0>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
+    return launch_mfma_multi<NT, PM, 0>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
 }
 
-template <bool BF16>
+template <int PM>
 int dispatch_nt(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq, double *energy,
                 float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     switch (ctx->Dp / 16) {
-    case 1: return launch_variant<1, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    case 2: return launch_variant<2, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    case 3: return launch_variant<3, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    case 4: return launch_variant<4, BF16>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
-    default: return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
+    case 1: return launch_variant<1, PM>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 2: return launch_variant<2, PM>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    case 3:
+        if constexpr (PM != PM_F64)
+            return launch_variant<3, PM>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+        break;
+    case 4:
+        if constexpr (PM != PM_F64)
+            return launch_variant<4, PM>(ctx, V, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+        break;
+    default: break;
     }
+    return tn_fail(ctx, TN_EINVAL, PM == PM_F64 ? "the batched fp64 sampler supports D <= 32"
+                                                : "bond dimension above 64");
 }
 
 }  // namespace
@@ -703,16 +842,19 @@ int tn_run_mfma(tn_ctx *ctx, int batch, uint64_t seed, uint64_t step0, int per_s
     if (ctx->Lx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     if (per_step <= 0) return tn_fail(ctx, TN_EINVAL, "proposals per step must be positive");
     if (variant < 0) variant = tn_ctx_variant(ctx);
-    if (variant >= tn_team_variants(ctx->Dp / 16)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
+    const int pm = ctx->prec == TN_BF16 ? PM_BF16 : (ctx->prec == TN_FP64_MFMA ? PM_F64 : PM_F32);
+    if (variant >= team_variants(ctx->Dp / 16, pm)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     int rc;
     if (!scr) {
         if ((rc = tn_ensure(ctx, &ctx->gscr, &ctx->gscr_cap, tn_mfma_scratch_bytes(ctx, batch)))) return rc;
         scr = ctx->gscr;
     }
     float *g = (float *)scr;
-    if (ctx->prec == TN_BF16)
-        return dispatch_nt<true>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
-    return dispatch_nt<false>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    if (pm == PM_BF16)
+        return dispatch_nt<PM_BF16>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    if (pm == PM_F64)
+        return dispatch_nt<PM_F64>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
+    return dispatch_nt<PM_F32>(ctx, variant, batch, spins, eval, logq, energy, g, seed, step0, per_step, first_id);
 }
 
 int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp_desc *descs, int n,
@@ -722,13 +864,13 @@ int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp
     if (NT < 1 || NT > 4) return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
     if (variant < 0 || variant >= tn_team_variants(NT)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     switch (NT * 2 + (bf16 ? 1 : 0)) {
-    case 2: return launch_variant_multi<1, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    case 3: return launch_variant_multi<1, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    case 4: return launch_variant_multi<2, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    case 5: return launch_variant_multi<2, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    case 6: return launch_variant_multi<3, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    case 7: return launch_variant_multi<3, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    case 8: return launch_variant_multi<4, false>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
-    default: return launch_variant_multi<4, true>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 2: return launch_variant_multi<1, PM_F32>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 3: return launch_variant_multi<1, PM_BF16>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 4: return launch_variant_multi<2, PM_F32>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 5: return launch_variant_multi<2, PM_BF16>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 6: return launch_variant_multi<3, PM_F32>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 7: return launch_variant_multi<3, PM_BF16>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    case 8: return launch_variant_multi<4, PM_F32>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
+    default: return launch_variant_multi<4, PM_BF16>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
     }
 }

@@ -10,8 +10,8 @@ import os
 
 import torch
 
-FP64, FP32, BF16 = 0, 1, 2
-PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+FP64, FP32, BF16, FP64_MFMA = 0, 1, 2, 3
+PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp64_mfma": FP64_MFMA}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtnmh.so")
