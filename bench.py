@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted MH proposals/s, 2D Ising L=64 D=32: batched FP32 vs plain FP64"
 UNIT = "accepted proposals/s"
 PEAK_FP32_MFMA = 157.3e12
+PEAK_FP64_MFMA = 78.6e12
 PEAK_HBM = 8.0e12
 
 
@@ -256,6 +257,8 @@ def run_antiferro256(steps, warmup, n_eval=2048):
     out = {}
     for name, prec in (("bf16", BF16), ("fp32", FP32)):
         s.set_precision(prec)
+        variant, _ = s.autotune(C, max_steps=1)   # launch variant of a one-step launch, timed
+        log(f"[bench] antiferro256 {name}: tuned variant {variant}")
         state = s.init_state(C)
         prop = s.empty_batch(C)
         for t in range(warmup):
@@ -277,7 +280,7 @@ def run_antiferro256(steps, warmup, n_eval=2048):
         st = s.stats()
         kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         out[name] = dict(value=st["accepted"] / wall, ms_per_step=wall * 1e3 / steps,
-                         sampler_ms=kms, acceptance=st["accepted"] / max(st["proposed"], 1),
+                         sampler_ms=kms, acceptance=st["accepted"] / max(st["proposed"], 1), variant=variant,
                          spins=prop[0][:n_eval].clone(), logq=prop[1][:n_eval].clone())
         log(f"[bench] antiferro256 {name}: {wall * 1e3 / steps:.1f} ms/step, sampler {kms:.1f} ms, "
             f"acceptance {out[name]['acceptance']:.4f}")
@@ -301,7 +304,7 @@ def run_antiferro256(steps, warmup, n_eval=2048):
             "roofline": {"bound": "mfma", "achieved": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 1e12,
                          "peak": 2500.0, "unit": "TFLOP/s",
                          "frac": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
-                         "traffic": None, "kernel": "k_sampler_team<4,true,0>",
+                         "traffic": None, "kernel": f"k_sampler_team<4,1,{out['bf16']['variant']}>",
                          "flop_count": "12 D^2 L^2 per proposal",
                          "frac_6D2L2_minimum": flops / 2 / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
                          "kernel_ms": out["bf16"]["sampler_ms"]},
@@ -494,12 +497,12 @@ def run_fitbuild(sweeps=(0, 1, 2), n_inst=64):
 
 
 def run_precision(steps=40, chains=1024, temps=(1.0, 0.5, 0.3, 0.212)):
-    """Acceptance of the three sampler precisions on one environment build:
-    the +-J 32x32 instance of the hybrid workload, D = 16, from all-up, at
-    several temperatures (FP64 plain path, FP32 and BF16 batched path; the
-    operands of each are derived from the same FP64 environments)."""
+    """Acceptance of the sampler precisions on one environment build: the
+    +-J 32x32 instance of the hybrid workload, D = 16, from all-up, at several
+    temperatures (FP64 plain path; FP64, FP32 and BF16 operands on the batched
+    path; the operands of each are derived from the same FP64 environments)."""
     import torch
-    from paper_2104_13264_amd import Sampler, FP64, FP32, BF16
+    from paper_2104_13264_amd import Sampler, FP64, FP32, BF16, FP64_MFMA
     from workloads import ea_pm, SEED
     out = {"workload": "precision_ea32_D16", "chains": chains, "steps": steps, "rows": []}
     for T in temps:
@@ -507,7 +510,7 @@ def run_precision(steps=40, chains=1024, temps=(1.0, 0.5, 0.3, 0.212)):
         s = Sampler()
         s.build_env(inst.Jh, inst.Jv, None, inst.beta, 16, FP64)
         row = {"T": T, "degenerate_cuts": s.stats()["degenerate_cuts"]}
-        for name, prec in (("fp64", FP64), ("fp32", FP32), ("bf16", BF16)):
+        for name, prec in (("fp64", FP64), ("fp64_mfma", FP64_MFMA), ("fp32", FP32), ("bf16", BF16)):
             s.set_precision(prec)
             state = s.init_state(chains)
             s.stats(reset=True)
@@ -518,7 +521,8 @@ def run_precision(steps=40, chains=1024, temps=(1.0, 0.5, 0.3, 0.212)):
         torch.cuda.synchronize()
         s.close()
         out["rows"].append(row)
-        log(f"[bench] precision T={T}: acceptance fp64 {row['fp64']:.5f}, fp32 {row['fp32']:.5f}, "
+        log(f"[bench] precision T={T}: acceptance fp64 {row['fp64']:.5f}, fp64_mfma {row['fp64_mfma']:.5f}, "
+            f"fp32 {row['fp32']:.5f}, "
             f"bf16 {row['bf16']:.5f} (degenerate cuts {row['degenerate_cuts']})")
     return out
 
@@ -760,6 +764,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
+    ap.add_argument("--no-batched-fp64", action="store_true",
+                    help="skip the batched fp64 path (fp64 operands on the matrix cores)")
     ap.add_argument("--tune-steps", type=int, default=32,
                     help="largest MH-step count per sampler launch the autotuner tries "
                          "(0: no tuning, variant 0 and the built-in count)")
@@ -840,6 +846,15 @@ def main():
         log(f"[bench] fp64 plain: {res64['wall']*1e3/args.steps:.3f} ms/step, "
             f"acc {res64['accepted']}/{res64['proposed']}")
 
+    res64m = None
+    if not args.no_batched_fp64:
+        res64m, _ = run_gpu(3, inst, args.steps, args.warmup, env_state,
+                            ahead=m, tune_steps=0 if args.ahead is not None else min(args.tune_steps, args.steps),
+                            tune_cache=args.tune_cache)
+        log(f"[bench] fp64 batched: {res64m['wall']*1e3/args.steps:.3f} ms/step, "
+            f"sampler launches of {res64m['launch_sizes']} steps: {sum(res64m['kern_ms']):.3f} ms in total, "
+            f"acc {res64m['accepted']}/{res64m['proposed']}")
+
     value = res32["accepted"] / res32["wall"]
     ms_per_step = res32["wall"] * 1e3 / args.steps
     # Roofline of the sampler launches timed above (HIP events on the stream
@@ -879,7 +894,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic,
-                     "kernel": f"k_sampler_team<2,false,{res32['variant']}>",
+                     "kernel": f"k_sampler_team<2,0,{res32['variant']}>",
                      "flop_count": "12 D^2 L^2 per proposal",
                      "frac_6D2L2_minimum": flops["6D2L2"] / kern_s / PEAK_FP32_MFMA,
                      "frac_8D2L2_executed": flops["8D2L2"] / kern_s / PEAK_FP32_MFMA,
@@ -902,6 +917,23 @@ def main():
                              "tau_int_mean_energy": tau_int(res64["E"]),
                              "sampler_ms": res64["sampler_ms"]}
         out["speedup_vs_plain_fp64"] = value / v64 if v64 > 0 else None
+    if res64m is not None:
+        v64m = res64m["accepted"] / res64m["wall"]
+        props64 = C * sum(res64m["launch_sizes"])
+        kern64 = sum(res64m["kern_ms"]) * 1e-3
+        out["batched_fp64"] = {"value": v64m, "unit": UNIT,
+                               "ms_per_step": res64m["wall"] * 1e3 / args.steps,
+                               "acceptance": res64m["accepted"] / max(res64m["proposed"], 1),
+                               "tau_int_mean_energy": tau_int(res64m["E"]),
+                               "kernel": f"k_sampler_team<{-(-D // 16)},2,{res64m['variant']}>",
+                               "launch_steps": res64m["launch_sizes"],
+                               "kernel_ms_total": sum(res64m["kern_ms"]),
+                               "frac_fp64_mfma_12D2L2": 12.0 * D * D * L * L * props64 / kern64 / PEAK_FP64_MFMA,
+                               "frac_fp64_mfma_8D2L2_executed":
+                                   8.0 * D * D * L * L * props64 / kern64 / PEAK_FP64_MFMA,
+                               "near_threshold_draws": res64m["near"]}
+        if res64 is not None:
+            out["batched_fp64"]["speedup_vs_plain_fp64"] = v64m / (res64["accepted"] / res64["wall"])
     if not args.no_cpu:
         cb = run_cpu_oracle(inst)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

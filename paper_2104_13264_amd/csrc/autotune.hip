@@ -156,7 +156,7 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
     if (cache_path) cache = read_cache(cache_path);
     Choice best;
     auto hit = cache.find(key);
-    const int nvar = (plain || ctx->prec == TN_FP64_MFMA) ? 1 : tn_team_variants(NT);
+    const int nvar = (plain || ctx->prec == TN_FP64_MFMA) ? 1 : tn_team_variants(NT, ctx->prec == TN_BF16);
     if (hit != cache.end() && hit->second.variant >= 0 && hit->second.variant < nvar &&
         hit->second.proposals >= 1) {
         best = hit->second;
@@ -290,7 +290,7 @@ int tn_autotune_multi(tn_ctx *ctx, const char *cache_path, int *variants_out) {
             key += (first ? "" : ",") + kv.first + "*" + std::to_string(kv.second);
             first = false;
         }
-        const int nvar = tn_team_variants(g.NT);
+        const int nvar = tn_team_variants(g.NT, g.bf16);
         Choice best;
         auto hit = cache.find(key);
         if (hit != cache.end() && hit->second.variant >= 0 && hit->second.variant < nvar) {

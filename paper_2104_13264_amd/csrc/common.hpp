@@ -295,9 +295,11 @@ inline size_t tn_mfma_scratch_bytes(const tn_ctx *ctx, int batch) {
 inline size_t tn_fp64_scratch_bytes(const tn_ctx *ctx, int batch) {
     return (size_t)batch * ctx->Lx * 2 * ctx->D * sizeof(double);
 }
-// Launch variants of the batched sampler for bond class NT = Dp / 16 (same
-// arithmetic, different launch shape; sampler_mfma.hip).
-constexpr int tn_team_variants(int NT) { return NT <= 2 ? 3 : 1; }
+// Launch variants of the batched sampler for bond class NT = Dp / 16 and its
+// operands (same arithmetic, different launch shape; sampler_mfma.hip): four
+// for D <= 32, two for BF16 D 33-64, one for FP32 D 33-64 (no recomputing
+// variant there: it would need every one of a lane's 512 registers).
+constexpr int tn_team_variants(int NT, bool bf16) { return NT <= 2 ? 4 : (bf16 ? 2 : 1); }
 // Whether tn_autotune's choice applies to the context's current instance
 // (same lattice, padded bond dimension and precision), and its variant (0 if
 // there is none).

@@ -506,7 +506,7 @@ int tn_periodic_step(tn_ctx *ctx, uint64_t seed, uint64_t step, int cut_row, int
         // team of a chain has no proposal and leaves at once
         const int NT = ((P->D + 15) / 16);
         const bool bf = P->prec == TN_BF16;
-        const int v = tn_team_variants(NT) > 1 ? 1 : 0;
+        const int v = NT <= 2 ? 1 : 0;
         if ((rc = tn_run_mfma_multi(ctx, NT, bf, v, P->sd_eval, T, 8 * T, P->Lxo, 0, 0, true))) return rc;
         if ((rc = tn_run_mfma_multi(ctx, NT, bf, v, P->sd_samp, T, 8 * T, P->Lxo, seed, step, false))) return rc;
     }

@@ -37,6 +37,8 @@
 // kernel must round alike, and the compiler's choice of which product of an
 // expression to fuse may differ between instantiations.  Fused operations are
 // written out (fmaf).
+#include <type_traits>
+
 #pragma clang fp contract(off)
 
 namespace {
@@ -59,7 +61,7 @@ struct Arith<PM_F64> {
     using E = double;
     using V4 = doublex4;
 };
-constexpr int team_variants(int NT, int PM) { return PM == PM_F64 ? 1 : tn_team_variants(NT); }
+constexpr int team_variants(int NT, int PM) { return PM == PM_F64 ? 1 : tn_team_variants(NT, PM == PM_BF16); }
 
 #define TN_MAX_LX 256
 
@@ -259,11 +261,19 @@ constexpr int TW = 4;   // waves per team
 // Per bond class and launch variant V: TL LDS stages (columns in flight);
 // SETS: 16-proposal sets per wave; WPE: waves per SIMD the registers allow;
 // ABUF: operand register sets (two: read one column ahead; one: read just in
-// time).  The variants differ in launch shape only, never in the arithmetic
-// of a proposal; for D <= 32 an autotuner picks one (tn_autotune):
+// time).  The variants differ in launch shape and in where the y tiles live,
+// never in the arithmetic of a proposal; an autotuner picks one
+// (tn_autotune):
 //   V = 0  two sets per wave, two waves per SIMD (D 33-64: one set, one wave)
 //   V = 1  one set per wave, two waves per SIMD (half the LDS per team)
 //   V = 2  one set per wave, three waves per SIMD
+//   last   (V = 3 for D <= 32, V = 1 for BF16 D 33-64) recomputing: no y tiles
+//          in scratch.  The sweep keeps only a checkpoint of its state per
+//          block of BR columns; the draw, block by block, sweeps the block's
+//          columns again from its checkpoint with the y tiles in registers
+//          and then draws them.  It moves 1/BR of the tile traffic for half
+//          again the products (the per-proposal y tiles of a row outgrow
+//          every cache, and BF16 products are cheap next to HBM bytes).
 template <int NT, int PM, int V>
 struct TeamCfg {
     static_assert(V >= 0 && V < team_variants(NT, PM), "no such variant for this bond class");
@@ -272,9 +282,13 @@ struct TeamCfg {
     static constexpr uint32_t LANE = STAGE % (TW * 64 * 16) == 0 ? 16 : 4;     // dwordx4 or dword fetches
     static constexpr int LOADS = (int)(STAGE / (TW * 64 * LANE));            // per wave per column
     static_assert(LOADS * TW * 64 * LANE == STAGE, "stage must split evenly");
-    static constexpr int TL = NT <= 2 ? 4 : 2;
+    static constexpr bool REC = (NT <= 2 && !F64 && V == 3) || (NT > 2 && BF16 && V == 1);
+    static constexpr int BR = !REC ? 1 : NT == 1 ? 8 : NT == 2 ? 4 : 2;   // columns per block (registers)
+    // D > 32: one team per CU holds the LDS; four BF16 stages fit beside the
+    // row tables up to Lx = 256 (about 122 KB), FP32 stages are twice as big
+    static constexpr int TL = (NT <= 2 || BF16) ? 4 : 2;
     static constexpr int SETS = (NT <= 2 && V == 0 && !F64) ? 2 : 1;
-    static constexpr int WPE = F64 ? (NT == 1 ? 2 : 1) : (NT <= 2 ? (V == 2 ? 3 : 2) : 1);
+    static constexpr int WPE = F64 ? (NT == 1 ? 2 : 1) : REC ? (NT <= 2 ? 2 : 1) : (NT <= 2 ? (V == 2 ? 3 : 2) : 1);
     static constexpr int ABUF = F64 ? (NT == 1 ? 2 : 1) : ((BF16 || NT <= 2) ? 2 : 1);
     static constexpr int PT = TW * 16 * SETS;   // proposals per team
 };
@@ -396,6 +410,48 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                             uniform_u32((uint32_t)Lx * gstride));
     // this wave's share of a stage: LOADS chunks of 64 lanes x LANE bytes
     const uint32_t share = (uint32_t)w * CF::LOADS * 64 * CF::LANE;
+    // Checkpoints of the recomputing variant, in the set's scratch: block b's
+    // entry state, r_+ and r_- as the products read them (bf16 in BF16 mode)
+    // and the rescale exponent of each lane.
+    constexpr uint32_t CPV = CF::BF16 ? 8 : 16;              // bytes per lane of a 4-entry piece
+    constexpr uint32_t CPB = 2 * NT * 64 * CPV + 64 * 4;     // bytes per checkpoint
+    auto cp_save = [&](int b, const V4 (&v0)[NT], const V4 (&v1)[NT], int e) {
+        if constexpr (CF::REC) {
+            const uint32_t base = uniform_u32((uint32_t)b * CPB);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo) {
+                    const V4 &v = sp ? v1[mo] : v0[mo];
+                    const uint32_t off = (uint32_t)(((sp * NT + mo) * 64 + lane) * CPV);
+                    if constexpr (CF::BF16)
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(uintx2, bf16x4_rne(v)), grs[0], off, base, 0);
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, v), grs[0], off, base, 0);
+                }
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)e, grs[0], (uint32_t)(2 * NT * 64 * CPV + lane * 4), base, 0);
+        }
+    };
+    auto cp_load = [&](int b, V4 (&v0)[NT], V4 (&v1)[NT], int &e) {
+        if constexpr (CF::REC) {
+            const uint32_t base = uniform_u32((uint32_t)b * CPB);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int mo = 0; mo < NT; ++mo) {
+                    V4 &v = sp ? v1[mo] : v0[mo];
+                    const uint32_t off = (uint32_t)(((sp * NT + mo) * 64 + lane) * CPV);
+                    if constexpr (CF::BF16) {
+                        const uintx2 h = __builtin_amdgcn_raw_buffer_load_b64(grs[0], off, base, 0);
+                        v = V4{__uint_as_float(h[0] << 16), __uint_as_float(h[0] & 0xffff0000u),
+                               __uint_as_float(h[1] << 16), __uint_as_float(h[1] & 0xffff0000u)};
+                    } else {
+                        v = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(grs[0], off, base, 0));
+                    }
+                }
+            e = (int)__builtin_amdgcn_raw_buffer_load_b32(grs[0], (uint32_t)(2 * NT * 64 * CPV + lane * 4), base, 0);
+        }
+    };
     // random words of the draw set's proposal, drawn as the row goes: one
     // Philox block per four sites, kept for the next sites
     const uint32_t jj = (uint32_t)(bd);
@@ -429,14 +485,32 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             }
         }
         const size_t rowb = (size_t)r * Lx;
+        // Operands of the sweep come in its order (from the far end of the
+        // row), those of the draw in the draw order.  The recomputing variant
+        // reads, per block of BR draw columns, the block's sweep columns and
+        // then its draw columns: stream position q of its draw role is
+        // column step o = q mod 2 BR of block q / 2 BR.
+        auto cols = [&](int t) { return drawR ? Lx - 1 - t : t; };   // sweep step -> column
+        auto cold = [&](int t) { return drawR ? t : Lx - 1 - t; };   // draw step -> column
+        const char *Gsw = uniform_ptr((const char *)(drawR ? A.GR : A.GL) + rowb * AT::SITE_BYTES);
+        const char *Gdr = uniform_ptr((const char *)(drawR ? A.GL : A.GR) + rowb * AT::SITE_BYTES);
         for (int role = 0; role < 2; ++role) {
             const bool sweep = role == 0;
-            const bool rightward = sweep ? !drawR : drawR;
-            const char *Gb = uniform_ptr((const char *)(rightward ? A.GL : A.GR) + rowb * AT::SITE_BYTES);
-            auto colof = [&](int t) { return rightward ? t : Lx - 1 - t; };
-            auto issue = [&](int t) {   // stage t % TL <- column colof(min(t, Lx - 1))
-                const char *src = Gb + (size_t)colof(min(t, Lx - 1)) * AT::SITE_BYTES + share + lane * CF::LANE;
-                unsigned char *dst = ring + (t % TL) * CF::STAGE + share;
+            auto src_of = [&](int q) -> const char * {
+                if constexpr (CF::REC) {
+                    if (!sweep) {
+                        const int b = q / (2 * CF::BR), o = q - b * (2 * CF::BR);
+                        if (o < CF::BR)
+                            return Gsw + (size_t)cols(min(max(Lx - (b + 1) * CF::BR + o, 0), Lx - 1)) * AT::SITE_BYTES;
+                        return Gdr + (size_t)cold(min(b * CF::BR + o - CF::BR, Lx - 1)) * AT::SITE_BYTES;
+                    }
+                }
+                return sweep ? Gsw + (size_t)cols(min(q, Lx - 1)) * AT::SITE_BYTES
+                             : Gdr + (size_t)cold(min(q, Lx - 1)) * AT::SITE_BYTES;
+            };
+            auto issue = [&](int q) {   // stage q % TL <- the operands of stream position q
+                const char *src = src_of(q) + share + lane * CF::LANE;
+                unsigned char *dst = ring + (q % TL) * CF::STAGE + share;
 #pragma unroll
                 for (int j = 0; j < CF::LOADS; ++j)
                     lds_fetch<CF::LANE>(src + j * 64 * CF::LANE,
@@ -450,55 +524,95 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             AT a[CF::ABUF][2];   // [set of registers][spin]
             lds_tiles<NT, PM>(a[0][0], ring, lane);
             lds_tiles<NT, PM>(a[0][1], ring + CF::STAGE / 2, lane);
-            if (sweep) {
-                V4 v0[SE][NT], v1[SE][NT];   // r_+ and r_- of every set
+            // next stream position: own fetch has landed (at most N ops issued
+            // after it in flight), the team meets, the operands go to registers
+            auto ring_next = [&](int k, int q, auto nops) __attribute__((always_inline)) {
+                wait_vm<decltype(nops)::value>();
+                team_barrier();
+                const unsigned char *stg = ring + ((q + 1) % TL) * CF::STAGE;
+                lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
+                lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
+            };
+            // One sweep column for every set: y_s = G_c(s) r_s, rescaled, goes
+            // to keep(st, y); r_s' = sum_s W(s', s) v_c(s) y_s replaces r; the
+            // exponent of the next rescale.  mid() runs after the products are
+            // issued (the stage fetch).
+            auto sweep_col = [&](int k, int t, V4 (&v0)[SE][NT], V4 (&v1)[SE][NT], int (&e)[SE], auto &&mid,
+                                 auto &&keep) __attribute__((always_inline)) {
+                const int c = cols(t);
+                V4 acc[SE][2][NT];
 #pragma unroll
-                for (int st = 0; st < SE; ++st)
+                for (int st = 0; st < SE; ++st) mul_both<NT, PM>(a[k % CF::ABUF], v0[st], v1[st], acc[st]);
+                mid();
+#pragma unroll
+                for (int st = 0; st < SE; ++st) {
+                    const bool up_minus = r > 0 && prow[c][slot(st)] < 0;
+                    ET m[4];   // the mixing weights W(s', s) v_c(s), fp32 (or fp64 in FP64 mode)
+                    if constexpr (F64) {
+                        const doublex2 m01 = *(const doublex2 *)&vS[c][up_minus ? 1 : 0][0][0];
+                        const doublex2 m23 = *(const doublex2 *)&vS[c][up_minus ? 1 : 0][1][0];
+                        m[0] = m01[0];
+                        m[1] = m01[1];
+                        m[2] = m23[0];
+                        m[3] = m23[1];
+                    } else {
+                        const floatx4 mf = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) m[i] = mf[i];
+                    }
+                    if (t % RS == 0 && t > 0) {
+#pragma unroll
+                        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                            for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) acc[st][sp][mo][i] = ldexp(acc[st][sp][mo][i], -e[st]);
+                    }
+                    keep(st, c, acc[st]);
+#pragma unroll
+                    for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            v0[st][mo][i] = fma_e(m[1], acc[st][1][mo][i], m[0] * acc[st][0][mo][i]);
+                            v1[st][mo][i] = fma_e(m[3], acc[st][1][mo][i], m[2] * acc[st][0][mo][i]);
+                        }
+                    if (t % RS == RS - 1) {
+                        ET mx = 0;
+#pragma unroll
+                        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                            for (int mo = 0; mo < NT; ++mo)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) mx = fmax(mx, fabs(acc[st][sp][mo][i]));
+                        e[st] = pow2_exponent_f(rows4_max(mx));
+                    }
+                }
+            };
+            auto init_state = [&](V4 (&v0)[SE][NT], V4 (&v1)[SE][NT], int (&e)[SE]) {
+#pragma unroll
+                for (int st = 0; st < SE; ++st) {
 #pragma unroll
                     for (int mt = 0; mt < NT; ++mt) v0[st][mt] = v1[st][mt] = V4{0, 0, 0, 0};
-                if (grp == 0)
-#pragma unroll
-                    for (int st = 0; st < SE; ++st) v0[st][0][0] = v1[st][0][0] = 1;
+                    if (grp == 0) v0[st][0][0] = v1[st][0][0] = 1;
+                    e[st] = 0;
+                }
+            };
+            if (sweep) {
+                V4 v0[SE][NT], v1[SE][NT];   // r_+ and r_- of every set
                 int e[SE];
-#pragma unroll
-                for (int st = 0; st < SE; ++st) e[st] = 0;
-                auto stepP = [&](int k, int t) {
-                    const int c = colof(t);
-                    V4 acc[SE][2][NT];
-#pragma unroll
-                    for (int st = 0; st < SE; ++st) mul_both<NT, PM>(a[k % CF::ABUF], v0[st], v1[st], acc[st]);
-                    issue(t + TL - 1);
-#pragma unroll
-                    for (int st = 0; st < SE; ++st) {
-                        const bool up_minus = r > 0 && prow[c][slot(st)] < 0;
-                        ET m[4];   // the mixing weights W(s', s) v_c(s), fp32 (or fp64 in FP64 mode)
-                        if constexpr (F64) {
-                            const doublex2 m01 = *(const doublex2 *)&vS[c][up_minus ? 1 : 0][0][0];
-                            const doublex2 m23 = *(const doublex2 *)&vS[c][up_minus ? 1 : 0][1][0];
-                            m[0] = m01[0];
-                            m[1] = m01[1];
-                            m[2] = m23[0];
-                            m[3] = m23[1];
-                        } else {
-                            const floatx4 mf = *(const floatx4 *)&mixP[c][up_minus ? 1 : 0][0][0];
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) m[i] = mf[i];
-                        }
-                        if (t % RS == 0 && t > 0) {
-#pragma unroll
-                            for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-                                for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                                    for (int i = 0; i < 4; ++i) acc[st][sp][mo][i] = ldexp(acc[st][sp][mo][i], -e[st]);
-                        }
+                init_state(v0, v1, e);
+                // the y tiles go to scratch for the draw; the recomputing
+                // variant instead keeps the state entering each draw block's
+                // first sweep column (a checkpoint per BR columns)
+                auto store_y = [&](int st, int c, const V4 (&y)[2][NT]) {
+                    if constexpr (!CF::REC) {
 #pragma unroll
                         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
                             for (int mo = 0; mo < NT; ++mo) {
                                 if constexpr (F64) {
-                                    const doublex2 lo = {acc[st][sp][mo][0], acc[st][sp][mo][1]};
-                                    const doublex2 hi = {acc[st][sp][mo][2], acc[st][sp][mo][3]};
+                                    const doublex2 lo = {y[sp][mo][0], y[sp][mo][1]};
+                                    const doublex2 hi = {y[sp][mo][2], y[sp][mo][3]};
                                     const uint32_t off = (uint32_t)(((sp * NT + mo) * 64 + lane) * 32);
                                     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, lo), grs[st], off,
                                                                            uniform_u32((uint32_t)c * gstride), 0);
@@ -506,38 +620,23 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                                                                            uniform_u32((uint32_t)c * gstride), 0);
                                 } else {
                                     __builtin_amdgcn_raw_buffer_store_b128(
-                                        __builtin_bit_cast(uintx4, acc[st][sp][mo]), grs[st],
+                                        __builtin_bit_cast(uintx4, y[sp][mo]), grs[st],
                                         (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
                                 }
                             }
-#pragma unroll
-                        for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                v0[st][mo][i] = fma_e(m[1], acc[st][1][mo][i], m[0] * acc[st][0][mo][i]);
-                                v1[st][mo][i] = fma_e(m[3], acc[st][1][mo][i], m[2] * acc[st][0][mo][i]);
-                            }
-                        if (t % RS == RS - 1) {
-                            ET mx = 0;
-#pragma unroll
-                            for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-                                for (int mo = 0; mo < NT; ++mo)
-#pragma unroll
-                                    for (int i = 0; i < 4; ++i) mx = fmax(mx, fabs(acc[st][sp][mo][i]));
-                            e[st] = pow2_exponent_f(rows4_max(mx));
-                        }
                     }
-                    // own fetch of column t + 1 has landed: at most the ops
-                    // issued after it are in flight (fewer in the first steps,
-                    // which follow the prologue's fetches)
-                    constexpr int ST = SE * 2 * NT * (F64 ? 2 : 1);   // stores per step
-                    if (t >= TL - 2) wait_vm<ST + (TL - 2) * (CF::LOADS + ST)>();
-                    else wait_vm<(TL - 2) * CF::LOADS + ST>();
-                    team_barrier();
-                    const unsigned char *stg = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
-                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
+                };
+                // own fetch of column t + 1 has landed: at most the ops issued
+                // after it are in flight (fewer in the first steps, which
+                // follow the prologue's fetches)
+                constexpr int ST = CF::REC ? 0 : SE * 2 * NT * (F64 ? 2 : 1);   // y stores per step
+                constexpr int NW = ST + (TL - 2) * (CF::LOADS + ST), NW0 = (TL - 2) * CF::LOADS + ST;
+                auto stepP = [&](int k, int t) {
+                    if constexpr (CF::REC)
+                        if (t > 0 && (Lx - t) % CF::BR == 0) cp_save((Lx - t) / CF::BR - 1, v0[0], v1[0], e[0]);
+                    sweep_col(k, t, v0, v1, e, [&] { issue(t + TL - 1); }, store_y);
+                    if (t >= TL - 2) ring_next(k, t, std::integral_constant<int, NW>{});
+                    else ring_next(k, t, std::integral_constant<int, NW0>{});
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
@@ -546,31 +645,6 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                 }
                 if (t < Lx) stepP(0, t);
             } else {
-                auto gload = [&](V4 (&gk)[SE][2][NT], int c) {
-#pragma unroll
-                    for (int st = 0; st < SE; ++st)
-#pragma unroll
-                        for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-                            for (int mo = 0; mo < NT; ++mo) {
-                                if constexpr (F64) {
-                                    const uint32_t off = (uint32_t)(((s2 * NT + mo) * 64 + lane) * 32);
-                                    const doublex2 lo = __builtin_bit_cast(
-                                        doublex2, __builtin_amdgcn_raw_buffer_load_b128(grs[st], off, uniform_u32((uint32_t)c * gstride), 0));
-                                    const doublex2 hi = __builtin_bit_cast(
-                                        doublex2, __builtin_amdgcn_raw_buffer_load_b128(grs[st], off + 16, uniform_u32((uint32_t)c * gstride), 0));
-                                    gk[st][s2][mo] = V4{lo[0], lo[1], hi[0], hi[1]};
-                                } else {
-                                    gk[st][s2][mo] = __builtin_bit_cast(
-                                        floatx4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                     grs[st], (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
-                                                     uniform_u32((uint32_t)c * gstride), 0));
-                                }
-                            }
-                };
-                V4 g[2][SE][2][NT];
-                gload(g[0], colof(0));
-                gload(g[1], colof(min(1, Lx - 1)));
                 V4 lam[SE][NT];
 #pragma unroll
                 for (int st = 0; st < SE; ++st)
@@ -582,8 +656,11 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                 int sprev = 0;
                 uint4 words = make_uint4(0u, 0u, 0u, 0u);
                 int wblk = -1;
-                auto stepS = [&](int k, int t) {
-                    const int c = colof(t);
+                // One draw column: w(s) = v hf <Lam, y_s>, the draw, and Lam
+                // G_c(s) of the drawn spin; mid() runs after the products and
+                // the inner products are issued (the stage fetch).
+                auto draw_col = [&](int k, int t, const V4 (&y)[SE][2][NT], auto &&mid) __attribute__((always_inline)) {
+                    const int c = cold(t);
                     const int8_t up = prow[c][pd];
                     const int8_t given = crow[c][pd];
                     const int i = r * Lx + c;
@@ -606,12 +683,11 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                         for (int mo = 0; mo < NT; ++mo)
 #pragma unroll
                             for (int ii = 0; ii < 4; ++ii) {
-                                d0[st] = fma_e(lam[st][mo][ii], g[k][st][0][mo][ii], d0[st]);
-                                d1[st] = fma_e(lam[st][mo][ii], g[k][st][1][mo][ii], d1[st]);
+                                d0[st] = fma_e(lam[st][mo][ii], y[st][0][mo][ii], d0[st]);
+                                d1[st] = fma_e(lam[st][mo][ii], y[st][1][mo][ii], d1[st]);
                             }
                     }
-                    issue(t + TL - 1);
-                    gload(g[k], colof(min(t + 2, Lx - 1)));
+                    mid();
 #pragma unroll
                     for (int st = 0; st < SE; ++st) rows4_sum2(d0[st], d1[st]);
                     const ET dd0 = (SE == 2 && ds) ? d0[SE - 1] : d0[0];
@@ -682,22 +758,104 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     for (int st = 0; st < SE; ++st)
 #pragma unroll
                         for (int mo = 0; mo < NT; ++mo) lam[st][mo] = sdset[st] > 0 ? acc[st][0][mo] : acc[st][1][mo];
+                };
+                if constexpr (!CF::REC) {
+                    auto gload = [&](V4 (&gk)[SE][2][NT], int c) {
+#pragma unroll
+                        for (int st = 0; st < SE; ++st)
+#pragma unroll
+                            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                                for (int mo = 0; mo < NT; ++mo) {
+                                    if constexpr (F64) {
+                                        const uint32_t off = (uint32_t)(((s2 * NT + mo) * 64 + lane) * 32);
+                                        const doublex2 lo = __builtin_bit_cast(
+                                            doublex2, __builtin_amdgcn_raw_buffer_load_b128(grs[st], off, uniform_u32((uint32_t)c * gstride), 0));
+                                        const doublex2 hi = __builtin_bit_cast(
+                                            doublex2, __builtin_amdgcn_raw_buffer_load_b128(grs[st], off + 16, uniform_u32((uint32_t)c * gstride), 0));
+                                        gk[st][s2][mo] = V4{lo[0], lo[1], hi[0], hi[1]};
+                                    } else {
+                                        gk[st][s2][mo] = __builtin_bit_cast(
+                                            floatx4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                         grs[st], (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
+                                                         uniform_u32((uint32_t)c * gstride), 0));
+                                    }
+                                }
+                    };
+                    V4 g[2][SE][2][NT];
+                    gload(g[0], cold(0));
+                    gload(g[1], cold(min(1, Lx - 1)));
                     // own fetch of column t + 1 has landed (ops issued after it:
                     // the y loads of its step and TL - 2 steps of fetches and y
                     // loads; more in the first steps)
                     constexpr int GL = SE * 2 * NT * (F64 ? 2 : 1);   // y loads per step
-                    wait_vm<GL + (TL - 2) * (CF::LOADS + GL)>();
-                    team_barrier();
-                    const unsigned char *stg = ring + ((t + 1) % TL) * CF::STAGE;
-                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
-                    lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][1], stg + CF::STAGE / 2, lane);
-                };
-                int t = 0;
-                for (; t + 2 <= Lx; t += 2) {
-                    stepS(0, t);
-                    stepS(1, t + 1);
+                    auto stepS = [&](int k, int t) {
+                        draw_col(k, t, g[k], [&] {
+                            issue(t + TL - 1);
+                            gload(g[k], cold(min(t + 2, Lx - 1)));
+                        });
+                        ring_next(k, t, std::integral_constant<int, GL + (TL - 2) * (CF::LOADS + GL)>{});
+                    };
+                    int t = 0;
+                    for (; t + 2 <= Lx; t += 2) {
+                        stepS(0, t);
+                        stepS(1, t + 1);
+                    }
+                    if (t < Lx) stepS(0, t);
+                } else {
+                    // Per block b of BR draw columns (the last one ragged at
+                    // the far end): the sweep of its columns again from its
+                    // checkpoint (the far block from the start vector), the
+                    // y tiles kept in registers, then its draw.  Only the
+                    // stage fetches are vector-memory operations of a step,
+                    // besides the checkpoint loads (counted as none: the
+                    // waits then err on the long side).
+                    constexpr int BR = CF::BR;
+                    constexpr int NW = (TL - 2) * CF::LOADS;
+                    const int nblk = (Lx + BR - 1) / BR;
+                    V4 cv0[SE][NT], cv1[SE][NT];   // the next block's checkpoint, loaded one block ahead
+                    int ce[SE];
+                    if (nblk > 1) cp_load(0, cv0[0], cv1[0], ce[0]);
+                    for (int b = 0; b < nblk; ++b) {
+                        V4 v0[SE][NT], v1[SE][NT];
+                        int e[SE];
+                        if (b == nblk - 1) {
+                            init_state(v0, v1, e);
+                        } else {
+#pragma unroll
+                            for (int mt = 0; mt < NT; ++mt) {
+                                v0[0][mt] = cv0[0][mt];
+                                v1[0][mt] = cv1[0][mt];
+                            }
+                            e[0] = ce[0];
+                            if (b + 1 < nblk - 1) cp_load(b + 1, cv0[0], cv1[0], ce[0]);
+                        }
+                        V4 yr[BR][SE][2][NT];
+                        const int q0 = 2 * BR * b;
+#pragma unroll
+                        for (int j = 0; j < BR; ++j) {
+                            const int t = Lx - (b + 1) * BR + j;   // sweep step of the block's column j
+                            if (t >= 0)
+                                sweep_col(j, t, v0, v1, e, [&] { issue(q0 + j + TL - 1); },
+                                          [&](int st, int, const V4 (&y)[2][NT]) {
+#pragma unroll
+                                              for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                                                  for (int mo = 0; mo < NT; ++mo) yr[j][st][sp][mo] = y[sp][mo];
+                                          });
+                            else
+                                issue(q0 + j + TL - 1);
+                            ring_next(j, q0 + j, std::integral_constant<int, NW>{});
+                        }
+#pragma unroll
+                        for (int i = 0; i < BR; ++i) {
+                            const int t = b * BR + i;   // draw step; its column's y is the block's sweep column BR - 1 - i
+                            if (t < Lx) draw_col(BR + i, t, yr[BR - 1 - i], [&] { issue(q0 + BR + i + TL - 1); });
+                            else issue(q0 + BR + i + TL - 1);
+                            ring_next(BR + i, q0 + BR + i, std::integral_constant<int, NW>{});
+                        }
+                    }
                 }
-                if (t < Lx) stepS(0, t);
             }
         }
         __syncthreads();   // the drawn row is complete in LDS
@@ -791,14 +949,17 @@ int launch_mfma_multi(tn_ctx *ctx, const tn_samp_desc *descs, int n, int blocks,
     return TN_OK;
 }
 
-// D <= 32 classes: the three launch variants; D 33-64: variant 0 only; FP64
-// (D <= 32): variant 0 only
+// D <= 32 classes: variants 0-3; BF16 D 33-64: variants 0 and 1; FP32 D 33-64
+// and FP64 (D <= 32): variant 0 only
 template <int NT, int PM>
 int launch_variant(tn_ctx *ctx, int V, int B, int8_t *S, bool eval, double *logq, double *energy,
                    float *g, uint64_t seed, uint64_t step0, int per_step, uint64_t first_id) {
     if constexpr (NT <= 2 && PM != PM_F64) {
         if (V == 1) return launch_mfma<NT, PM, 1>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
         if (V == 2) return launch_mfma<NT, PM, 2>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+        if (V == 3) return launch_mfma<NT, PM, 3>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
+    } else if constexpr (PM == PM_BF16) {
+        if (V == 1) return launch_mfma<NT, PM, 1>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
     }
     return launch_mfma<NT, PM, 0>(ctx, B, S, eval, logq, energy, g, seed, step0, per_step, first_id);
 }
@@ -809,6 +970,9 @@ int launch_variant_multi(tn_ctx *ctx, int V, const tn_samp_desc *descs, int n, i
     if constexpr (NT <= 2) {
         if (V == 1) return launch_mfma_multi<NT, PM, 1>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
         if (V == 2) return launch_mfma_multi<NT, PM, 2>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
+        if (V == 3) return launch_mfma_multi<NT, PM, 3>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
+    } else if constexpr (PM == PM_BF16) {
+        if (V == 1) return launch_mfma_multi<NT, PM, 1>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
     }
     return launch_mfma_multi<NT, PM, 0>(ctx, descs, n, blocks, maxLx, seed, step0, eval);
 }
@@ -862,7 +1026,7 @@ int tn_run_mfma_multi(tn_ctx *ctx, int NT, bool bf16, int variant, const tn_samp
     if (blocks == 0) return TN_OK;
     if (maxLx > TN_MAX_LX) return tn_fail(ctx, TN_EINVAL, "Lx above 256");
     if (NT < 1 || NT > 4) return tn_fail(ctx, TN_EINVAL, "bond dimension above 64");
-    if (variant < 0 || variant >= tn_team_variants(NT)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
+    if (variant < 0 || variant >= tn_team_variants(NT, bf16)) return tn_fail(ctx, TN_EINVAL, "no such sampler variant");
     switch (NT * 2 + (bf16 ? 1 : 0)) {
     case 2: return launch_variant_multi<1, PM_F32>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
     case 3: return launch_variant_multi<1, PM_BF16>(ctx, variant, descs, n, blocks, maxLx, seed, step0, eval ? 1 : 0);
