@@ -30,6 +30,7 @@ METRIC = "accepted MH proposals/s, 2D Ising L=64 D=32: batched FP32 vs plain FP6
 UNIT = "accepted proposals/s"
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
+PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
 
 
@@ -304,7 +305,8 @@ def run_antiferro256(steps, warmup, n_eval=2048):
             "roofline": {"bound": "mfma", "achieved": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 1e12,
                          "peak": 2500.0, "unit": "TFLOP/s",
                          "frac": flops / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
-                         "traffic": None, "kernel": f"k_sampler_team<4,1,{out['bf16']['variant']}>",
+                         "traffic": measured_traffic(C, out["bf16"]["variant"], "sampler_team_antiferro256_traffic.json"),
+                         "kernel": f"k_sampler_team<4,1,{out['bf16']['variant']}>",
                          "flop_count": "12 D^2 L^2 per proposal",
                          "frac_6D2L2_minimum": flops / 2 / (out["bf16"]["sampler_ms"] * 1e-3) / 2.5e15,
                          "kernel_ms": out["bf16"]["sampler_ms"]},
@@ -739,11 +741,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(proposals_per_launch, variant):
+def measured_traffic(proposals_per_launch, variant, name="sampler_team_ferro64_traffic.json"):
     """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
     they were taken on the current kernel source in this launch shape (the
     file holds one entry per measured shape)."""
-    p = os.path.join(ROOT, "profiles", "sampler_team_ferro64_traffic.json")
+    p = os.path.join(ROOT, "profiles", name)
     try:
         with open(p) as fh:
             d = json.load(fh)
@@ -766,6 +768,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain fp64 path")
     ap.add_argument("--no-batched-fp64", action="store_true",
                     help="skip the batched fp64 path (fp64 operands on the matrix cores)")
+    ap.add_argument("--no-batched-bf16", action="store_true",
+                    help="skip the batched bf16 path (bf16 operands, fp32 accumulation)")
     ap.add_argument("--tune-steps", type=int, default=32,
                     help="largest MH-step count per sampler launch the autotuner tries "
                          "(0: no tuning, variant 0 and the built-in count)")
@@ -792,6 +796,14 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler "
               "shards by chains, one process per GPU, and only one GPU is measured here", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        # a plain copy of known size for counter calibration: 256 MiB read + 256 MiB written
+        import torch
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     if args.workload != "ferro64":
         if args.workload == "ea_mix":
             out = run_ea_mix(args.steps, args.warmup)
@@ -823,13 +835,6 @@ def main():
 
     inst = ferro_64()
     L, D, C = inst.Lx, inst.D, inst.chains
-    if args.calib_copy:
-        # a plain copy of known size: 256 MiB read + 256 MiB written
-        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
     log(f"[bench] ferro 64x64 D={D} chains={C} steps={args.steps} warmup={args.warmup}")
 
     m = ahead_steps(C) if args.ahead is None else args.ahead
@@ -854,6 +859,15 @@ def main():
         log(f"[bench] fp64 batched: {res64m['wall']*1e3/args.steps:.3f} ms/step, "
             f"sampler launches of {res64m['launch_sizes']} steps: {sum(res64m['kern_ms']):.3f} ms in total, "
             f"acc {res64m['accepted']}/{res64m['proposed']}")
+
+    res16 = None
+    if not args.no_batched_bf16:
+        res16, _ = run_gpu(2, inst, args.steps, args.warmup, env_state,
+                           ahead=m, tune_steps=0 if args.ahead is not None else min(args.tune_steps, args.steps),
+                           tune_cache=args.tune_cache)
+        log(f"[bench] bf16 batched: {res16['wall']*1e3/args.steps:.3f} ms/step, variant {res16['variant']}, "
+            f"sampler launches of {res16['launch_sizes']} steps: {sum(res16['kern_ms']):.3f} ms in total, "
+            f"acc {res16['accepted']}/{res16['proposed']}")
 
     value = res32["accepted"] / res32["wall"]
     ms_per_step = res32["wall"] * 1e3 / args.steps
@@ -934,6 +948,18 @@ def main():
                                "near_threshold_draws": res64m["near"]}
         if res64 is not None:
             out["batched_fp64"]["speedup_vs_plain_fp64"] = v64m / (res64["accepted"] / res64["wall"])
+    if res16 is not None:
+        props16 = C * sum(res16["launch_sizes"])
+        kern16 = sum(res16["kern_ms"]) * 1e-3
+        out["batched_bf16"] = {"value": res16["accepted"] / res16["wall"], "unit": UNIT,
+                               "ms_per_step": res16["wall"] * 1e3 / args.steps,
+                               "acceptance": res16["accepted"] / max(res16["proposed"], 1),
+                               "tau_int_mean_energy": tau_int(res16["E"]),
+                               "kernel": f"k_sampler_team<{-(-D // 16)},1,{res16['variant']}>",
+                               "launch_steps": res16["launch_sizes"],
+                               "kernel_ms_total": sum(res16["kern_ms"]),
+                               "frac_bf16_mfma_12D2L2": 12.0 * D * D * L * L * props16 / kern16 / PEAK_BF16_MFMA,
+                               "near_threshold_draws": res16["near"]}
     if not args.no_cpu:
         cb = run_cpu_oracle(inst)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
