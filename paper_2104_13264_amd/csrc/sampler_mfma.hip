@@ -1,7 +1,7 @@
 // Batched sampler on the matrix cores: the same sequential draw and the same
 // conditionals as the plain path (Sec. 2 Eqs. bayes, pi-approx; App. A
 // Eq. proba-ratio-apx), with the per-column products run as 16x16 MFMA tiles
-// (FP32 16x16x4, BF16 16x16x16 with FP32 accumulation, or FP64 16x16x4).
+// (FP32 16x16x4, BF16 16x16x32 with FP32 accumulation, or FP64 16x16x4).
 // The precision mode PM selects the operands and the vector arithmetic: FP32
 // and BF16 vectors are fp32, FP64 vectors are fp64.
 //
@@ -82,6 +82,12 @@ typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int uintx2 __attribute__((ext_vector_type(2)));
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// Two four-entry bf16 pieces as the eight-entry operand of the 16x16x32 product.
+__device__ __forceinline__ bf16x8 cat8(const shortx4 lo, const shortx4 hi) {
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 // Four floats to bf16 with round-to-nearest-even (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ shortx4 bf16x4_rne(const floatx4 v) {
     const floatx2 lo = {v[0], v[1]}, hi = {v[2], v[3]};
@@ -109,7 +115,7 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_a
 
 // A operands of one spin's product for one column, per lane: every 16-row
 // output block mo = 0..NT-1 with the 4 NT k-chunks of the fp32 or fp64
-// 16x16x4 product or the NT chunks of the bf16 16x16x16 product.  Tile layout
+// 16x16x4 product or the NT chunks of the bf16 products (16 k each).  Tile layout
 // per site: [s][mo][mt][64 lanes][4 chunks] (fp32: 16 bytes per lane; bf16: 8;
 // fp64: 32).
 template <int NT, int PM>
@@ -214,12 +220,24 @@ __device__ __forceinline__ void mul_both(const ATiles<NT, PM> (&a)[2], const typ
             b0[mt] = bf16x4_rne(x0[mt]);
             b1[mt] = bf16x4_rne(x1[mt]);
         }
+        // k-chunks in pairs on the 16x16x32 product: a lane's eight operand
+        // entries are its four of chunk 2p followed by its four of chunk
+        // 2p + 1, on both sides, so every A entry meets the B entry of the
+        // same vector index; an odd last chunk on the 16x16x16 product
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt)
+        for (int p = 0; p + 1 < NT; p += 2)
 #pragma unroll
             for (int mo = 0; mo < NT; ++mo) {
-                acc[0][mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0].a[mo][mt], b0[mt], acc[0][mo], 0, 0, 0);
-                acc[1][mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1].a[mo][mt], b1[mt], acc[1][mo], 0, 0, 0);
+                acc[0][mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8(a[0].a[mo][p], a[0].a[mo][p + 1]),
+                                                                     cat8(b0[p], b0[p + 1]), acc[0][mo], 0, 0, 0);
+                acc[1][mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8(a[1].a[mo][p], a[1].a[mo][p + 1]),
+                                                                     cat8(b1[p], b1[p + 1]), acc[1][mo], 0, 0, 0);
+            }
+        if constexpr (NT & 1)
+#pragma unroll
+            for (int mo = 0; mo < NT; ++mo) {
+                acc[0][mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0].a[mo][NT - 1], b0[NT - 1], acc[0][mo], 0, 0, 0);
+                acc[1][mo] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1].a[mo][NT - 1], b1[NT - 1], acc[1][mo], 0, 0, 0);
             }
     } else {
 #pragma unroll
