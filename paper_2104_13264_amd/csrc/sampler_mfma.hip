@@ -303,8 +303,8 @@ struct TeamCfg {
     static constexpr bool REC = (NT <= 2 && !F64 && V == 3) || (NT > 2 && BF16 && V == 1);
     static constexpr int BR = !REC ? 1 : NT == 1 ? 8 : NT == 2 ? 4 : 2;   // columns per block (registers)
     // D > 32: one team per CU holds the LDS; four BF16 stages fit beside the
-    // row tables up to Lx = 256 (about 122 KB), FP32 stages are twice as big
-    static constexpr int TL = (NT <= 2 || BF16) ? 4 : 2;
+    // row tables up to Lx = 256 (about 122 KB), three FP32 ones (about 154 KB)
+    static constexpr int TL = (NT <= 2 || BF16) ? 4 : 3;
     static constexpr int SETS = (NT <= 2 && V == 0 && !F64) ? 2 : 1;
     static constexpr int WPE = F64 ? (NT == 1 ? 2 : 1) : REC ? (NT <= 2 ? 2 : 1) : (NT <= 2 ? (V == 2 ? 3 : 2) : 1);
     static constexpr int ABUF = F64 ? (NT == 1 ? 2 : 1) : ((BF16 || NT <= 2) ? 2 : 1);
@@ -644,11 +644,14 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                             }
                     }
                 };
-                // own fetch of column t + 1 has landed: at most the ops issued
-                // after it are in flight (fewer in the first steps, which
-                // follow the prologue's fetches)
-                constexpr int ST = CF::REC ? 0 : SE * 2 * NT * (F64 ? 2 : 1);   // y stores per step
-                constexpr int NW = ST + (TL - 2) * (CF::LOADS + ST), NW0 = (TL - 2) * CF::LOADS + ST;
+                // own fetch of column t + 1 has landed: at most the loads
+                // issued after it are in flight (fewer in the first steps,
+                // which follow the prologue's fetches).  The y stores are not
+                // counted: the counter may drop for a store before it drops
+                // for an earlier load, so a count that includes stores could
+                // be reached with the fetch still in flight; stores still
+                // pending only make the wait longer.
+                constexpr int NW = (TL - 2) * CF::LOADS, NW0 = NW;
                 auto stepP = [&](int k, int t) {
                     if constexpr (CF::REC)
                         if (t > 0 && (Lx - t) % CF::BR == 0) cp_save((Lx - t) / CF::BR - 1, v0[0], v1[0], e[0]);
