@@ -543,9 +543,10 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
             lds_tiles<NT, PM>(a[0][0], ring, lane);
             lds_tiles<NT, PM>(a[0][1], ring + CF::STAGE / 2, lane);
             // next stream position: own fetch has landed (at most N ops issued
-            // after it in flight), the team meets, the operands go to registers
+            // after it in flight; N < 0: the step has waited already), the
+            // team meets, the operands go to registers
             auto ring_next = [&](int k, int q, auto nops) __attribute__((always_inline)) {
-                wait_vm<decltype(nops)::value>();
+                if constexpr (decltype(nops)::value >= 0) wait_vm<decltype(nops)::value>();
                 team_barrier();
                 const unsigned char *stg = ring + ((q + 1) % TL) * CF::STAGE;
                 lds_tiles<NT, PM>(a[(k ^ 1) % CF::ABUF][0], stg, lane);
@@ -644,20 +645,22 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                             }
                     }
                 };
-                // own fetch of column t + 1 has landed: at most the loads
-                // issued after it are in flight (fewer in the first steps,
-                // which follow the prologue's fetches).  The y stores are not
-                // counted: the counter may drop for a store before it drops
-                // for an earlier load, so a count that includes stores could
-                // be reached with the fetch still in flight; stores still
-                // pending only make the wait longer.
-                constexpr int NW = (TL - 2) * CF::LOADS, NW0 = NW;
+                // Own fetch of column t + 1 has landed once at most the loads
+                // issued after it are in flight: (TL - 2) stage fetches (fewer
+                // in the first steps, which follow the prologue's).  The y
+                // stores are not counted, since the counter may drop for a
+                // store before it drops for an earlier load; so the wait sits
+                // right after this step's fetch, before this step's stores,
+                // where pending stores are those of earlier steps.
+                constexpr int NW = (TL - 2) * CF::LOADS;
                 auto stepP = [&](int k, int t) {
                     if constexpr (CF::REC)
                         if (t > 0 && (Lx - t) % CF::BR == 0) cp_save((Lx - t) / CF::BR - 1, v0[0], v1[0], e[0]);
-                    sweep_col(k, t, v0, v1, e, [&] { issue(t + TL - 1); }, store_y);
-                    if (t >= TL - 2) ring_next(k, t, std::integral_constant<int, NW>{});
-                    else ring_next(k, t, std::integral_constant<int, NW0>{});
+                    sweep_col(k, t, v0, v1, e, [&] {
+                        issue(t + TL - 1);
+                        wait_vm<NW>();
+                    }, store_y);
+                    ring_next(k, t, std::integral_constant<int, -1>{});
                 };
                 int t = 0;
                 for (; t + 2 <= Lx; t += 2) {
