@@ -646,8 +646,9 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     }
                 };
                 // Own fetch of column t + 1 has landed once at most the loads
-                // issued after it are in flight: (TL - 2) stage fetches (fewer
-                // in the first steps, which follow the prologue's).  The y
+                // issued after it are in flight: (TL - 2) stage fetches, in
+                // every step (positions past the row's end fetch its last
+                // column again).  The y
                 // stores are not counted, since the counter may drop for a
                 // store before it drops for an earlier load; so the wait sits
                 // right after this step's fetch, before this step's stores,
