@@ -160,6 +160,7 @@ def multi_items():
         (random_instance(9, 7, 0.5, 24, seed=93), 24, 16),
         (ea_pm(12, 2.0, 32, seed=94), 32, 70),
         (ferro(8, 0.4407, 40), 40, 9),
+        (random_instance(5, 8, 0.6, 64, seed=95), 64, 130),
     ]
 
 
