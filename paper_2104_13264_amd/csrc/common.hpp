@@ -386,7 +386,9 @@ int tn_grad_device(tn_ctx *ctx, const tn_ctx *upper, double *dJh, double *dJv, d
 // ---------------------------------------------------------------------------
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
-// 4x32 S-box with two 32x32->64 multiplies, Weyl-incremented key.
+// 4x32 S-box with two 32x32->64 multiplies, Weyl-incremented key.  Each
+// product is taken whole (one v_mad_u64_u32 instead of separate low and high
+// multiplies, both quarter rate).
 __device__ __forceinline__ uint4 tn_philox(uint4 ctr, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int rnd = 0; rnd < 10; ++rnd) {
@@ -394,10 +396,10 @@ __device__ __forceinline__ uint4 tn_philox(uint4 ctr, uint32_t k0, uint32_t k1) 
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * ctr.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, ctr.x);
-        const uint32_t lo1 = 0xCD9E8D57u * ctr.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, ctr.z);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * ctr.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * ctr.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         ctr = make_uint4(hi1 ^ ctr.y ^ k0, lo1, hi0 ^ ctr.w ^ k1, lo0);
     }
     return ctr;

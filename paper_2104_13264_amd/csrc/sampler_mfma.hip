@@ -679,6 +679,12 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
 #pragma unroll
                     for (int st = 0; st < SE; ++st) lam[st][0][0] = 1;
                 int sprev = 0;
+                // Random words: Philox block b serves sites 4b .. 4b + 3 of the
+                // row-major site index.  The GW lane groups of a draw set each
+                // hold one of GW consecutive blocks (one Philox pass per 4 GW
+                // sites instead of one per 4 sites in every group), and the
+                // word of a site comes from the group holding its block.
+                constexpr int GW = 4 / SE;   // lane groups per draw set
                 uint4 words = make_uint4(0u, 0u, 0u, 0u);
                 int wblk = -1;
                 // One draw column: w(s) = v hf <Lam, y_s>, the draw, and Lam
@@ -689,11 +695,13 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                     const int8_t up = prow[c][pd];
                     const int8_t given = crow[c][pd];
                     const int i = r * Lx + c;
-                    if (!eval && (i >> 2) != wblk) {   // uniform: every lane's sites move together
-                        wblk = i >> 2;
-                        words = tn_philox(make_uint4((uint32_t)wblk, (uint32_t)wid, wst, (inst << 2) | 0u), k0, k1);
+                    if (!eval && (i >> 2) / GW != wblk) {   // uniform: every lane's sites move together
+                        wblk = (i >> 2) / GW;
+                        words = tn_philox(make_uint4((uint32_t)(wblk * GW + grp % GW), (uint32_t)wid, wst, (inst << 2) | 0u),
+                                          k0, k1);
                     }
-                    const uint32_t word = tn_word(words, i & 3);
+                    const int wsrc = n + 16 * ((grp / GW) * GW + (i >> 2) % GW);   // lane holding block i >> 2
+                    const uint32_t word = (uint32_t)__builtin_amdgcn_ds_bpermute(wsrc * 4, (int)tn_word(words, i & 3));
                     const bool up_minus = r > 0 && up < 0;
                     const double2 vv = *(const double2 *)&vS[c][up_minus ? 1 : 0][sprev][0];
                     V4 acc[SE][2][NT];
