@@ -315,6 +315,38 @@ def run_antiferro256(steps, warmup, n_eval=2048):
             "env_build_s": build_s, "logZ": lz}
 
 
+def run_peaks(reps=3):
+    """Attained peak of each unit the kernels use (tn_peak_probe): the best of
+    `reps` timed launches per probe, beside the published figure; for the
+    arithmetic probes also the clock that the rate implies (rate over the
+    chip's flops per cycle: 256 CUs x 4 SIMDs x the unit's flops per SIMD and
+    cycle)."""
+    from paper_2104_13264_amd import peak_probe
+    probes = [  # kind, amount, published peak, unit scale, flops per cycle of the chip
+        ("mfma_f32", 60000, PEAK_FP32_MFMA, 1e12, 1024 * 64),
+        ("mfma_bf16", 120000, PEAK_BF16_MFMA, 1e12, 1024 * 1024),
+        ("mfma_f64", 30000, PEAK_FP64_MFMA, 1e12, 1024 * 32),
+        ("fma_f64", 200000, PEAK_FP64_MFMA, 1e12, 1024 * 32),
+        ("hbm_read", 16 << 30, PEAK_HBM, 1e9, None),
+        ("hbm_copy", 8 << 30, PEAK_HBM, 1e9, None),
+    ]
+    out = {}
+    for kind, amount, peak, scale, per_cycle in probes:
+        best = 0.0
+        for _ in range(reps):
+            sec, work = peak_probe(kind, amount)
+            best = max(best, work / sec)
+        e = {"attained": best / scale, "published": peak / scale,
+             "unit": "TFLOP/s" if per_cycle else "GB/s", "frac": best / peak}
+        if per_cycle:
+            e["implied_clock_ghz"] = best / per_cycle / 1e9
+        log(f"[bench] peak {kind}: {e['attained']:.1f} {e['unit']} of {e['published']:.1f} "
+            f"({100 * e['frac']:.1f}%)" + (f", implied clock {e['implied_clock_ghz']:.2f} GHz" if per_cycle else ""))
+        out[kind] = e
+    return {"metric": "attained peak per unit (one unit alone, best of %d launches)" % reps, "probes": out,
+            "n_gpus": 1, "data": "synthetic"}
+
+
 def run_potts(steps, warmup, L=32, d=3, D=16, chains=8192):
     """q-state Potts ferromagnet (general local dimension d, App. A), L x L
     open boundaries, J = 1, h = 0, at the critical coupling of the square
@@ -789,7 +821,7 @@ def main():
                     help="cut schedule of the periodic workload")
     ap.add_argument("--workload", default="ferro64",
                     choices=["ferro64", "ea_mix", "antiferro256", "frustrated128", "hybrid", "delta",
-                             "periodic", "precision", "fitbuild", "potts"],
+                             "periodic", "precision", "fitbuild", "potts", "peaks"],
                     help="ferro64 is the headline line; the others report the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -823,6 +855,8 @@ def main():
             out = run_precision()
         elif args.workload == "potts":
             out = run_potts(args.steps, args.warmup)
+        elif args.workload == "peaks":
+            out = run_peaks()
         elif args.workload == "periodic":
             out = run_periodic(steps=args.periodic_steps, cuts=args.periodic_cuts, sweeps=args.periodic_sweeps)
         else:

@@ -554,6 +554,38 @@ typedef struct {
  * Synchronises the stream. */
 int tn_stats(tn_ctx *ctx, tn_stats_t *out, int reset);
 
+/* Peak probes.  The rooflines of the kernels are quoted against MI355X's
+ * published peaks; these probes measure what the chip attains for each unit
+ * the kernels use, each unit alone at its highest rate, so that a kernel can
+ * also be read against what is reachable (the attained rate includes the
+ * clock the chip holds under that load).  Not part of the sampling path.
+ *   TN_PEAK_MFMA_F32   v_mfma_f32_16x16x4_f32, eight independent chains per
+ *                      wave, four waves per SIMD; amount = iterations
+ *   TN_PEAK_MFMA_BF16  v_mfma_f32_16x16x32_bf16, as above
+ *   TN_PEAK_MFMA_F64   v_mfma_f64_16x16x4_f64, four chains per wave
+ *   TN_PEAK_FMA_F64    v_fma_f64 on every lane, sixteen chains; amount =
+ *                      iterations
+ *   TN_PEAK_HBM_READ   stream read of a buffer of `amount` bytes (16-byte
+ *                      loads, eight in flight per lane)
+ *   TN_PEAK_HBM_COPY   copy between two buffers of `amount` bytes each
+ * One untimed launch, then one launch timed with HIP events on the null
+ * stream of the current device.  Out (host): *seconds of the timed launch,
+ * *work its flops (compute probes) or bytes moved, read plus written (memory
+ * probes).  The buffers are allocated and freed by the call.  Errors:
+ * TN_EINVAL for an unknown kind, amount < 1, compute amount above 2^30,
+ * memory amount not a multiple of 16 or above 64 GiB, or NULL outputs;
+ * TN_ENOMEM if the buffers cannot be allocated; TN_EHIP for a failed launch.
+ * Synchronises the device. */
+enum tn_peak_kind {
+    TN_PEAK_MFMA_F32 = 0,
+    TN_PEAK_MFMA_BF16 = 1,
+    TN_PEAK_MFMA_F64 = 2,
+    TN_PEAK_FMA_F64 = 3,
+    TN_PEAK_HBM_READ = 4,
+    TN_PEAK_HBM_COPY = 5
+};
+int tn_peak_probe(int kind, long long amount, double *seconds, double *work);
+
 #ifdef __cplusplus
 }
 #endif

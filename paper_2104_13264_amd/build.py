@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtnmh.so")
 SOURCES = ["api.hip", "autotune.hip", "env_build.hip", "operands.hip", "sampler_fp64.hip",
            "sampler_mfma.hip", "mh.hip", "grad.hip", "metropolis.hip", "stats.hip",
-           "periodic.hip", "potts.hip"]
+           "periodic.hip", "potts.hip", "peaks.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # never emit packed fp32 arithmetic

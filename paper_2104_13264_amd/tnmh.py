@@ -95,6 +95,7 @@ def lib():
         "tn_periodic_energy": (i, [vp, vp, vp]),
         "tn_periodic_sweeps": (i, [vp, i, u64, u64, vp, vp]),
         "tn_periodic_link_overlap": (i, [vp, i, vp, vp, vp]),
+        "tn_peak_probe": (i, [i, ctypes.c_longlong, ctypes.POINTER(d), ctypes.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -114,7 +115,23 @@ def exported_symbols():
             "tn_autotune", "tn_autotune_multi", "tn_metropolis_sweeps", "tn_link_overlap",
             "tn_periodic_setup", "tn_periodic_step", "tn_periodic_energy", "tn_periodic_link_overlap",
             "tn_set_compression", "tn_periodic_sweeps", "tn_sample_noalloc", "tn_logz_frozen",
-            "tn_potts_build_env"]
+            "tn_potts_build_env", "tn_peak_probe"]
+
+
+PEAK_KINDS = {"mfma_f32": 0, "mfma_bf16": 1, "mfma_f64": 2, "fma_f64": 3, "hbm_read": 4, "hbm_copy": 5}
+
+
+def peak_probe(kind, amount):
+    """tn_peak_probe on the current device: (seconds, work) of one timed
+    launch of the probe `kind` (a key of PEAK_KINDS); amount is iterations
+    for the compute probes, buffer bytes for the memory ones."""
+    if not torch.cuda.is_available():
+        raise TNError("no GPU: the probes run HIP kernels")
+    sec, work = ctypes.c_double(), ctypes.c_double()
+    rc = lib().tn_peak_probe(PEAK_KINDS[kind], int(amount), ctypes.byref(sec), ctypes.byref(work))
+    if rc != 0:
+        raise TNError(f"tn_peak_probe({kind}, {amount}) failed with code {rc}")
+    return sec.value, work.value
 
 
 def _ptr(t):
