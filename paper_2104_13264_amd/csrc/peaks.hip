@@ -73,6 +73,13 @@ __global__ void __launch_bounds__(BLOCK) k_peak_mfma_bf16(int iters, float *out)
         for (int k = 0; k < CHAINS; ++k) {
             asm volatile("v_mfma_f32_16x16x32_bf16 %0, %1, %2, %0" : "+a"(acc[k]) : "v"(a), "v"(b));
         }
+    // the compiler does not see the MFMAs above: give their results the wait
+    // states a vector read of an MFMA result needs, then name the accumulators
+    // in asm that follows (volatile asm keeps its order), so that no read of
+    // them moves above the wait
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7");
+#pragma unroll
+    for (int k = 0; k < CHAINS; ++k) asm volatile("" : "+a"(acc[k]));
     float s = 0.f;
 #pragma unroll
     for (int k = 0; k < CHAINS; ++k) s += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
@@ -93,6 +100,9 @@ __global__ void __launch_bounds__(BLOCK) k_peak_mfma_f64(int iters, float *out) 
         for (int k = 0; k < CHAINS64; ++k) {
             asm volatile("v_mfma_f64_16x16x4_f64 %0, %1, %2, %0" : "+v"(acc[k]) : "v"(a), "v"(b));
         }
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7");   // as in the BF16 probe
+#pragma unroll
+    for (int k = 0; k < CHAINS64; ++k) asm volatile("" : "+v"(acc[k]));
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < CHAINS64; ++k) s += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
