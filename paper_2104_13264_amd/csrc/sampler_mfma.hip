@@ -98,6 +98,17 @@ __device__ __forceinline__ shortx4 bf16x4_rne(const floatx4 v) {
 // Buffer resource over [base, base + bytes): loads and stores take a 32-bit
 // per-lane offset and a wave-uniform column offset; accesses outside the
 // range read 0 / are dropped.
+// Cache policy of the FP32 y tiles (FP32 and BF16 operands): non-temporal.
+// Each byte is written once and read once, a whole row sweep later, and the
+// tiles in flight (hundreds of MB) outgrow L2 and the MALL; marked
+// non-temporal they do not displace the environment operands, which every
+// team of the launch re-reads from L2 (variant 2 at the 64x64, D = 32
+// headline: 38.1 -> 35.6 ms per 20-step launch).  The recomputing variant's
+// checkpoints (tens of MB per launch) and the FP64 tiles keep the default
+// policy: marked non-temporal they ran slower (the BF16 recomputing launch
+// 20.3 -> 22.8 ms).
+constexpr int SCR_POLICY = 2;   // the nt bit of the buffer instructions' cache policy
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
@@ -640,7 +651,8 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                                 } else {
                                     __builtin_amdgcn_raw_buffer_store_b128(
                                         __builtin_bit_cast(uintx4, y[sp][mo]), grs[st],
-                                        (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride), 0);
+                                        (uint32_t)(((sp * NT + mo) * 64 + lane) * 16), uniform_u32((uint32_t)c * gstride),
+                                        SCR_POLICY);
                                 }
                             }
                     }
@@ -811,7 +823,7 @@ __device__ __forceinline__ void team_body(const tn_samp_desc &A, const int unit0
                                         gk[st][s2][mo] = __builtin_bit_cast(
                                             floatx4, __builtin_amdgcn_raw_buffer_load_b128(
                                                          grs[st], (uint32_t)(((s2 * NT + mo) * 64 + lane) * 16),
-                                                         uniform_u32((uint32_t)c * gstride), 0));
+                                                         uniform_u32((uint32_t)c * gstride), SCR_POLICY));
                                     }
                                 }
                     };
