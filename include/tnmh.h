@@ -315,7 +315,10 @@ int tn_build_env_multi(tn_ctx *ctx, int n, const tn_instance *inst, int prec, do
  * n host pointers each, entry i pointing to instance i's device state
  * (spins int8 [chains_i][Ly_i][Lx_i], logq and energy fp64 [chains_i],
  * accepted uint8 [chains_i]).  Chains are bitwise those tn_mh_step gives a
- * single-instance context with the same instance number. */
+ * single-instance context with the same instance number.  Errors: TN_EINVAL
+ * if an instance was switched to TN_FP64_MFMA (tn_set_precision on
+ * tn_multi_instance's context): batched steps take TN_FP64, TN_FP32 and
+ * TN_BF16 instances. */
 int tn_mh_step_multi(tn_ctx *ctx, uint64_t seed, uint64_t step, int8_t *const *state_spins,
                      double *const *state_logq, double *const *state_energy,
                      uint8_t *const *accepted);
@@ -443,7 +446,8 @@ int tn_autotune(tn_ctx *ctx, int chains, int max_steps, const char *cache_path, 
  * choices.  variants_out (host, int [8], may be NULL): entry
  * 4 * bf16 + NT - 1 gets the variant of group (bf16, NT = D rounded up to 16,
  * divided by 16), -1 where there is no such group.  TN_ESTATE before
- * tn_build_env_multi. */
+ * tn_build_env_multi; TN_EINVAL for a TN_FP64_MFMA instance, as in
+ * tn_mh_step_multi. */
 int tn_autotune_multi(tn_ctx *ctx, const char *cache_path, int *variants_out);
 
 /* ---- Periodic boundaries by frozen lines ---------------------------------

@@ -75,6 +75,13 @@ int tn_multi_prepare(tn_ctx *ctx) {
     for (size_t i = 0; i < ctx->kids.size(); ++i) {
         tn_ctx *k = ctx->kids[i];
         const int C = ctx->kid_chains[i];
+        // an instance switched to FP64 operands on the matrix cores
+        // (tn_set_precision) has no batched sampler group: refuse it rather
+        // than run a group's kernel on its operand layout
+        if (k->prec == TN_FP64_MFMA)
+            return tn_fail(ctx, TN_EINVAL, "instance " + std::to_string(i) +
+                                               " has TN_FP64_MFMA operands: batched steps take TN_FP64, "
+                                               "TN_FP32 or TN_BF16");
         const size_t nsite = (size_t)k->Lx * k->Ly;
         const size_t spin_bytes = (((size_t)C * nsite + 255) / 256) * 256;
         const size_t need = spin_bytes + 2 * (size_t)C * sizeof(double);

@@ -45,7 +45,9 @@ std::string arch_name(int device) {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
-const char *prec_name(int prec) { return prec == TN_FP64 ? "fp64" : prec == TN_FP32 ? "fp32" : "bf16"; }
+const char *prec_name(int prec) {
+    return prec == TN_FP64 ? "fp64" : prec == TN_FP32 ? "fp32" : prec == TN_BF16 ? "bf16" : "fp64mfma";
+}
 
 std::map<std::string, Choice> read_cache(const char *path) {
     std::map<std::string, Choice> m;

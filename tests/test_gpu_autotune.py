@@ -207,3 +207,19 @@ def test_multi_variants_step_bitwise_alike(prec, tmp_path):
         for a, b in zip(r, runs[0]):
             for k in a:
                 np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_cache_keys_distinguish_bf16_and_fp64_mfma(tmp_path):
+    # the same lattice, D and chain count tuned in BF16 and in FP64 on the
+    # matrix cores land under two keys of one cache file
+    from paper_2104_13264_amd import Sampler, FP64_MFMA
+    inst = random_instance(6, 7, 0.6, 16, seed=96)
+    path = tmp_path / "keys.json"
+    for prec in (BF16, FP64_MFMA):
+        s = Sampler()
+        s.build_env(inst.Jh, inst.Jv, inst.h, inst.beta, 16, prec)
+        s.autotune(32, max_steps=2, cache=str(path))
+        s.close()
+    keys = list(json.loads(path.read_text()))
+    assert len(keys) == 2
+    assert any("|bf16|" in k for k in keys) and any("|fp64mfma|" in k for k in keys)

@@ -195,3 +195,25 @@ def test_graph_capture_refuses_calls_other_than_mh_steps():
     for k in ("spins", "logq", "energy", "accepted"):
         assert torch.equal(a[k], b[k])
     s.close()
+
+
+def test_multi_step_refuses_fp64_mfma_instance():
+    # An instance switched to FP64 operands on the matrix cores has no batched
+    # sampler group: the step and its tuner refuse it instead of running a
+    # group's kernel on its operand layout; switched back, the step works.
+    from paper_2104_13264_amd import Sampler, TNError, FP64_MFMA
+    items = [random_instance(5, 6, 0.6, 8, seed=68), random_instance(6, 5, 0.7, 8, seed=69)]
+    s = Sampler()
+    s.build_env_multi([dict(Jh=i.Jh, Jv=i.Jv, h=i.h, beta=i.beta, D=8, chains=16) for i in items], FP32)
+    subs = [s.instance(k) for k in range(len(items))]
+    st = [sub.init_state(16) for sub in subs]
+    subs[1].set_precision(FP64_MFMA)
+    with pytest.raises(TNError):
+        s.mh_step_multi(st, 3, 0)
+    with pytest.raises(TNError):
+        s.autotune_multi()
+    subs[1].set_precision(FP32)
+    s.mh_step_multi(st, 3, 0)
+    torch.cuda.synchronize()
+    assert all(bool(torch.isfinite(x["logq"]).all()) for x in st)
+    s.close()
