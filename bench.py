@@ -807,6 +807,9 @@ def main():
                          "(0: no tuning, variant 0 and the built-in count)")
     ap.add_argument("--tune-cache", default=None,
                     help="the autotuner's JSON file of earlier choices (default: time afresh)")
+    ap.add_argument("--force-variant", type=int, default=None,
+                    help="batched FP32 leg: use this launch variant with launches of all the timed steps "
+                         "(through a tuning-cache entry; for counter runs of other launch shapes)")
     ap.add_argument("--ahead", type=int, default=None,
                     help="MH steps per sampler launch (default: enough for two four-wave teams per CU)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -872,9 +875,22 @@ def main():
     log(f"[bench] ferro 64x64 D={D} chains={C} steps={args.steps} warmup={args.warmup}")
 
     m = ahead_steps(C) if args.ahead is None else args.ahead
+    tune_cache = args.tune_cache
+    if args.force_variant is not None:
+        # a cache entry the tuner takes as found: the variant, and launches of
+        # all the timed steps
+        import tempfile
+        import torch
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        steps = min(args.tune_steps, args.steps)
+        key = f"{arch}|{L}x{inst.Ly}|D{D}|fp32|chains{C}|steps{steps}"
+        tune_cache = os.path.join(tempfile.mkdtemp(), "forced.json")
+        with open(tune_cache, "w") as fh:
+            fh.write("{\n  " + json.dumps(key) + ": " +
+                     json.dumps({"variant": args.force_variant, "proposals": steps * C, "ns_per_proposal": 0.0}) + "\n}\n")
     res32, env_state = run_gpu(1, inst, args.steps, args.warmup, ahead=m,
                                tune_steps=0 if args.ahead is not None else min(args.tune_steps, args.steps),
-                               tune_cache=args.tune_cache)
+                               tune_cache=tune_cache)
     m = res32["steps_per_launch"]
     log(f"[bench] fp32 batched: {res32['wall']*1e3/args.steps:.3f} ms/step, "
         f"sampler launches of {res32['launch_sizes']} steps: {sum(res32['kern_ms']):.3f} ms in total, "
