@@ -586,7 +586,17 @@ k_potts_rows(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         double y[PD];
 #pragma unroll
         for (int s = 0; s < PD; ++s) y[s] = 0.0;
-        if (rightward) {   // y_s = G_c(s) r_s
+        if (D == T) {
+            // full teams: G is zero outside Dl x Dr and so are the vector
+            // components past the bond, so a fixed T-term product adds exact
+            // zeros after the same terms in the same order; unrolled, its
+            // shuffles and loads issue together instead of one chain per term
+            const double *G0 = (rightward ? Gc : Gr) + (size_t)c * PD * DD;
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+#pragma unroll
+                for (int s = 0; s < PD; ++s) y[s] += G0[s * DD + k * D + j] * __shfl(rv[s], k, T);
+        } else if (rightward) {   // y_s = G_c(s) r_s
             const double *G0 = Gc + (size_t)c * PD * DD;
             for (int k = 0; k < Dr; ++k) {
 #pragma unroll
@@ -706,7 +716,11 @@ k_potts_rows(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         if (t > 0 && sprev == s) E -= Jh[(size_t)r * (Lx - 1) + (rightward ? c - 1 : c)];
         if (up && up[c] == s) E -= Jv[(size_t)(r - 1) * Lx + c];
         double nl = 0.0;
-        if (rightward) {   // Lam <- Lam G_c(s)
+        if (D == T) {      // as in the sweep: a fixed T-term product
+            const double *Gs = (rightward ? Gr : Gc) + ((size_t)c * PD + s) * DD;
+#pragma unroll
+            for (int a = 0; a < T; ++a) nl += __shfl(lam, a, T) * Gs[a * D + j];
+        } else if (rightward) {   // Lam <- Lam G_c(s)
             const double *Gs = Gr + ((size_t)c * PD + s) * DD;
             for (int a = 0; a < Dl; ++a) {
                 const double x = __shfl(lam, a, T);
