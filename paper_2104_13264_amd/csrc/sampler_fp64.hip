@@ -71,7 +71,19 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         const int c = rightward ? Lx - 1 - t : t;
         const int Dl = dm[c], Dr = dm[c + 1];
         double y0 = 0.0, y1 = 0.0;
-        if (rightward) {   // y_s = G_c(s) r_s: input right bond, output left bond
+        if (D == T) {
+            // full teams: G is zero outside Dl x Dr and so are the vector
+            // components past the bond, so a fixed T-term product adds exact
+            // zeros after the same terms in the same order; unrolled, its
+            // shuffles and loads issue together instead of one chain per term
+            const double *G0 = (rightward ? Gc : Gr) + (size_t)c * 2 * DD, *G1 = G0 + DD;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const double x0 = __shfl(r0, k, T), x1 = __shfl(r1, k, T);
+                y0 += G0[k * D + j] * x0;
+                y1 += G1[k * D + j] * x1;
+            }
+        } else if (rightward) {   // y_s = G_c(s) r_s: input right bond, output left bond
             const double *G0 = Gc + (size_t)c * 2 * DD, *G1 = G0 + DD;
             for (int k = 0; k < Dr; ++k) {
                 const double x0 = __shfl(r0, k, T), x1 = __shfl(r1, k, T);
@@ -168,7 +180,14 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         if (t > 0) E -= Jh[r * (Lx - 1) + (rightward ? c - 1 : c)] * (double)(sprev * s);
         if (up) E -= Jv[(r - 1) * Lx + c] * (double)(up[c] * s);
         double nl = 0.0;
-        if (rightward) {   // Lam <- Lam G_c(s): input left bond, output right bond
+        if (D == T) {      // as in the sweep: a fixed T-term product
+            const double *Gs = (rightward ? Gr : Gc) + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                const double x = __shfl(lam, a, T);
+                nl += x * Gs[a * D + j];
+            }
+        } else if (rightward) {   // Lam <- Lam G_c(s): input left bond, output right bond
             const double *Gs = Gr + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
             for (int a = 0; a < Dl; ++a) {
                 const double x = __shfl(lam, a, T);
