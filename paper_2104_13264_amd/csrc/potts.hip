@@ -569,24 +569,57 @@ k_potts_rows(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
     int8_t *row = S + ((size_t)b * Ly + r) * Lx;
     const bool rightward = (r & 1) == 0;
 
-    // field and bond to the fixed value above, per value
-    auto vweight = [&](int c, int s) {
+    // field and bond to the fixed value u above (u < 0: no row above), per value
+    auto vweight = [&](int c, int s, int u) {
         double v = F[(size_t)c * PD + s];
-        if (up && up[c] == s) v *= ekv[c];
+        if (u == s) v *= ekv[c];
         return v;
+    };
+    // Full teams with few operands per lane (PD T <= 48) pipeline their
+    // loads: the sweep reads a column's operands one column ahead, the draw
+    // every value's operands of its column before it draws.  A column's own
+    // loads come first, since loads complete in the order they are issued.
+    // (two columns of operands in registers at PD T = 48 leave two waves
+    // per SIMD, all that a launch of 8192 proposals fills; PD T = 64 would
+    // leave one)
+    constexpr bool PIPE = PD * T <= 48;
+    constexpr int PP = PIPE ? PD : 1, TP = PIPE ? T : 1;
+    const bool pipe = PIPE && D == T;
+    auto opload = [&](double (&g)[PP][TP], const double *G0) {
+#pragma unroll
+        for (int s = 0; s < PP; ++s)
+#pragma unroll
+            for (int k = 0; k < TP; ++k) g[s][k] = G0[s * DD + k * D + j];
     };
 
     // ---- environment sweep of the free columns, from the far end of the row
     double rv[PD];
 #pragma unroll
     for (int s = 0; s < PD; ++s) rv[s] = (j == 0) ? 1.0 : 0.0;
+    const double *Gsw = rightward ? Gc : Gr;   // the sweep's layout
+    double gv[PP][TP];                         // operands of the column (pipelined)
+    if (pipe) opload(gv, Gsw + (size_t)(rightward ? Lx - 1 : 0) * PD * DD);
     for (int t = 0; t < Lx; ++t) {
         const int c = rightward ? Lx - 1 - t : t;
         const int Dl = dm[c], Dr = dm[c + 1];
+        const int u = up ? up[c] : -1;
         double y[PD];
 #pragma unroll
         for (int s = 0; s < PD; ++s) y[s] = 0.0;
-        if (D == T) {
+        if (pipe) {
+            // the next column's operands (the last column's again at the end)
+            const int cn = t + 1 < Lx ? (rightward ? c - 1 : c + 1) : c;
+            double gn[PP][TP];
+            opload(gn, Gsw + (size_t)cn * PD * DD);
+#pragma unroll
+            for (int k = 0; k < TP; ++k)
+#pragma unroll
+                for (int s = 0; s < PP; ++s) y[s] += gv[s][k] * __shfl(rv[s], k, T);
+#pragma unroll
+            for (int s = 0; s < PP; ++s)
+#pragma unroll
+                for (int k = 0; k < TP; ++k) gv[s][k] = gn[s][k];
+        } else if (D == T) {
             // full teams: G is zero outside Dl x Dr and so are the vector
             // components past the bond, so a fixed T-term product adds exact
             // zeros after the same terms in the same order; unrolled, its
@@ -625,7 +658,7 @@ k_potts_rows(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
             double sum = 0.0, vy[PD];
 #pragma unroll
             for (int s = 0; s < PD; ++s) {
-                vy[s] = vweight(c, s) * y[s];
+                vy[s] = vweight(c, s, u) * y[s];
                 sum += vy[s];
             }
             double mx = 0.0;
@@ -650,12 +683,27 @@ k_potts_rows(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         const int c = rightward ? t : Lx - 1 - t;
         const int Dl = dm[c], Dr = dm[c + 1];
         const double eKp = t > 0 ? ekh[rightward ? c - 1 : c] : 1.0;   // bond to the previous draw
+        const int u = up ? up[c] : -1;
+        // the column's stored right environments, its energy terms and, when
+        // pipelined, every value's operands of the left product, in that order
+        double gy[PD];
+#pragma unroll
+        for (int s = 0; s < PD; ++s) gy[s] = j < D ? gs[((size_t)c * PD + s) * D + j] : 0.0;
+        double hv[PD];
+        if (h) {
+#pragma unroll
+            for (int q = 0; q < PD; ++q) hv[q] = h[((size_t)r * Lx + c) * PD + q];
+        }
+        const double jh = t > 0 ? Jh[(size_t)r * (Lx - 1) + (rightward ? c - 1 : c)] : 0.0;
+        const double jv = up ? Jv[(size_t)(r - 1) * Lx + c] : 0.0;
+        double gd[PP][TP];
+        if (pipe) opload(gd, (rightward ? Gr : Gc) + (size_t)c * PD * DD);
         double w[PD], cum[PD];
         int nclamp = 0;
 #pragma unroll
         for (int s = 0; s < PD; ++s) {
-            const double g = j < D ? gs[((size_t)c * PD + s) * D + j] : 0.0;
-            double v = vweight(c, s);
+            const double g = gy[s];
+            double v = vweight(c, s, u);
             if (t > 0 && sprev == s) v *= eKp;
             w[s] = v * team_sum<T>(lam * g);
             if (w[s] < 0.0) {
@@ -712,11 +760,26 @@ k_potts_rows(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
             if (q == s) ws = w[q];
         lq += log(ws / tot);
         // energy: field, bond to the previous neighbour, bond above
-        if (h) E -= h[((size_t)r * Lx + c) * PD + s];
-        if (t > 0 && sprev == s) E -= Jh[(size_t)r * (Lx - 1) + (rightward ? c - 1 : c)];
-        if (up && up[c] == s) E -= Jv[(size_t)(r - 1) * Lx + c];
+        if (h) {
+            double hs = hv[0];
+#pragma unroll
+            for (int q = 1; q < PD; ++q)
+                if (q == s) hs = hv[q];
+            E -= hs;
+        }
+        if (t > 0 && sprev == s) E -= jh;
+        if (u == s) E -= jv;
         double nl = 0.0;
-        if (D == T) {      // as in the sweep: a fixed T-term product
+        if (pipe) {        // the drawn value's operands, loaded before the draw
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                double ga = gd[0][a];
+#pragma unroll
+                for (int q = 1; q < PP; ++q)
+                    if (q == s) ga = gd[q][a];
+                nl += __shfl(lam, a, T) * ga;
+            }
+        } else if (D == T) {      // as in the sweep: a fixed T-term product
             const double *Gs = (rightward ? Gr : Gc) + ((size_t)c * PD + s) * DD;
 #pragma unroll
             for (int a = 0; a < T; ++a) nl += __shfl(lam, a, T) * Gs[a * D + j];
