@@ -64,12 +64,20 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
     int8_t *row = S + ((size_t)b * Ly + r) * Lx;
 
     const bool rightward = (r & 1) == 0;   // snake order: even rows left to right
+    // Full teams with T <= 32 load both spins' operands of a drawing column
+    // before the draw and multiply the drawn spin's after it, so that the
+    // draw does not wait for their loads (two columns of T doubles leave two
+    // waves per SIMD, all that a launch of 4096 proposals fills)
+    constexpr bool PIPE = T <= 32;
+    constexpr int TP = PIPE ? T : 1;
+    const bool pipe = PIPE && D == T;
 
     // ---- environment sweep of the free columns, from the far end of the row
     double r0 = (j == 0) ? 1.0 : 0.0, r1 = r0;
     for (int t = 0; t < Lx; ++t) {
         const int c = rightward ? Lx - 1 - t : t;
         const int Dl = dm[c], Dr = dm[c + 1];
+        const int su = up ? up[c] : 1;   // loaded ahead of the operands
         double y0 = 0.0, y1 = 0.0;
         if (D == T) {
             // full teams: G is zero outside Dl x Dr and so are the vector
@@ -110,7 +118,6 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
             const double *f = fr + c * 6;
             // bond towards the next column of the sweep
             const double *fb = fr + (rightward ? c : c + 1) * 6;
-            const int su = up ? up[c] : 1;
             const double v0 = f[0] * (su > 0 ? f[2] : f[3]);   // s = +1
             const double v1 = f[1] * (su > 0 ? f[3] : f[2]);   // s = -1
             const double n0 = fb[4] * v0 * y0 + fb[5] * v1 * y1;
@@ -141,6 +148,15 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         }
         const double g0 = j < D ? gs[(c * 2 + 0) * D + j] : 0.0;
         const double g1 = j < D ? gs[(c * 2 + 1) * D + j] : 0.0;
+        double gd0[TP], gd1[TP];   // both spins' operands of the left product
+        if (pipe) {
+            const double *G0 = (rightward ? Gr : Gc) + (size_t)c * 2 * DD;
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                gd0[a] = G0[a * D + j];
+                gd1[a] = G0[DD + a * D + j];
+            }
+        }
         double w0 = v0 * team_sum<T>(lam * g0);
         double w1 = v1 * team_sum<T>(lam * g1);
         if (w0 < 0.0) {
@@ -180,7 +196,13 @@ k_row_fp64(int r, int B, int Lx, int Ly, int D, const double *__restrict__ Jh,
         if (t > 0) E -= Jh[r * (Lx - 1) + (rightward ? c - 1 : c)] * (double)(sprev * s);
         if (up) E -= Jv[(r - 1) * Lx + c] * (double)(up[c] * s);
         double nl = 0.0;
-        if (D == T) {      // as in the sweep: a fixed T-term product
+        if (pipe) {        // the drawn spin's operands, loaded before the draw
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                const double x = __shfl(lam, a, T);
+                nl += x * (s > 0 ? gd0[a] : gd1[a]);
+            }
+        } else if (D == T) {      // as in the sweep: a fixed T-term product
             const double *Gs = (rightward ? Gr : Gc) + ((size_t)c * 2 + (s > 0 ? 0 : 1)) * DD;
 #pragma unroll
             for (int a = 0; a < T; ++a) {
