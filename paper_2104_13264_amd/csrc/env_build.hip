@@ -22,6 +22,24 @@ __global__ void k_fill_dims(int *dims, int n, int v) {
         dims[t] = v;
 }
 
+// use(t, load(t)) for t = threadIdx.x, threadIdx.x + blockDim.x, ... < n, in
+// that order, with the loads of SB consecutive iterations issued before any
+// of their uses.  A strided loop that stores what it loads cannot move its
+// next load ahead of the store (the two may alias), so it would wait out
+// every load in turn.
+template <int SB, class Load, class Use>
+__device__ __forceinline__ void batched_loop(int n, Load &&load, Use &&use) {
+    const int step = (int)blockDim.x;
+    for (int t0 = threadIdx.x; t0 < n; t0 += SB * step) {
+        double v[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) v[i] = t0 + i * step < n ? load(t0 + i * step) : 0.0;
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (t0 + i * step < n) use(t0 + i * step, v[i]);
+    }
+}
+
 // X_c = sum_d env_{k+1,c}[a,d,b] M_{k,c}[l,u,d,x],  M = sum_s of the site
 // tensor of App. A Eq. (tensor-general) with the field factor exp(beta h s);
 // every column of row k, by the whole workgroup.
@@ -56,15 +74,31 @@ __device__ void mpo_apply_row(const tn_env_desc &dsc, int k) {
         double *X = dsc.xbox + (size_t)c * 8 * D * D;
         const int m = Dl * lw, n = Dr * xw, ld = 2 * D;
         const double *E = dsc.env + ((size_t)(k + 1) * Lx + c) * 2 * D * D;
-        for (int t = threadIdx.x; t < m * 2 * n; t += blockDim.x) {
-            const int j = t % n, rest = t / n, u = rest & 1, i = rest >> 1;
-            const int a = i / lw, l = i % lw, b = j / xw, x = j % xw;
-            double acc = 0.0;
-            for (int d = 0; d < dw; ++d) {
-                const double e = triv ? 1.0 : E[a * 2 * D + d * D + b];
-                acc += e * M[l][u][d][x];
+        // the env entries of four outputs are loaded before any is stored (a
+        // store to X may alias a later load of E, so the loop would otherwise
+        // wait out each load in turn); the sums are those of the plain loop
+        constexpr int SB = 4;
+        const int nout = m * 2 * n, step = (int)blockDim.x;
+        for (int t0 = threadIdx.x; t0 < nout; t0 += SB * step) {
+            double ev[SB][2];
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+                const int t = t0 + q * step;
+                const int j = t % n, a = (t / n >> 1) / lw, b = j / xw;
+#pragma unroll
+                for (int d = 0; d < 2; ++d)
+                    ev[q][d] = (t >= nout || d >= dw) ? 0.0 : (triv ? 1.0 : E[a * 2 * D + d * D + b]);
             }
-            X[(i * 2 + u) * ld + j] = acc;
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+                const int t = t0 + q * step;
+                if (t >= nout) break;
+                const int j = t % n, rest = t / n, u = rest & 1, i = rest >> 1;
+                const int l = i % lw, x = j % xw;
+                double acc = 0.0;
+                for (int d = 0; d < dw; ++d) acc += ev[q][d] * M[l][u][d][x];
+                X[(i * 2 + u) * ld + j] = acc;
+            }
         }
         if (threadIdx.x == 0) {
             dsc.xdims[c] = m;
@@ -490,6 +524,7 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds, double 
     const int ld = 2 * D;
     const size_t box = (size_t)8 * D2;
     const double eps = 2.220446049250313e-16;
+    constexpr int QSB = QLDS ? 8 : 4;   // loads batched per staging loop (registers)
 
     for (int c = threadIdx.x; c < Lx; c += blockDim.x) {
         mX[c] = xdims[c];
@@ -506,12 +541,10 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds, double 
         const int m = 2 * mX[c], n = nX[c], n1 = nX[c + 1];
         const int lda = m | 1;   // odd leading dimension: lanes of a row on distinct banks
         double x2 = 0.0;
-        for (int t = threadIdx.x; t < m * n; t += blockDim.x) {
-            const int r = t / n, j = t % n;
-            const double v = X[r * ld + j];
-            QA[(size_t)j * lda + r] = v;
+        batched_loop<QSB>(m * n, [&](int t) { return X[(t / n) * ld + t % n]; }, [&](int t, double v) {
+            QA[(size_t)(t % n) * lda + t / n] = v;
             x2 += v * v;
-        }
+        });
         x2 = tn_block_sum(x2, red);   // ends with a barrier: QA is complete
         const double xn = sqrt(x2);
         const double xinv = xn > 0.0 ? 1.0 / xn : 1.0;
@@ -526,10 +559,10 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds, double 
         __syncthreads();
         // stage X_{c+1} [q][(u, j)] (n rows), then T = R X_{c+1} into its first kk rows
         const int w1 = 2 * n1;
-        for (int t = threadIdx.x; t < n * w1; t += blockDim.x) {
+        batched_loop<QSB>(n * w1, [&](int t) {
             const int q = t / w1, e = t % w1;
-            QB[t] = Xn[(q * 2 + e / n1) * ld + e % n1];
-        }
+            return Xn[(q * 2 + e / n1) * ld + e % n1];
+        }, [&](int t, double v) { QB[t] = v; });
         __syncthreads();
         for (int t = threadIdx.x; t < kk * w1; t += blockDim.x) {
             const int p = t / w1, e = t % w1;
@@ -579,13 +612,15 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds, double 
         const int lenp = (len + 15) & ~15;   // zero padded to 16-wide slices
         const int ldw = lenp | 1;            // odd: rows of W on distinct banks
         double f2 = 0.0;
-        for (int t = threadIdx.x; t < rows * lenp; t += blockDim.x) {
+        batched_loop<QSB>(rows * lenp, [&](int t) {
             const int i = t / lenp, e = t % lenp;
-            const double v = e < len ? X[(i * 2 + e / ncol) * ld + e % ncol] : 0.0;
+            return e < len ? X[(i * 2 + e / ncol) * ld + e % ncol] : 0.0;
+        }, [&](int t, double v) {
+            const int i = t / lenp, e = t % lenp;
             W[i * ldw + e] = v;
             Worig[i * ldw + e] = v;
             f2 += v * v;
-        }
+        });
         f2 = tn_block_sum(f2, red);
         const double zero2 = f2 * (len * eps) * (len * eps);
         const int sweeps = qw_jacobi<QLDS ? 4 : 8>(W, rows, len, ldw, zero2, nrm, &flag);   // len <= 2 D
@@ -628,8 +663,18 @@ __device__ void truncate_row(const tn_env_desc &dsc, int k, double *lds, double 
         const int m1 = 2 * mX[c - 1];
         for (int t = threadIdx.x; t < m1 * chi; t += blockDim.x) {
             const int r = t / chi, kq = t % chi;
+            // the same sum in the same order, QSB loads of X at a time
+            const double *xr = Xp + r * ld;
             double acc = 0.0;
-            for (int q = 0; q < rows; ++q) acc += Xp[r * ld + q] * Z[q * chi + kq];
+            int q = 0;
+            for (; q + QSB <= rows; q += QSB) {
+                double xv[QSB];
+#pragma unroll
+                for (int i = 0; i < QSB; ++i) xv[i] = xr[q + i];
+#pragma unroll
+                for (int i = 0; i < QSB; ++i) acc += xv[i] * Z[(q + i) * chi + kq];
+            }
+            for (; q < rows; ++q) acc += xr[q] * Z[q * chi + kq];
             Y[t] = acc;
         }
         for (int t = threadIdx.x; t < chi * len; t += blockDim.x) {
